@@ -1,0 +1,220 @@
+/*
+ * sbm.h -- C ABI of the MI355X (gfx950) matrix-free shifted-boundary (SBM) Poisson library.
+ *
+ * The library applies v = A u for the high-order SBM discretisation of -Laplace u = f in
+ * Omega, u = g on Gamma, posed on the surrogate domain made of the background cells that
+ * lie entirely inside Omega (Wichrowski, "Matrix-Free Evaluation of High-Order Shifted
+ * Boundary Finite Element Operators", Sec. 2 and Sec. 2.1, Eq. (1)):
+ *
+ *   a(u,v) = int grad u . grad v - int_{Gam~} (du/dn~) v - int_{Gam~} (dv/dn~) E u
+ *            + int_{Gam~} sigma E u v,
+ *
+ * where E u at a surrogate-face quadrature point x~ is the value of the face's own cell
+ * polynomial at the closest point x = x~ + d on the true boundary (Sec. 3.3, Alg. 3).
+ * For SBM_DG the Laplace term is replaced by its symmetric interior-penalty (SIPG) form
+ * (Sec. 2.1, last display; Sec. 3.2, Alg. 2).  Cells are tensor-product Q_p elements on
+ * Gauss-Lobatto-Legendre nodes with lexicographic local numbering (Sec. 3.1); cell
+ * integrals use (p+1)^d Gauss points, face integrals (p+1)^(d-1).
+ *
+ * Conventions common to every entry point:
+ *   - Return value: SBM_OK or an error code; sbm_last_error() then holds a message
+ *     (thread-local).  No C++ exception crosses this boundary.
+ *   - "device" pointers are HIP device allocations of the current device; "host"
+ *     pointers are ordinary CPU memory.  The caller owns every buffer it passes in.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).  Device work
+ *     is enqueued on it; calls marked "asynchronous" return before the work finishes.
+ *   - Vectors have n_dofs entries of the requested precision (double for SBM_F64,
+ *     float for SBM_F32), contiguous.
+ *   - Supported: dim 2 or 3, p = 1..8, isotropic cells (equal h in every direction).
+ */
+#ifndef SBM_H
+#define SBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbm_ctx *sbm_handle;
+
+typedef enum {
+  SBM_OK = 0,
+  SBM_EINVAL = 1,        /* invalid argument (bad pointer, size, aliasing, geometry) */
+  SBM_ENOMEM = 2,        /* device or host allocation failed */
+  SBM_EHIP = 3,          /* a HIP runtime call failed */
+  SBM_ENOCONV = 4,       /* solver stopped before reaching the tolerance */
+  SBM_EUNSUPPORTED = 5   /* degree, dimension or option outside the built set */
+} sbm_status;
+
+enum { SBM_CG = 0, SBM_DG = 1 };      /* continuous Q_p / SIPG discontinuous Q_p */
+enum { SBM_F64 = 0, SBM_F32 = 1 };    /* arithmetic and vector precision of an apply */
+
+/* Level-set kinds; the true domain is {phi < 0}. */
+enum {
+  SBM_LS_SPHERE = 0,       /* |x - centre| - radius (a disk in 2D) */
+  SBM_LS_ELLIPSOID = 1,    /* axis-aligned, semi_axes[k], centred at centre */
+  SBM_LS_TORUS = 2,        /* 3D only: axis z through centre, major radius R, minor r */
+  SBM_LS_SPHERE_UNION = 3, /* union of n_spheres balls (centres n x 3 row-major, radii) */
+  SBM_LS_HALFSPACE = 4     /* normal . x - offset with a unit normal */
+};
+
+/* Uniform Cartesian background mesh: n[k] cells on [lo[k], hi[k]], k < dim. */
+typedef struct {
+  int dim;
+  int n[3];
+  double lo[3];
+  double hi[3];
+} sbm_mesh;
+
+typedef struct {
+  int kind;
+  double centre[3];
+  double radius;
+  double semi_axes[3];
+  double R, r;
+  double normal[3];
+  double offset;
+  int n_spheres;          /* SBM_LS_SPHERE_UNION: the arrays below are copied by sbm_setup */
+  const double *centres;  /* host, n_spheres x 3 (the third entry is ignored in 2D) */
+  const double *radii;    /* host, n_spheres */
+} sbm_levelset;
+
+typedef struct {
+  double penalty_gamma;    /* sigma_Gamma = penalty_gamma * p^2 / h  (<= 0 selects 10) */
+  double dg_penalty_gamma; /* sigma_F     = dg_penalty_gamma * p^2 / h (<= 0 selects 10) */
+  double shift_scale;      /* d is scaled by this factor; 1 = the method, 0 = no shift */
+  int flags;               /* SBM_SETUP_HOST_ONLY: build the host-side data only (no device
+                              allocation; the handle then serves sbm_info, sbm_dof_points,
+                              sbm_rhs_points and the sbm_export_* calls, nothing else) */
+} sbm_options;
+
+enum { SBM_SETUP_HOST_ONLY = 1 };
+
+/*
+ * sbm_setup -- build one operator (Sec. 3.4 data structures, Sec. 4.4 initialisation).
+ * Classifies the background cells (active: phi < 0 at all 2^d vertices), lists the
+ * surrogate faces (faces of active cells whose neighbour is missing or inactive), finds
+ * for every surrogate-face Gauss point x~ the exact closest point x on {phi = 0}, stores
+ * the shifted reference coordinates xi = xi~ + shift_scale (x - x~) / h, numbers the DoFs
+ * and uploads everything to the current device.
+ * DoF order: CG -- ranks of the touched lattice points m = p*c + j in lexicographic order
+ * (first coordinate fastest); DG -- (rank of the active cell) * (p+1)^d + local index.
+ * opts may be NULL (defaults).  On success *out owns all device memory of the operator.
+ * Errors: EINVAL (mesh/level set/pointer), EUNSUPPORTED (dim, p), ENOMEM, EHIP.
+ */
+sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int disc,
+                     const sbm_options *opts, sbm_handle *out);
+
+/* Counts and the device bytes the handle holds.  Any output pointer may be NULL. */
+sbm_status sbm_info(sbm_handle h, int64_t *n_dofs, int64_t *n_cells, int64_t *n_sbm_faces,
+                    int64_t *n_interior_faces, size_t *device_bytes);
+
+/* Releases every resource of h (NULL is ignored).  Synchronises the device first. */
+void sbm_destroy(sbm_handle h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *sbm_last_error(void);
+
+/*
+ * sbm_apply -- v = A u (Sec. 3.5 workflow: cell loop, then surrogate faces; for DG the
+ * interior faces are evaluated cell by cell).  u and v are device vectors of n_dofs
+ * entries of the precision prec (SBM_F64: double, SBM_F32: float); v is overwritten and
+ * must not alias u.  Asynchronous on stream; never synchronises.
+ * Errors: EINVAL (NULL handle/pointer, u == v, bad prec), EHIP (launch failure).
+ */
+sbm_status sbm_apply(sbm_handle h, const void *u, void *v, int prec, void *stream);
+
+/*
+ * sbm_apply_parts -- diagnostic split of sbm_apply: runs only the launches selected in
+ * parts (SBM_PART_ZERO: clear v (CG only); SBM_PART_CELLS: cell term, for DG including
+ * the interior faces; SBM_PART_SBM_FACES: surrogate-boundary faces).  The parts
+ * accumulate into v exactly as inside sbm_apply, so ZERO|CELLS|SBM_FACES == sbm_apply.
+ * It exists to time the cell and surrogate-face work separately (the share of time spent
+ * in surrogate faces, Sec. 4.3).  Same argument rules as sbm_apply.  Asynchronous.
+ */
+enum { SBM_PART_ZERO = 1, SBM_PART_CELLS = 2, SBM_PART_SBM_FACES = 4, SBM_PART_ALL = 7 };
+sbm_status sbm_apply_parts(sbm_handle h, const void *u, void *v, int prec, int parts, void *stream);
+
+/*
+ * sbm_apply_batch -- n independent applies v_i = A_i u_i, launched together on one
+ * stream (one launch per kernel kind and degree for all operators of the batch).
+ * Same argument rules as sbm_apply for every i.  Asynchronous.
+ */
+sbm_status sbm_apply_batch(int n, const sbm_handle *hs, const void *const *u, void *const *v,
+                           int prec, void *stream);
+
+/* Physical coordinates of every DoF (host, n_dofs x dim). */
+sbm_status sbm_dof_points(sbm_handle h, double *xyz);
+
+/*
+ * Points where the caller evaluates the problem data for sbm_rhs (host arrays):
+ *   cell_qp:  n_cells x (p+1)^d x dim  Gauss points of every active cell, cell-rank order,
+ *             lexicographic point order (first coordinate fastest);
+ *   bdry_pts: n_sbm_faces x (p+1)^(d-1) x dim  closest points x on the true boundary of
+ *             every surrogate-face Gauss point, in the library's face order.
+ * Either pointer may be NULL.
+ */
+sbm_status sbm_rhs_points(sbm_handle h, double *cell_qp, double *bdry_pts);
+
+/*
+ * sbm_rhs -- right-hand side of Eq. (1): b_i = int f psi_i - int_{Gam~} (dpsi_i/dn~) g
+ * + int_{Gam~} sigma g psi_i, from f at cell_qp and g at bdry_pts (host arrays laid out
+ * as sbm_rhs_points).  b is a device FP64 vector of n_dofs entries.  Synchronous.
+ */
+sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double *b, void *stream);
+
+/* Solver selection for sbm_solve. */
+enum {
+  SBM_SOLVE_GMRES_F64 = 0,  /* restarted GMRES(m) in FP64 */
+  SBM_SOLVE_GMRES_IR = 1,   /* FP64 iterative refinement around FP32 GMRES(m) */
+  SBM_SOLVE_CG_F64 = 2      /* conjugate gradients in FP64: only for symmetric operators
+                               (shift_scale = 0); the shifted operator is nonsymmetric */
+};
+
+typedef struct {
+  int status;             /* sbm_status of the solve */
+  int outer_its;          /* refinement steps (IR) or restart cycles (GMRES) */
+  int inner_its;          /* total Krylov iterations */
+  int applies_f64;        /* FP64 operator applications */
+  int applies_f32;        /* FP32 operator applications */
+  double rel_residual;    /* final ||b - A x||_2 / ||b||_2, computed in FP64 on the device */
+  double seconds;         /* wall time of the call */
+} sbm_solve_info;
+
+/*
+ * sbm_solve -- solve A x = b to ||b - A x|| <= rel_tol ||b|| from the initial guess in x.
+ * b, x: device FP64 vectors of n_dofs entries (x is read as the initial guess and
+ * overwritten).  restart: Krylov dimension m of GMRES (<= 0 selects 50).  max_it bounds
+ * the total Krylov iterations.  jacobi != 0 right-preconditions with the inverse of the
+ * operator's diagonal.  Synchronous (returns after the work on stream has finished).
+ * Errors: EINVAL, ENOCONV (info->rel_residual holds what was reached), EHIP.
+ */
+sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, int max_it,
+                     int mode, int restart, int jacobi, void *stream, sbm_solve_info *info);
+
+/*
+ * sbm_diagonal -- the diagonal of A (device vector of n_dofs entries, precision prec),
+ * computed matrix-free from the cell and face contributions.  Asynchronous.
+ */
+sbm_status sbm_diagonal(sbm_handle h, void *diag, int prec, void *stream);
+
+/* Device bytes sbm_setup would allocate for this problem (host-side estimate, no setup). */
+size_t sbm_footprint_estimate(const sbm_mesh *mesh, int p, int disc, int64_t n_cells_hint,
+                              int64_t n_faces_hint);
+
+/* ---- introspection for setup-parity tests (host outputs) ---- */
+/* Active-cell multi-indices (n_cells x dim, int32, cell-rank order). */
+sbm_status sbm_export_cells(sbm_handle h, int32_t *cells);
+/* Surrogate faces: (cell rank, axis, side) triples (n_sbm_faces x 3, int32, library order). */
+sbm_status sbm_export_sbm_faces(sbm_handle h, int32_t *faces);
+/* Shifted reference coordinates xi of every face point (n_sbm_faces x (p+1)^(d-1) x dim). */
+sbm_status sbm_export_face_xi(sbm_handle h, double *xi);
+/* Global DoF id of every local DoF of every active cell (n_cells x (p+1)^d, int64). */
+sbm_status sbm_export_cell_dofs(sbm_handle h, int64_t *dofs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SBM_H */

@@ -1,0 +1,576 @@
+// Matrix-free SBM operator kernels for gfx950 (CDNA4, wave64).
+//
+//   cell_kernel     Laplace cell term on every active cell (Alg. 1), CG scatter by atomics
+//   dg_cell_kernel  DG: Laplace cell term plus the SIPG terms of the cell's interior faces,
+//                   evaluated cell by cell (Alg. 2 split per side), plain stores
+//   sbm_face_kernel surrogate-boundary faces (Alg. 3): normal derivative by sum
+//                   factorisation, E u by point evaluation at the shifted point, tested
+//                   against values and normal derivatives, atomics into v
+//
+// Layout shared by all kernels: one "entity" (cell or face) is handled by NP = (p+1)^(d-1)
+// consecutive threads, EPB entities per workgroup.  Thread t of an entity owns one
+// pencil of p+1 values along a coordinate axis; the (p+1)^d tile of the cell lives in LDS.
+// The x-runs of a cell (p+1 consecutive DoFs along the first axis) are contiguous in
+// both numberings, so gathers and scatters read and write p+1 consecutive entries from a
+// per-run base index.
+//
+// Cell term in Kronecker-sum form: all active cells are translates of one reference cell
+// with Jacobian h I (Sec. 3.4), so the Gauss-point loop of Alg. 1 is a fixed diagonal
+// scaling and evaluate / quadrature / integrate collapse per axis into the 1D matrices
+//   M_ij = sum_q w_q l_i(g_q) l_j(g_q),   K_ij = sum_q w_q l'_i(g_q) l'_j(g_q)
+// (exact with p+1 Gauss points), A_K = h^(d-2) sum_k M x .. K(axis k) .. x M.  In 3D this
+// costs 7 one-dimensional sweeps instead of the 12 of the gradient form.
+#include "sbm_internal.h"
+
+namespace sbm {
+namespace {
+
+template <int D, int N1>
+struct Shape {
+  static constexpr int NP = (D == 3) ? N1 * N1 : N1;
+  static constexpr int NB = NP * N1;
+};
+
+// Entities per workgroup: fill up to 256 threads, keep the static LDS below 64 KiB.
+template <typename T, int D, int N1, int NBUF>
+constexpr int epb() {
+  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
+  int e = 256 / NP;
+  if (e < 1) e = 1;
+  while (e > 1 && (e * NBUF * NB + 4 * e * NP) * (int)sizeof(T) > 60000) --e;
+  return e;
+}
+
+// XCD-aware block order: the dispatcher hands block b to XCD (b mod 8), so give every XCD
+// one contiguous range of logical blocks; neighbouring cells then share that XCD's L2.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int x = b & 7, k = b >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  return (x < rem) ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+template <int N1>
+__device__ __forceinline__ void lagrange_at(const double (&z)[N1], const double (&cinv)[N1], double x,
+                                            double (&out)[N1]) {
+  // l_j(x) = cinv_j prod_{m != j} (x - z_m), product form (stable when extrapolating)
+  double dlt[N1], pre[N1], suf[N1];
+#pragma unroll
+  for (int m = 0; m < N1; ++m) dlt[m] = x - z[m];
+  pre[0] = 1.0;
+#pragma unroll
+  for (int m = 1; m < N1; ++m) pre[m] = pre[m - 1] * dlt[m - 1];
+  suf[N1 - 1] = 1.0;
+#pragma unroll
+  for (int m = N1 - 2; m >= 0; --m) suf[m] = suf[m + 1] * dlt[m + 1];
+#pragma unroll
+  for (int j = 0; j < N1; ++j) out[j] = cinv[j] * pre[j] * suf[j];
+}
+
+// ------------------------------------------------------------------------------------
+// Cell term, Kronecker-sum sum factorisation.  CG: atomic scatter.  (DG uses dg_cell_kernel.)
+// ------------------------------------------------------------------------------------
+template <typename T, int D, int N1, int EPB>
+__global__ __launch_bounds__(256) void cell_kernel(int n_cells, const int32_t *__restrict__ runs,
+                                                   const T *__restrict__ u, T *__restrict__ v,
+                                                   KTab<T, N1> tab, T scale) {
+  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
+  __shared__ T sa[EPB * NB];
+  __shared__ T sb[EPB * NB];
+  const int le = threadIdx.x / NP, t = threadIdx.x - le * NP;
+  const int cell = xcd_block() * EPB + le;
+  const bool act = cell < n_cells;
+  T *A = sa + le * NB;
+  T *B = sb + le * NB;
+
+  // phase 1: pencils along the last axis, gathered from global memory
+  T x[N1];
+  {
+    const int i0 = (D == 3) ? t % N1 : t;
+    const int r0 = (D == 3) ? t / N1 : 0;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const int run = (D == 3) ? r0 + N1 * k : k;
+      x[k] = act ? u[runs[(int64_t)cell * NP + run] + i0] : T(0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    T a = 0, b = 0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      a += tab.M[i * N1 + j] * x[j];
+      b += tab.K[i * N1 + j] * x[j];
+    }
+    A[t + NP * i] = a;
+    B[t + NP * i] = b;
+  }
+  __syncthreads();
+  if constexpr (D == 3) {
+    // phase 2: pencils along axis 1; c = M a, e = K a + M b
+    const int ix = t % N1, iz = t / N1;
+    T a[N1], b[N1];
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      a[j] = A[ix + N1 * j + NP * iz];
+      b[j] = B[ix + N1 * j + NP * iz];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+      T c = 0, e = 0;
+#pragma unroll
+      for (int j = 0; j < N1; ++j) {
+        c += tab.M[i * N1 + j] * a[j];
+        e += tab.K[i * N1 + j] * a[j] + tab.M[i * N1 + j] * b[j];
+      }
+      A[ix + N1 * i + NP * iz] = c;
+      B[ix + N1 * i + NP * iz] = e;
+    }
+    __syncthreads();
+  }
+  // last phase: pencils along axis 0 (thread t = run index); out = K c + M e
+  T c[N1], e[N1];
+#pragma unroll
+  for (int j = 0; j < N1; ++j) {
+    c[j] = A[j + N1 * t];
+    e[j] = B[j + N1 * t];
+  }
+  if (act) {
+    T *vp = v + runs[(int64_t)cell * NP + t];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+      T o = 0;
+#pragma unroll
+      for (int j = 0; j < N1; ++j) o += tab.K[i * N1 + j] * c[j] + tab.M[i * N1 + j] * e[j];
+      atomic_add(vp + i, scale * o);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Face helpers (3D: tangential axes b < c; 2D: one tangential axis b)
+// ------------------------------------------------------------------------------------
+template <int D, int N1>
+struct FaceAxes {
+  int a, s, Sa, Sb, Sc;
+  __device__ __forceinline__ FaceAxes(int code) {
+    a = code >> 1;
+    s = code & 1;
+    Sa = (a == 0) ? 1 : (a == 1 ? N1 : N1 * N1);
+    if (D == 3) {
+      Sb = (a == 0) ? N1 : 1;            // lower tangential axis
+      Sc = (a == 2) ? N1 : N1 * N1;      // upper tangential axis
+    } else {
+      Sb = (a == 0) ? N1 : 1;
+      Sc = 0;
+    }
+  }
+};
+
+// Gauss -> GLL transposed interpolation of two face arrays f3, f4 (Gauss-point order
+// qb + N1 qc), results at face node t = jb + N1 jc.  Uses f1, f2 as scratch.
+template <typename T, int D, int N1>
+__device__ __forceinline__ void face_integrate(const KTab<T, N1> &tab, int t, T *f1, T *f2, const T *f3,
+                                               const T *f4, T &Rv, T &Rg) {
+  if constexpr (D == 3) {
+    const int qb = t % N1, jc = t / N1;
+    T r1 = 0, r2 = 0;
+#pragma unroll
+    for (int qc = 0; qc < N1; ++qc) {
+      r1 += tab.N[qc * N1 + jc] * f3[qb + N1 * qc];
+      r2 += tab.N[qc * N1 + jc] * f4[qb + N1 * qc];
+    }
+    f1[t] = r1;
+    f2[t] = r2;
+    __syncthreads();
+    const int jb = t % N1;
+    T a1 = 0, a2 = 0;
+#pragma unroll
+    for (int q = 0; q < N1; ++q) {
+      a1 += tab.N[q * N1 + jb] * f1[q + N1 * jc];
+      a2 += tab.N[q * N1 + jb] * f2[q + N1 * jc];
+    }
+    Rv = a1;
+    Rg = a2;
+  } else {
+    T a1 = 0, a2 = 0;
+#pragma unroll
+    for (int q = 0; q < N1; ++q) {
+      a1 += tab.N[q * N1 + t] * f3[q];
+      a2 += tab.N[q * N1 + t] * f4[q];
+    }
+    Rv = a1;
+    Rg = a2;
+  }
+}
+
+// GLL -> Gauss interpolation on the face of two node arrays f1, f2 (node order jb + N1 jc);
+// returns the values at Gauss point t = qb + N1 qc.  Uses f3, f4 as scratch.
+template <typename T, int D, int N1>
+__device__ __forceinline__ void face_interpolate(const KTab<T, N1> &tab, int t, const T *f1, const T *f2,
+                                                 T *f3, T *f4, T &o1, T &o2) {
+  if constexpr (D == 3) {
+    const int qb = t % N1, jc = t / N1;
+    T r1 = 0, r2 = 0;
+#pragma unroll
+    for (int jb = 0; jb < N1; ++jb) {
+      r1 += tab.N[qb * N1 + jb] * f1[jb + N1 * jc];
+      r2 += tab.N[qb * N1 + jb] * f2[jb + N1 * jc];
+    }
+    f3[t] = r1;
+    f4[t] = r2;
+    __syncthreads();
+    const int qc = t / N1;
+    T a1 = 0, a2 = 0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      a1 += tab.N[qc * N1 + j] * f3[qb + N1 * j];
+      a2 += tab.N[qc * N1 + j] * f4[qb + N1 * j];
+    }
+    o1 = a1;
+    o2 = a2;
+  } else {
+    T a1 = 0, a2 = 0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      a1 += tab.N[t * N1 + j] * f1[j];
+      a2 += tab.N[t * N1 + j] * f2[j];
+    }
+    o1 = a1;
+    o2 = a2;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Surrogate-boundary faces (Alg. 3).  One entity = one face of its active cell K.
+// ------------------------------------------------------------------------------------
+template <typename T, int D, int N1, int EPB, bool DG>
+__global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_t *__restrict__ face_cell,
+                                                       const int32_t *__restrict__ face_code,
+                                                       const double *__restrict__ face_xi,
+                                                       const int32_t *__restrict__ runs,
+                                                       const T *__restrict__ u, T *__restrict__ v,
+                                                       KTab<T, N1> tab, KScal sc) {
+  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, P = N1 - 1;
+  __shared__ T su_all[EPB * NB];
+  __shared__ T sw_all[EPB * NB];
+  __shared__ T f_all[4 * EPB * NP];
+  const int le = threadIdx.x / NP, t = threadIdx.x - le * NP;
+  const int f = xcd_block() * EPB + le;
+  const bool act = f < n_faces;
+  T *su = su_all + le * NB;
+  T *sw = sw_all + le * NB;
+  T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
+  const int cell = act ? face_cell[f] : 0;
+  const FaceAxes<D, N1> fa(act ? face_code[f] : 0);
+  const T h = T(sc.h), sig = T(sc.sigma_gamma);
+  const T sgn = fa.s ? T(1) : T(-1);
+
+  // gather u_K: thread t = run index
+  int64_t base = 0;
+  if (act) {
+    base = DG ? (int64_t)cell * NB + N1 * t : (int64_t)runs[(int64_t)cell * NP + t];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) su[N1 * t + i] = u[base + i];
+  }
+  __syncthreads();
+
+  // normal derivative (reference, along axis a) at the face nodes t = jb + N1 jc
+  const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
+  const int node_off = jb * fa.Sb + jc * fa.Sc;
+  {
+    T g = 0;
+#pragma unroll
+    for (int ia = 0; ia < N1; ++ia) g += (fa.s ? tab.D1[ia] : tab.D0[ia]) * su[ia * fa.Sa + node_off];
+    f1[t] = g;
+    f2[t] = g;
+  }
+  __syncthreads();
+  T dn, dn2;
+  face_interpolate<T, D, N1>(tab, t, f1, f2, f3, f4, dn, dn2);
+  dn *= sgn / h;
+
+  // E u at the shifted point of Gauss point t (point evaluation, (p+1)^d terms)
+  T eu = 0;
+  T om = 0;
+  if (act) {
+    const double *xq = face_xi + ((int64_t)f * NP + t) * D;
+    double l[D][N1];
+#pragma unroll
+    for (int k = 0; k < D; ++k) lagrange_at<N1>(tab.z, tab.cinv, xq[k], l[k]);
+    T l0[N1], l1[N1];
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      l0[j] = T(l[0][j]);
+      l1[j] = T(l[1][j]);
+    }
+    if constexpr (D == 3) {
+#pragma unroll
+      for (int i2 = 0; i2 < N1; ++i2) {
+        T s1 = 0;
+#pragma unroll
+        for (int i1 = 0; i1 < N1; ++i1) {
+          T s0 = 0;
+#pragma unroll
+          for (int i0 = 0; i0 < N1; ++i0) s0 += l0[i0] * su[i0 + N1 * i1 + NP * i2];
+          s1 += l1[i1] * s0;
+        }
+        eu += T(l[2][i2]) * s1;
+      }
+      om = h * h * tab.w[t % N1] * tab.w[t / N1];
+    } else {
+#pragma unroll
+      for (int i1 = 0; i1 < N1; ++i1) {
+        T s0 = 0;
+#pragma unroll
+        for (int i0 = 0; i0 < N1; ++i0) s0 += l0[i0] * su[i0 + N1 * i1];
+        eu += l1[i1] * s0;
+      }
+      om = h * tab.w[t];
+    }
+  }
+  __syncthreads();  // f3/f4 reads of face_interpolate are done
+  f3[t] = om * (sig * eu - dn);   // tested against v
+  f4[t] = -om * eu * sgn / h;     // tested against the reference derivative along a
+  __syncthreads();
+  T Rv, Rg;
+  face_integrate<T, D, N1>(tab, t, f1, f2, f3, f4, Rv, Rg);
+#pragma unroll
+  for (int ia = 0; ia < N1; ++ia)
+    sw[ia * fa.Sa + node_off] = ((ia == fa.s * P) ? Rv : T(0)) + (fa.s ? tab.D1[ia] : tab.D0[ia]) * Rg;
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < N1; ++i) atomic_add(v + base + i, sw[N1 * t + i]);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// DG cell kernel: Laplace cell term + SIPG terms of the cell's interior faces, computed
+// from the cell's side only (each interior face is evaluated twice, once per cell), so
+// every cell writes only its own block: no atomics, deterministic.
+// For the face (a, s) of K with neighbour N and outward normal n_K = (2s-1) e_a:
+//   [u]_K = u_K - u_N,  {du/dn_K} = (du_K/dn_K + du_N/dn_K)/2,
+//   K's rows += int (sigma_F [u]_K - {du/dn_K}) v - 1/2 [u]_K dv/dn_K   (Alg. 2, per side)
+// ------------------------------------------------------------------------------------
+template <typename T, int D, int N1, int EPB>
+__global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t *__restrict__ nbr,
+                                                      const T *__restrict__ u, T *__restrict__ v,
+                                                      KTab<T, N1> tab, KScal sc, T scale) {
+  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, P = N1 - 1;
+  __shared__ T su_all[EPB * NB];
+  __shared__ T sa_all[EPB * NB];
+  __shared__ T sb_all[EPB * NB];
+  __shared__ T sw_all[EPB * NB];
+  __shared__ T f_all[4 * EPB * NP];
+  const int le = threadIdx.x / NP, t = threadIdx.x - le * NP;
+  const int cell = xcd_block() * EPB + le;
+  const bool act = cell < n_cells;
+  T *su = su_all + le * NB, *A = sa_all + le * NB, *B = sb_all + le * NB, *sw = sw_all + le * NB;
+  T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
+  const T h = T(sc.h), sigf = T(sc.sigma_f);
+
+  // gather own block (contiguous), thread t = run
+  if (act) {
+    const T *up = u + (int64_t)cell * NB + N1 * t;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) su[N1 * t + i] = up[i];
+  }
+  __syncthreads();
+  // ---- volume term (Kronecker sum), same sweeps as cell_kernel, input from LDS ----
+  {
+    T x[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) x[k] = su[t + NP * k];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+      T a = 0, b = 0;
+#pragma unroll
+      for (int j = 0; j < N1; ++j) {
+        a += tab.M[i * N1 + j] * x[j];
+        b += tab.K[i * N1 + j] * x[j];
+      }
+      A[t + NP * i] = a;
+      B[t + NP * i] = b;
+    }
+  }
+  __syncthreads();
+  if constexpr (D == 3) {
+    const int ix = t % N1, iz = t / N1;
+    T a[N1], b[N1];
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      a[j] = A[ix + N1 * j + NP * iz];
+      b[j] = B[ix + N1 * j + NP * iz];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+      T c = 0, e = 0;
+#pragma unroll
+      for (int j = 0; j < N1; ++j) {
+        c += tab.M[i * N1 + j] * a[j];
+        e += tab.K[i * N1 + j] * a[j] + tab.M[i * N1 + j] * b[j];
+      }
+      A[ix + N1 * i + NP * iz] = c;
+      B[ix + N1 * i + NP * iz] = e;
+    }
+    __syncthreads();
+  }
+  {
+    T c[N1], e[N1];
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      c[j] = A[j + N1 * t];
+      e[j] = B[j + N1 * t];
+    }
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+      T o = 0;
+#pragma unroll
+      for (int j = 0; j < N1; ++j) o += tab.K[i * N1 + j] * c[j] + tab.M[i * N1 + j] * e[j];
+      sw[N1 * t + i] = scale * o;
+    }
+  }
+  // ---- interior faces ----
+  const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
+  for (int code = 0; code < 2 * D; ++code) {
+    const FaceAxes<D, N1> fa(code);
+    const int nb = act ? nbr[(int64_t)cell * 2 * D + code] : -1;
+    const bool has = nb >= 0;
+    __syncthreads();  // previous users of A (neighbour tile) and f1..f4 are done
+    if (has) {
+      const T *up = u + (int64_t)nb * NB + N1 * t;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) A[N1 * t + i] = up[i];
+    }
+    __syncthreads();
+    const T sgn = fa.s ? T(1) : T(-1);
+    const int node_off = jb * fa.Sb + jc * fa.Sc;
+    {
+      T dK = 0, dN = 0;
+#pragma unroll
+      for (int ia = 0; ia < N1; ++ia) {
+        dK += (fa.s ? tab.D1[ia] : tab.D0[ia]) * su[ia * fa.Sa + node_off];
+        dN += (fa.s ? tab.D0[ia] : tab.D1[ia]) * A[ia * fa.Sa + node_off];
+      }
+      const T uK = su[fa.s * P * fa.Sa + node_off];
+      const T uN = A[(1 - fa.s) * P * fa.Sa + node_off];
+      f1[t] = uK - uN;                          // [u]_K at the face nodes
+      f2[t] = T(0.5) * sgn * (dK + dN) / h;     // {du/dn_K} at the face nodes
+    }
+    __syncthreads();
+    T jq, aq;
+    face_interpolate<T, D, N1>(tab, t, f1, f2, f3, f4, jq, aq);
+    T om;
+    if constexpr (D == 3)
+      om = h * h * tab.w[t % N1] * tab.w[t / N1];
+    else
+      om = h * tab.w[t];
+    __syncthreads();
+    f3[t] = om * (sigf * jq - aq);
+    f4[t] = T(-0.5) * om * jq * sgn / h;
+    __syncthreads();
+    T Rv, Rg;
+    face_integrate<T, D, N1>(tab, t, f1, f2, f3, f4, Rv, Rg);
+    if (has) {
+#pragma unroll
+      for (int ia = 0; ia < N1; ++ia)
+        sw[ia * fa.Sa + node_off] += ((ia == fa.s * P) ? Rv : T(0)) + (fa.s ? tab.D1[ia] : tab.D0[ia]) * Rg;
+    }
+  }
+  __syncthreads();
+  if (act) {
+    T *vp = v + (int64_t)cell * NB + N1 * t;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) vp[i] = sw[N1 * t + i];
+  }
+}
+
+template <typename T, int N1>
+KTab<T, N1> make_ktab(const Rules1D &r) {
+  KTab<T, N1> k;
+  for (int i = 0; i < N1 * N1; ++i) {
+    k.M[i] = T(r.M[i]);
+    k.K[i] = T(r.K[i]);
+    k.N[i] = T(r.N[i]);
+  }
+  for (int j = 0; j < N1; ++j) {
+    k.D0[j] = T(r.D0[j]);
+    k.D1[j] = T(r.D1[j]);
+    k.w[j] = T(r.w[j]);
+    k.z[j] = r.z[j];
+    k.cinv[j] = r.cinv[j];
+  }
+  return k;
+}
+
+template <typename T, int D, int N1>
+hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t s) {
+  constexpr int NP = Shape<D, N1>::NP;
+  const KTab<T, N1> tab = make_ktab<T, N1>(c->rules);
+  const KScal sc{c->h, c->sigma_gamma, c->sigma_f};
+  const T scale = T(D == 3 ? c->h : 1.0);
+  const int nc = (int)c->n_cells, nf = (int)c->n_sbm;
+  if (c->disc == SBM_CG) {
+    if (parts & SBM_PART_ZERO) {
+      hipError_t e = vec_fill(v, c->n_dofs, 0.0, sizeof(T) == 8 ? SBM_F64 : SBM_F32, s);
+      if (e != hipSuccess) return e;
+    }
+    if (nc > 0 && (parts & SBM_PART_CELLS)) {
+      constexpr int E = epb<T, D, N1, 2>();
+      hipLaunchKernelGGL((cell_kernel<T, D, N1, E>), dim3((nc + E - 1) / E), dim3(E * NP), 0, s, nc,
+                         c->d_runs, u, v, tab, scale);
+    }
+    if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
+      constexpr int E = epb<T, D, N1, 2>();
+      hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E, false>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s,
+                         nf, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, v, tab, sc);
+    }
+  } else {
+    if (nc > 0 && (parts & SBM_PART_CELLS)) {
+      constexpr int E = epb<T, D, N1, 4>();
+      hipLaunchKernelGGL((dg_cell_kernel<T, D, N1, E>), dim3((nc + E - 1) / E), dim3(E * NP), 0, s, nc,
+                         c->d_nbr, u, v, tab, sc, scale);
+    }
+    if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
+      constexpr int E = epb<T, D, N1, 2>();
+      hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E, true>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s,
+                         nf, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, v, tab, sc);
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int D>
+hipError_t apply_dim(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t s) {
+  switch (c->p) {
+    case 1: return apply_impl<T, D, 2>(c, u, v, parts, s);
+    case 2: return apply_impl<T, D, 3>(c, u, v, parts, s);
+    case 3: return apply_impl<T, D, 4>(c, u, v, parts, s);
+    case 4: return apply_impl<T, D, 5>(c, u, v, parts, s);
+    case 5: return apply_impl<T, D, 6>(c, u, v, parts, s);
+    case 6: return apply_impl<T, D, 7>(c, u, v, parts, s);
+    case 7: return apply_impl<T, D, 8>(c, u, v, parts, s);
+    case 8: return apply_impl<T, D, 9>(c, u, v, parts, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_apply(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s) {
+  if (prec == SBM_F64) {
+    return c->dim == 3 ? apply_dim<double, 3>(c, (const double *)u, (double *)v, parts, s)
+                       : apply_dim<double, 2>(c, (const double *)u, (double *)v, parts, s);
+  }
+  return c->dim == 3 ? apply_dim<float, 3>(c, (const float *)u, (float *)v, parts, s)
+                     : apply_dim<float, 2>(c, (const float *)u, (float *)v, parts, s);
+}
+
+}  // namespace sbm

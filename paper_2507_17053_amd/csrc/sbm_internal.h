@@ -1,0 +1,117 @@
+// Internal declarations of the SBM library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sbm.h"
+
+namespace sbm {
+
+constexpr int kMaxP = 8;
+constexpr int kMaxN1 = kMaxP + 1;
+
+// 1D reference data on [0,1] for one degree p (always computed in FP64 on the host).
+struct Rules1D {
+  int p = 0;
+  std::vector<double> z;      // GLL nodes (p+1)
+  std::vector<double> g, w;   // Gauss points and weights (p+1), weights sum to 1
+  std::vector<double> cinv;   // 1 / prod_{m != j} (z_j - z_m)
+  std::vector<double> M, K;   // 1D mass / stiffness on [0,1]: sum_q w_q l_i(g_q) l_j(g_q), ... l'_i l'_j
+  std::vector<double> N;      // N[q*(p+1)+j] = l_j(g_q): GLL -> Gauss interpolation
+  std::vector<double> D0, D1; // l'_j(0), l'_j(1)
+};
+Rules1D make_rules(int p);
+double lagrange_value(const Rules1D &r, int j, double x);
+double lagrange_derivative(const Rules1D &r, int j, double x);
+
+// Level set held by a context (arrays copied from the caller).
+struct LevelSet {
+  int kind = 0;
+  int dim = 3;
+  double centre[3] = {0, 0, 0};
+  double radius = 0, R = 0, r = 0, offset = 0;
+  double semi[3] = {1, 1, 1};
+  double normal[3] = {1, 0, 0};
+  std::vector<double> cs;  // n x 3
+  std::vector<double> rs;
+  double phi(const double *x) const;
+  void closest(const double *x, double *out) const;  // exact closest point on {phi = 0}
+};
+
+// Kernel-side tables, passed by value (kernel arguments live in the constant kernarg
+// segment; all table indices in the kernels are compile-time constants after unrolling).
+template <typename T, int N1>
+struct KTab {
+  T M[N1 * N1];
+  T K[N1 * N1];
+  T N[N1 * N1];
+  T D0[N1];
+  T D1[N1];
+  T w[N1];
+  double z[N1];
+  double cinv[N1];
+};
+
+// Per-operator scalars passed to the kernels.
+struct KScal {
+  double h;
+  double sigma_gamma;
+  double sigma_f;
+};
+
+struct Workspace;  // solver vectors (allocated on first solve)
+
+}  // namespace sbm
+
+struct sbm_ctx {
+  int dim = 3, p = 1, n1 = 2, disc = SBM_CG;
+  int n[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  double h = 1.0;
+  double gamma = 10.0, gamma_dg = 10.0, shift_scale = 1.0;
+  double sigma_gamma = 0.0, sigma_f = 0.0;
+  int64_t n_cells = 0, n_dofs = 0, n_sbm = 0, n_int = 0;
+  int nq_face = 1;   // (p+1)^(d-1)
+  int nb = 1;        // (p+1)^d
+  sbm::Rules1D rules;
+  sbm::LevelSet ls;
+  // host copies (setup results)
+  std::vector<int32_t> cells;      // n_cells x dim
+  std::vector<int32_t> faces;      // n_sbm x 3 (cell rank, axis, side)
+  std::vector<double> face_xi;     // n_sbm x nq x dim
+  std::vector<double> face_xtrue;  // n_sbm x nq x dim
+  std::vector<int32_t> runs;       // CG: n_cells x (p+1)^(d-1) first DoF of each x-run
+  std::vector<int32_t> nbr;        // n_cells x 2d neighbour rank or -1
+  // device copies
+  int32_t *d_runs = nullptr;       // CG
+  int32_t *d_nbr = nullptr;        // DG
+  int32_t *d_face_cell = nullptr;  // n_sbm
+  int32_t *d_face_code = nullptr;  // n_sbm: 2*axis + side
+  double *d_face_xi = nullptr;     // n_sbm x nq x dim
+  size_t device_bytes = 0;
+  bool host_only = false;
+  sbm::Workspace *ws = nullptr;
+};
+
+namespace sbm {
+// Thread-local last error.
+void set_error(const std::string &msg);
+// Launchers (kernels.hip).  All asynchronous on stream.
+hipError_t launch_apply(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s);
+hipError_t launch_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s);
+// Vector kernels (vec.hip)
+hipError_t vec_fill(void *x, int64_t n, double val, int prec, hipStream_t s);
+}  // namespace sbm
+
+#define SBM_HIP_CHECK(expr)                                                      \
+  do {                                                                           \
+    hipError_t _e = (expr);                                                      \
+    if (_e != hipSuccess) {                                                      \
+      sbm::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));         \
+      return SBM_EHIP;                                                           \
+    }                                                                            \
+  } while (0)

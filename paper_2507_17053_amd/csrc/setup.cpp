@@ -1,0 +1,894 @@
+// Host-side setup of the SBM operator (Sec. 2 surrogate domain, Sec. 2.1 closest-point
+// shifts, Sec. 3.4 per-face data) and the C-ABI entry points that do not launch kernels.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+
+#include "sbm_internal.h"
+
+namespace sbm {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------------------------------
+// 1D rules on [0,1] (Sec. 3.1): GLL nodes for the basis, Gauss points for quadrature.
+// ---------------------------------------------------------------------------------------
+static void legendre(int n, double x, double &pn, double &dpn) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) {
+    pn = 1.0;
+    dpn = 0.0;
+    return;
+  }
+  for (int k = 1; k < n; ++k) {
+    const double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+    p0 = p1;
+    p1 = p2;
+  }
+  pn = p1;
+  dpn = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+Rules1D make_rules(int p) {
+  Rules1D r;
+  r.p = p;
+  const int n1 = p + 1;
+  // Gauss-Legendre: roots of P_{p+1} by Newton
+  std::vector<double> gx(n1), gw(n1);
+  if (n1 == 1) {
+    gx[0] = 0.0;
+    gw[0] = 2.0;
+  } else {
+    for (int i = 0; i < n1; ++i) {
+      double x = -std::cos(M_PI * (i + 0.75) / (n1 + 0.5));
+      for (int it = 0; it < 100; ++it) {
+        double pn, dp;
+        legendre(n1, x, pn, dp);
+        const double dx = pn / dp;
+        x -= dx;
+        if (std::fabs(dx) < 1e-16) break;
+      }
+      double pn, dp;
+      legendre(n1, x, pn, dp);
+      gx[i] = x;
+      gw[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+  }
+  std::vector<int> ord(n1);
+  for (int i = 0; i < n1; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return gx[a] < gx[b]; });
+  r.g.resize(n1);
+  r.w.resize(n1);
+  for (int i = 0; i < n1; ++i) {
+    r.g[i] = 0.5 * (gx[ord[i]] + 1.0);
+    r.w[i] = 0.5 * gw[ord[i]];
+  }
+  // GLL: -1, roots of P'_p, 1
+  std::vector<double> zz(n1);
+  zz[0] = -1.0;
+  zz[p] = 1.0;
+  for (int i = 1; i < p; ++i) {
+    double x = -std::cos(M_PI * i / p);
+    for (int it = 0; it < 100; ++it) {
+      double pn, dp;
+      legendre(p, x, pn, dp);
+      const double d2 = (2.0 * x * dp - p * (p + 1.0) * pn) / (1.0 - x * x);
+      const double dx = dp / d2;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    zz[i] = x;
+  }
+  std::sort(zz.begin(), zz.end());
+  r.z.resize(n1);
+  for (int i = 0; i < n1; ++i) r.z[i] = 0.5 * (zz[i] + 1.0);
+  r.cinv.resize(n1);
+  for (int j = 0; j < n1; ++j) {
+    double d = 1.0;
+    for (int m = 0; m < n1; ++m)
+      if (m != j) d *= (r.z[j] - r.z[m]);
+    r.cinv[j] = 1.0 / d;
+  }
+  r.N.assign(n1 * n1, 0.0);
+  r.M.assign(n1 * n1, 0.0);
+  r.K.assign(n1 * n1, 0.0);
+  r.D0.resize(n1);
+  r.D1.resize(n1);
+  std::vector<double> lv(n1 * n1), ld(n1 * n1);
+  for (int q = 0; q < n1; ++q)
+    for (int j = 0; j < n1; ++j) {
+      lv[q * n1 + j] = lagrange_value(r, j, r.g[q]);
+      ld[q * n1 + j] = lagrange_derivative(r, j, r.g[q]);
+      r.N[q * n1 + j] = lv[q * n1 + j];
+    }
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j) {
+      double m = 0, k = 0;
+      for (int q = 0; q < n1; ++q) {
+        m += r.w[q] * lv[q * n1 + i] * lv[q * n1 + j];
+        k += r.w[q] * ld[q * n1 + i] * ld[q * n1 + j];
+      }
+      r.M[i * n1 + j] = m;
+      r.K[i * n1 + j] = k;
+    }
+  for (int j = 0; j < n1; ++j) {
+    r.D0[j] = lagrange_derivative(r, j, 0.0);
+    r.D1[j] = lagrange_derivative(r, j, 1.0);
+  }
+  return r;
+}
+
+double lagrange_value(const Rules1D &r, int j, double x) {
+  double v = r.cinv[j];
+  for (int m = 0; m <= r.p; ++m)
+    if (m != j) v *= (x - r.z[m]);
+  return v;
+}
+
+double lagrange_derivative(const Rules1D &r, int j, double x) {
+  double s = 0.0;
+  for (int k = 0; k <= r.p; ++k) {
+    if (k == j) continue;
+    double t = r.cinv[j];
+    for (int m = 0; m <= r.p; ++m)
+      if (m != j && m != k) t *= (x - r.z[m]);
+    s += t;
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Level sets and exact closest points
+// ---------------------------------------------------------------------------------------
+static double norm_d(const double *v, int d) {
+  double s = 0;
+  for (int k = 0; k < d; ++k) s += v[k] * v[k];
+  return std::sqrt(s);
+}
+
+double LevelSet::phi(const double *x) const {
+  const int d = dim;
+  switch (kind) {
+    case SBM_LS_SPHERE: {
+      double s = 0;
+      for (int k = 0; k < d; ++k) s += (x[k] - centre[k]) * (x[k] - centre[k]);
+      return std::sqrt(s) - radius;
+    }
+    case SBM_LS_ELLIPSOID: {
+      double s = 0;
+      for (int k = 0; k < d; ++k) {
+        const double t = (x[k] - centre[k]) / semi[k];
+        s += t * t;
+      }
+      return s - 1.0;
+    }
+    case SBM_LS_TORUS: {
+      const double y0 = x[0] - centre[0], y1 = x[1] - centre[1], y2 = x[2] - centre[2];
+      const double rho = std::sqrt(y0 * y0 + y1 * y1);
+      return std::sqrt((rho - R) * (rho - R) + y2 * y2) - r;
+    }
+    case SBM_LS_HALFSPACE: {
+      double s = 0;
+      for (int k = 0; k < d; ++k) s += normal[k] * x[k];
+      return s - offset;
+    }
+    case SBM_LS_SPHERE_UNION: {
+      double best = std::numeric_limits<double>::infinity();
+      for (size_t i = 0; i < rs.size(); ++i) {
+        double s = 0;
+        for (int k = 0; k < d; ++k) s += (x[k] - cs[3 * i + k]) * (x[k] - cs[3 * i + k]);
+        best = std::min(best, std::sqrt(s) - rs[i]);
+      }
+      return best;
+    }
+  }
+  return 0.0;
+}
+
+// Ellipsoid: x_k = a_k^2 y_k / (a_k^2 + t) with t the largest root of
+// F(t) = sum (a_k y_k / (a_k^2 + t))^2 - 1, bracketed and bisected.
+static void closest_ellipsoid(const double *a, const double *c, int d, const double *x, double *out) {
+  double y[3], a2[3];
+  double amin2 = std::numeric_limits<double>::infinity();
+  int kmin = 0;
+  for (int k = 0; k < d; ++k) {
+    y[k] = x[k] - c[k];
+    a2[k] = a[k] * a[k];
+    if (a2[k] < amin2) {
+      amin2 = a2[k];
+      kmin = k;
+    }
+  }
+  auto F = [&](double t) {
+    double s = 0;
+    for (int k = 0; k < d; ++k)
+      if (y[k] != 0.0) {
+        const double q = a[k] * y[k] / (a2[k] + t);
+        s += q * q;
+      }
+    return s - 1.0;
+  };
+  double lo = -amin2;
+  for (int k = 0; k < d; ++k)
+    if (y[k] != 0.0) lo = std::max(lo, -a2[k] + a[k] * std::fabs(y[k]));
+  double hs = 0;
+  for (int k = 0; k < d; ++k) hs += a2[k] * y[k] * y[k];
+  double hi = std::max(0.0, std::sqrt(hs));
+  if (lo == -amin2 && y[kmin] == 0.0 && F(lo) <= 0.0) {
+    double s = 0;
+    for (int k = 0; k < d; ++k) {
+      if (k == kmin) continue;
+      out[k] = a2[k] * y[k] / (a2[k] - amin2);
+      s += (out[k] / a[k]) * (out[k] / a[k]);
+    }
+    out[kmin] = a[kmin] * std::sqrt(std::max(0.0, 1.0 - s));
+    for (int k = 0; k < d; ++k) out[k] += c[k];
+    return;
+  }
+  for (int it = 0; it < 400; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (F(mid) > 0.0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const double t = 0.5 * (lo + hi);
+  for (int k = 0; k < d; ++k) out[k] = c[k] + a2[k] * y[k] / (a2[k] + t);
+}
+
+// Union of balls: nearest among the critical points of the distance on every boundary
+// stratum (each sphere: nearest/farthest point; each pairwise circle: nearest/farthest
+// point, or the two intersection points in 2D; each triple point in 3D) that is not
+// strictly inside another ball.  Candidates are visited in a fixed order and the first
+// strict minimum wins.
+static void closest_union(const std::vector<double> &cs, const std::vector<double> &rs, int d,
+                          const double *x, double *out) {
+  const int S = (int)rs.size();
+  double best = std::numeric_limits<double>::infinity();
+  bool found = false;
+  auto consider = [&](const double *pt, int o0, int o1, int o2) {
+    for (int l = 0; l < S; ++l) {
+      if (l == o0 || l == o1 || l == o2) continue;
+      double s = 0;
+      for (int k = 0; k < d; ++k) s += (pt[k] - cs[3 * l + k]) * (pt[k] - cs[3 * l + k]);
+      if (std::sqrt(s) < rs[l]) return;
+    }
+    double s = 0;
+    for (int k = 0; k < d; ++k) s += (pt[k] - x[k]) * (pt[k] - x[k]);
+    const double dist = std::sqrt(s);
+    if (dist < best) {
+      best = dist;
+      found = true;
+      for (int k = 0; k < d; ++k) out[k] = pt[k];
+    }
+  };
+  double pt[3];
+  for (int i = 0; i < S; ++i) {
+    double u[3];
+    for (int k = 0; k < d; ++k) u[k] = x[k] - cs[3 * i + k];
+    double nu = norm_d(u, d);
+    if (nu == 0.0) {
+      for (int k = 0; k < d; ++k) u[k] = 0.0;
+      u[0] = 1.0;
+      nu = 1.0;
+    }
+    for (int k = 0; k < d; ++k) pt[k] = cs[3 * i + k] + rs[i] * u[k] / nu;
+    consider(pt, i, -1, -1);
+    for (int k = 0; k < d; ++k) pt[k] = cs[3 * i + k] - rs[i] * u[k] / nu;
+    consider(pt, i, -1, -1);
+  }
+  for (int i = 0; i < S; ++i)
+    for (int j = i + 1; j < S; ++j) {
+      double e[3];
+      for (int k = 0; k < d; ++k) e[k] = cs[3 * j + k] - cs[3 * i + k];
+      const double D = norm_d(e, d);
+      if (!(std::fabs(rs[i] - rs[j]) < D && D < rs[i] + rs[j])) continue;
+      for (int k = 0; k < d; ++k) e[k] /= D;
+      const double t = (D * D + rs[i] * rs[i] - rs[j] * rs[j]) / (2.0 * D);
+      const double rho = std::sqrt(rs[i] * rs[i] - t * t);
+      double m[3];
+      for (int k = 0; k < d; ++k) m[k] = cs[3 * i + k] + t * e[k];
+      if (d == 2) {
+        const double perp[2] = {-e[1], e[0]};
+        for (int k = 0; k < 2; ++k) pt[k] = m[k] + rho * perp[k];
+        consider(pt, i, j, -1);
+        for (int k = 0; k < 2; ++k) pt[k] = m[k] - rho * perp[k];
+        consider(pt, i, j, -1);
+      } else {
+        double w[3], ym[3];
+        for (int k = 0; k < 3; ++k) ym[k] = x[k] - m[k];
+        const double pr = ym[0] * e[0] + ym[1] * e[1] + ym[2] * e[2];
+        for (int k = 0; k < 3; ++k) w[k] = ym[k] - pr * e[k];
+        double nw = norm_d(w, 3);
+        if (nw == 0.0) {
+          double a3[3] = {0, 0, 0};
+          int km = 0;
+          for (int k = 1; k < 3; ++k)
+            if (std::fabs(e[k]) < std::fabs(e[km])) km = k;
+          a3[km] = 1.0;
+          const double ad = a3[0] * e[0] + a3[1] * e[1] + a3[2] * e[2];
+          for (int k = 0; k < 3; ++k) w[k] = a3[k] - ad * e[k];
+          nw = norm_d(w, 3);
+        }
+        for (int k = 0; k < 3; ++k) pt[k] = m[k] + rho * w[k] / nw;
+        consider(pt, i, j, -1);
+        for (int k = 0; k < 3; ++k) pt[k] = m[k] - rho * w[k] / nw;
+        consider(pt, i, j, -1);
+      }
+    }
+  if (d == 3) {
+    for (int i = 0; i < S; ++i)
+      for (int j = i + 1; j < S; ++j)
+        for (int l = j + 1; l < S; ++l) {
+          // three-sphere intersection in the frame (ex, ey, ez) anchored at c_i
+          const double *c1 = &cs[3 * i], *c2 = &cs[3 * j], *c3 = &cs[3 * l];
+          double ex[3], ey[3], ez[3];
+          for (int k = 0; k < 3; ++k) ex[k] = c2[k] - c1[k];
+          const double dd = norm_d(ex, 3);
+          if (dd == 0.0) continue;
+          for (int k = 0; k < 3; ++k) ex[k] /= dd;
+          double c31[3];
+          for (int k = 0; k < 3; ++k) c31[k] = c3[k] - c1[k];
+          const double ii = ex[0] * c31[0] + ex[1] * c31[1] + ex[2] * c31[2];
+          for (int k = 0; k < 3; ++k) ey[k] = c31[k] - ii * ex[k];
+          const double ney = norm_d(ey, 3);
+          if (ney == 0.0) continue;
+          for (int k = 0; k < 3; ++k) ey[k] /= ney;
+          ez[0] = ex[1] * ey[2] - ex[2] * ey[1];
+          ez[1] = ex[2] * ey[0] - ex[0] * ey[2];
+          ez[2] = ex[0] * ey[1] - ex[1] * ey[0];
+          const double jj = ey[0] * c31[0] + ey[1] * c31[1] + ey[2] * c31[2];
+          const double r1 = rs[i], r2 = rs[j], r3 = rs[l];
+          const double xx = (r1 * r1 - r2 * r2 + dd * dd) / (2.0 * dd);
+          const double yy = (r1 * r1 - r3 * r3 + ii * ii + jj * jj) / (2.0 * jj) - (ii / jj) * xx;
+          const double z2 = r1 * r1 - xx * xx - yy * yy;
+          if (z2 <= 0.0) continue;
+          const double zz = std::sqrt(z2);
+          for (int sgn = 1; sgn >= -1; sgn -= 2) {
+            for (int k = 0; k < 3; ++k) pt[k] = c1[k] + xx * ex[k] + yy * ey[k] + sgn * zz * ez[k];
+            consider(pt, i, j, l);
+          }
+        }
+  }
+  if (!found)
+    for (int k = 0; k < d; ++k) out[k] = std::numeric_limits<double>::quiet_NaN();
+}
+
+void LevelSet::closest(const double *x, double *out) const {
+  const int d = dim;
+  switch (kind) {
+    case SBM_LS_SPHERE: {
+      double u[3];
+      for (int k = 0; k < d; ++k) u[k] = x[k] - centre[k];
+      const double nu = norm_d(u, d);
+      for (int k = 0; k < d; ++k) out[k] = centre[k] + radius * u[k] / nu;
+      return;
+    }
+    case SBM_LS_ELLIPSOID:
+      closest_ellipsoid(semi, centre, d, x, out);
+      return;
+    case SBM_LS_TORUS: {
+      const double y0 = x[0] - centre[0], y1 = x[1] - centre[1], y2 = x[2] - centre[2];
+      const double rho = std::sqrt(y0 * y0 + y1 * y1);
+      const double core[3] = {R * y0 / rho, R * y1 / rho, 0.0};
+      const double u[3] = {y0 - core[0], y1 - core[1], y2 - core[2]};
+      const double nu = norm_d(u, 3);
+      for (int k = 0; k < 3; ++k) out[k] = centre[k] + core[k] + r * u[k] / nu;
+      return;
+    }
+    case SBM_LS_HALFSPACE: {
+      const double ph = phi(x);
+      for (int k = 0; k < d; ++k) out[k] = x[k] - ph * normal[k];
+      return;
+    }
+    case SBM_LS_SPHERE_UNION:
+      closest_union(cs, rs, d, x, out);
+      return;
+  }
+}
+
+}  // namespace sbm
+
+using namespace sbm;
+
+// ---------------------------------------------------------------------------------------
+// Setup
+// ---------------------------------------------------------------------------------------
+template <typename V>
+static hipError_t upload(V **dst, const std::vector<V> &src, size_t &bytes) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void **)dst, src.size() * sizeof(V));
+  if (e != hipSuccess) return e;
+  bytes += src.size() * sizeof(V);
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice);
+}
+
+static void free_device(sbm_ctx *c) {
+  if (c->d_runs) (void)hipFree(c->d_runs);
+  if (c->d_nbr) (void)hipFree(c->d_nbr);
+  if (c->d_face_cell) (void)hipFree(c->d_face_cell);
+  if (c->d_face_code) (void)hipFree(c->d_face_code);
+  if (c->d_face_xi) (void)hipFree(c->d_face_xi);
+  c->d_runs = c->d_nbr = c->d_face_cell = c->d_face_code = nullptr;
+  c->d_face_xi = nullptr;
+}
+
+namespace sbm {
+void free_workspace(sbm_ctx *c);  // solver.hip
+}
+
+// Host part of the setup; separate so that tests can exercise it without a device.
+static sbm_status host_setup(sbm_ctx *c, const sbm_mesh *mesh, const sbm_levelset *ls, int p, int disc,
+                             const sbm_options *opts) {
+  if (!mesh || !ls) {
+    set_error("sbm_setup: NULL mesh or level set");
+    return SBM_EINVAL;
+  }
+  const int d = mesh->dim;
+  if (d != 2 && d != 3) {
+    set_error("sbm_setup: dim must be 2 or 3");
+    return SBM_EUNSUPPORTED;
+  }
+  if (p < 1 || p > kMaxP) {
+    set_error("sbm_setup: p must be in 1..8");
+    return SBM_EUNSUPPORTED;
+  }
+  if (disc != SBM_CG && disc != SBM_DG) {
+    set_error("sbm_setup: disc must be SBM_CG or SBM_DG");
+    return SBM_EINVAL;
+  }
+  for (int k = 0; k < d; ++k) {
+    if (mesh->n[k] < 1 || !(mesh->hi[k] > mesh->lo[k])) {
+      set_error("sbm_setup: mesh needs n >= 1 and hi > lo in every direction");
+      return SBM_EINVAL;
+    }
+  }
+  c->dim = d;
+  c->p = p;
+  c->n1 = p + 1;
+  c->disc = disc;
+  for (int k = 0; k < 3; ++k) {
+    c->n[k] = k < d ? mesh->n[k] : 1;
+    c->lo[k] = k < d ? mesh->lo[k] : 0.0;
+    c->hi[k] = k < d ? mesh->hi[k] : 1.0;
+  }
+  c->h = (c->hi[0] - c->lo[0]) / c->n[0];
+  for (int k = 1; k < d; ++k) {
+    const double hk = (c->hi[k] - c->lo[k]) / c->n[k];
+    if (std::fabs(hk - c->h) > 1e-12 * c->h) {
+      set_error("sbm_setup: cells must be isotropic (equal h in every direction)");
+      return SBM_EUNSUPPORTED;
+    }
+  }
+  c->gamma = (opts && opts->penalty_gamma > 0) ? opts->penalty_gamma : 10.0;
+  c->gamma_dg = (opts && opts->dg_penalty_gamma > 0) ? opts->dg_penalty_gamma : 10.0;
+  c->shift_scale = opts ? opts->shift_scale : 1.0;
+  c->sigma_gamma = c->gamma * p * p / c->h;
+  c->sigma_f = c->gamma_dg * p * p / c->h;
+
+  // level set
+  LevelSet &L = c->ls;
+  L.kind = ls->kind;
+  L.dim = d;
+  for (int k = 0; k < 3; ++k) {
+    L.centre[k] = ls->centre[k];
+    L.semi[k] = ls->semi_axes[k];
+    L.normal[k] = ls->normal[k];
+  }
+  L.radius = ls->radius;
+  L.R = ls->R;
+  L.r = ls->r;
+  L.offset = ls->offset;
+  switch (ls->kind) {
+    case SBM_LS_SPHERE:
+      if (!(ls->radius > 0)) {
+        set_error("sbm_setup: sphere radius must be > 0");
+        return SBM_EINVAL;
+      }
+      break;
+    case SBM_LS_ELLIPSOID:
+      for (int k = 0; k < d; ++k)
+        if (!(ls->semi_axes[k] > 0)) {
+          set_error("sbm_setup: ellipsoid semi-axes must be > 0");
+          return SBM_EINVAL;
+        }
+      break;
+    case SBM_LS_TORUS:
+      if (d != 3 || !(ls->r > 0) || !(ls->R > ls->r)) {
+        set_error("sbm_setup: torus needs dim 3 and R > r > 0");
+        return SBM_EINVAL;
+      }
+      break;
+    case SBM_LS_HALFSPACE: {
+      const double nn = norm_d(ls->normal, d);
+      if (!(std::fabs(nn - 1.0) < 1e-12)) {
+        set_error("sbm_setup: half-space normal must have unit length");
+        return SBM_EINVAL;
+      }
+      break;
+    }
+    case SBM_LS_SPHERE_UNION:
+      if (ls->n_spheres < 1 || !ls->centres || !ls->radii) {
+        set_error("sbm_setup: sphere union needs n_spheres >= 1 and centre/radius arrays");
+        return SBM_EINVAL;
+      }
+      L.cs.assign(3 * ls->n_spheres, 0.0);
+      L.rs.assign(ls->n_spheres, 0.0);
+      for (int i = 0; i < ls->n_spheres; ++i) {
+        for (int k = 0; k < d; ++k) L.cs[3 * i + k] = ls->centres[3 * i + k];
+        L.rs[i] = ls->radii[i];
+        if (!(L.rs[i] > 0)) {
+          set_error("sbm_setup: sphere radii must be > 0");
+          return SBM_EINVAL;
+        }
+      }
+      break;
+    default:
+      set_error("sbm_setup: unknown level-set kind");
+      return SBM_EINVAL;
+  }
+  c->rules = make_rules(p);
+  const Rules1D &R = c->rules;
+  const int n1 = p + 1;
+  c->nb = (d == 3) ? n1 * n1 * n1 : n1 * n1;
+  c->nq_face = (d == 3) ? n1 * n1 : n1;
+  const int np = c->nq_face;  // runs per cell = face points
+
+  // ---- vertex values and active cells (phi < 0 at all 2^d vertices) ----
+  const int64_t nx = c->n[0], ny = c->n[1], nz = (d == 3) ? c->n[2] : 1;
+  const int64_t vx = nx + 1, vy = ny + 1, vz = (d == 3) ? nz + 1 : 1;
+  std::vector<unsigned char> vin(vx * vy * vz);
+  for (int64_t k = 0; k < vz; ++k)
+    for (int64_t j = 0; j < vy; ++j)
+      for (int64_t i = 0; i < vx; ++i) {
+        double x[3] = {c->lo[0] + c->h * i, c->lo[1] + c->h * j, d == 3 ? c->lo[2] + c->h * k : 0.0};
+        vin[(k * vy + j) * vx + i] = L.phi(x) < 0.0;
+      }
+  std::vector<int32_t> rank(nx * ny * nz, -1);
+  c->cells.clear();
+  int64_t nc = 0;
+  for (int64_t k = 0; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        bool in = true;
+        for (int o = 0; o < (1 << d) && in; ++o) {
+          const int64_t ii = i + (o & 1), jj = j + ((o >> 1) & 1), kk = k + ((o >> 2) & 1);
+          in = vin[(kk * vy + jj) * vx + ii];
+        }
+        if (in) {
+          rank[(k * ny + j) * nx + i] = (int32_t)nc++;
+          c->cells.push_back((int32_t)i);
+          c->cells.push_back((int32_t)j);
+          if (d == 3) c->cells.push_back((int32_t)k);
+        }
+      }
+  c->n_cells = nc;
+
+  // ---- faces: neighbours, surrogate faces, interior-face count ----
+  c->nbr.assign(nc * 2 * d, -1);
+  c->faces.clear();
+  int64_t n_int = 0;
+  for (int64_t r = 0; r < nc; ++r) {
+    const int32_t *cc = &c->cells[r * d];
+    for (int a = 0; a < d; ++a)
+      for (int s = 0; s < 2; ++s) {
+        int64_t nbv[3] = {cc[0], cc[1], d == 3 ? cc[2] : 0};
+        nbv[a] += s ? 1 : -1;
+        int32_t nr = -1;
+        if (nbv[a] >= 0 && nbv[a] < c->n[a]) nr = rank[(nbv[2] * ny + nbv[1]) * nx + nbv[0]];
+        c->nbr[r * 2 * d + 2 * a + s] = nr;
+        if (nr < 0) {
+          c->faces.push_back((int32_t)r);
+          c->faces.push_back(a);
+          c->faces.push_back(s);
+        } else if (s == 1) {
+          ++n_int;
+        }
+      }
+  }
+  c->n_sbm = (int64_t)c->faces.size() / 3;
+  c->n_int = n_int;
+
+  // ---- face points: xi~ (face Gauss points), closest points, shifted xi ----
+  const int64_t nf = c->n_sbm;
+  c->face_xi.assign(nf * np * d, 0.0);
+  c->face_xtrue.assign(nf * np * d, 0.0);
+  for (int64_t f = 0; f < nf; ++f) {
+    const int32_t r = c->faces[3 * f], a = c->faces[3 * f + 1], s = c->faces[3 * f + 2];
+    const int32_t *cc = &c->cells[(int64_t)r * d];
+    for (int q = 0; q < np; ++q) {
+      double xt[3], xs[3], xx[3], cp[3];
+      int qq = q;
+      for (int k = 0; k < d; ++k) {
+        if (k == a) {
+          xt[k] = (double)s;
+        } else {
+          xt[k] = R.g[qq % n1];
+          qq /= n1;
+        }
+        xx[k] = c->lo[k] + c->h * ((double)cc[k] + xt[k]);
+      }
+      L.closest(xx, cp);
+      for (int k = 0; k < d; ++k) {
+        xs[k] = xt[k] + c->shift_scale * (cp[k] - xx[k]) / c->h;
+        c->face_xi[(f * np + q) * d + k] = xs[k];
+        c->face_xtrue[(f * np + q) * d + k] = cp[k];
+        if (!std::isfinite(xs[k])) {
+          set_error("sbm_setup: closest-point projection failed (degenerate level set?)");
+          return SBM_EINVAL;
+        }
+      }
+    }
+  }
+
+  // ---- DoF numbering ----
+  if (disc == SBM_CG) {
+    const int64_t lx = p * nx + 1, ly = p * ny + 1, lz = (d == 3) ? p * nz + 1 : 1;
+    std::vector<int32_t> id(lx * ly * lz, 0);
+    for (int64_t r = 0; r < nc; ++r) {
+      const int32_t *cc = &c->cells[r * d];
+      const int kz = (d == 3) ? n1 : 1;
+      for (int k = 0; k < kz; ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i) {
+            const int64_t m0 = (int64_t)p * cc[0] + i, m1 = (int64_t)p * cc[1] + j;
+            const int64_t m2 = (d == 3) ? (int64_t)p * cc[2] + k : 0;
+            id[(m2 * ly + m1) * lx + m0] = 1;
+          }
+    }
+    int64_t cnt = 0;
+    for (size_t m = 0; m < id.size(); ++m) {
+      if (id[m]) {
+        if (cnt >= (int64_t)std::numeric_limits<int32_t>::max()) {
+          set_error("sbm_setup: more than 2^31-1 DoFs");
+          return SBM_EUNSUPPORTED;
+        }
+        id[m] = (int32_t)cnt++;
+      } else {
+        id[m] = -1;
+      }
+    }
+    c->n_dofs = cnt;
+    c->runs.assign(nc * np, 0);
+    for (int64_t r = 0; r < nc; ++r) {
+      const int32_t *cc = &c->cells[r * d];
+      for (int t = 0; t < np; ++t) {
+        const int j = t % n1, k = (d == 3) ? t / n1 : 0;
+        const int64_t m0 = (int64_t)p * cc[0], m1 = (int64_t)p * cc[1] + j;
+        const int64_t m2 = (d == 3) ? (int64_t)p * cc[2] + k : 0;
+        c->runs[r * np + t] = id[(m2 * ly + m1) * lx + m0];
+      }
+    }
+  } else {
+    if (nc * (int64_t)c->nb >= (int64_t)std::numeric_limits<int32_t>::max()) {
+      set_error("sbm_setup: more than 2^31-1 DoFs");
+      return SBM_EUNSUPPORTED;
+    }
+    c->n_dofs = nc * c->nb;
+    c->runs.clear();
+  }
+  return SBM_OK;
+}
+
+extern "C" {
+
+const char *sbm_last_error(void) { return g_last_error.c_str(); }
+
+sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int disc,
+                     const sbm_options *opts, sbm_handle *out) {
+  if (!out) {
+    set_error("sbm_setup: NULL output handle");
+    return SBM_EINVAL;
+  }
+  *out = nullptr;
+  sbm_ctx *c = new (std::nothrow) sbm_ctx();
+  if (!c) {
+    set_error("sbm_setup: out of host memory");
+    return SBM_ENOMEM;
+  }
+  sbm_status st;
+  try {
+    st = host_setup(c, mesh, ls, p, disc, opts);
+  } catch (const std::bad_alloc &) {
+    set_error("sbm_setup: out of host memory");
+    st = SBM_ENOMEM;
+  }
+  if (st != SBM_OK) {
+    delete c;
+    return st;
+  }
+  if (opts && (opts->flags & SBM_SETUP_HOST_ONLY)) {
+    c->host_only = true;
+    *out = c;
+    return SBM_OK;
+  }
+  // ---- upload ----
+  std::vector<int32_t> fcell(c->n_sbm), fcode(c->n_sbm);
+  for (int64_t f = 0; f < c->n_sbm; ++f) {
+    fcell[f] = c->faces[3 * f];
+    fcode[f] = 2 * c->faces[3 * f + 1] + c->faces[3 * f + 2];
+  }
+  hipError_t e = hipSuccess;
+  size_t bytes = 0;
+  if (c->disc == SBM_CG) e = upload(&c->d_runs, c->runs, bytes);
+  if (e == hipSuccess && c->disc == SBM_DG) e = upload(&c->d_nbr, c->nbr, bytes);
+  if (e == hipSuccess) e = upload(&c->d_face_cell, fcell, bytes);
+  if (e == hipSuccess) e = upload(&c->d_face_code, fcode, bytes);
+  if (e == hipSuccess) e = upload(&c->d_face_xi, c->face_xi, bytes);
+  if (e != hipSuccess) {
+    set_error(std::string("sbm_setup: device upload failed: ") + hipGetErrorString(e));
+    free_device(c);
+    delete c;
+    return e == hipErrorOutOfMemory ? SBM_ENOMEM : SBM_EHIP;
+  }
+  c->device_bytes = bytes;
+  *out = c;
+  return SBM_OK;
+}
+
+sbm_status sbm_info(sbm_handle h, int64_t *n_dofs, int64_t *n_cells, int64_t *n_sbm_faces,
+                    int64_t *n_interior_faces, size_t *device_bytes) {
+  if (!h) {
+    set_error("sbm_info: NULL handle");
+    return SBM_EINVAL;
+  }
+  if (n_dofs) *n_dofs = h->n_dofs;
+  if (n_cells) *n_cells = h->n_cells;
+  if (n_sbm_faces) *n_sbm_faces = h->n_sbm;
+  if (n_interior_faces) *n_interior_faces = h->n_int;
+  if (device_bytes) *device_bytes = h->device_bytes;
+  return SBM_OK;
+}
+
+void sbm_destroy(sbm_handle h) {
+  if (!h) return;
+  if (!h->host_only) (void)hipDeviceSynchronize();
+  sbm::free_workspace(h);
+  free_device(h);
+  delete h;
+}
+
+sbm_status sbm_apply(sbm_handle h, const void *u, void *v, int prec, void *stream) {
+  if (!h) {
+    set_error("sbm_apply: NULL handle");
+    return SBM_EINVAL;
+  }
+  if (h->n_dofs == 0 && !h->host_only && (prec == SBM_F64 || prec == SBM_F32)) return SBM_OK;
+  if (!u || !v) {
+    set_error("sbm_apply: NULL vector");
+    return SBM_EINVAL;
+  }
+  if (h->host_only) {
+    set_error("sbm_apply: handle was set up with SBM_SETUP_HOST_ONLY");
+    return SBM_EINVAL;
+  }
+  if (u == v) {
+    set_error("sbm_apply: u and v must not alias");
+    return SBM_EINVAL;
+  }
+  if (prec != SBM_F64 && prec != SBM_F32) {
+    set_error("sbm_apply: prec must be SBM_F64 or SBM_F32");
+    return SBM_EINVAL;
+  }
+  SBM_HIP_CHECK(launch_apply(h, u, v, prec, SBM_PART_ALL, (hipStream_t)stream));
+  return SBM_OK;
+}
+
+sbm_status sbm_apply_parts(sbm_handle h, const void *u, void *v, int prec, int parts, void *stream) {
+  if (!h || h->host_only || (h->n_dofs > 0 && (!u || !v)) || (u == v && h->n_dofs > 0) ||
+      (prec != SBM_F64 && prec != SBM_F32) || (parts & ~SBM_PART_ALL)) {
+    set_error("sbm_apply_parts: invalid argument");
+    return SBM_EINVAL;
+  }
+  if (h->n_dofs == 0) return SBM_OK;
+  SBM_HIP_CHECK(launch_apply(h, u, v, prec, parts, (hipStream_t)stream));
+  return SBM_OK;
+}
+
+sbm_status sbm_dof_points(sbm_handle h, double *xyz) {
+  if (!h || !xyz) {
+    set_error("sbm_dof_points: NULL argument");
+    return SBM_EINVAL;
+  }
+  const int d = h->dim, n1 = h->n1, np = h->nq_face;
+  for (int64_t r = 0; r < h->n_cells; ++r) {
+    const int32_t *cc = &h->cells[r * d];
+    for (int t = 0; t < np; ++t) {
+      const int j = t % n1, k = (d == 3) ? t / n1 : 0;
+      for (int i = 0; i < n1; ++i) {
+        const int64_t dof = (h->disc == SBM_CG) ? (int64_t)h->runs[r * np + t] + i
+                                                : r * h->nb + (int64_t)n1 * t + i;
+        const int loc[3] = {i, j, k};
+        for (int m = 0; m < d; ++m) xyz[dof * d + m] = h->lo[m] + h->h * (cc[m] + h->rules.z[loc[m]]);
+      }
+    }
+  }
+  return SBM_OK;
+}
+
+sbm_status sbm_rhs_points(sbm_handle h, double *cell_qp, double *bdry_pts) {
+  if (!h) {
+    set_error("sbm_rhs_points: NULL handle");
+    return SBM_EINVAL;
+  }
+  const int d = h->dim, n1 = h->n1;
+  if (cell_qp) {
+    const int nq = h->nb;
+    for (int64_t r = 0; r < h->n_cells; ++r) {
+      const int32_t *cc = &h->cells[r * d];
+      for (int q = 0; q < nq; ++q) {
+        int qq = q;
+        for (int m = 0; m < d; ++m) {
+          cell_qp[(r * nq + q) * d + m] = h->lo[m] + h->h * (cc[m] + h->rules.g[qq % n1]);
+          qq /= n1;
+        }
+      }
+    }
+  }
+  if (bdry_pts) std::memcpy(bdry_pts, h->face_xtrue.data(), h->face_xtrue.size() * sizeof(double));
+  return SBM_OK;
+}
+
+sbm_status sbm_export_cells(sbm_handle h, int32_t *cells) {
+  if (!h || !cells) {
+    set_error("sbm_export_cells: NULL argument");
+    return SBM_EINVAL;
+  }
+  std::memcpy(cells, h->cells.data(), h->cells.size() * sizeof(int32_t));
+  return SBM_OK;
+}
+
+sbm_status sbm_export_sbm_faces(sbm_handle h, int32_t *faces) {
+  if (!h || !faces) {
+    set_error("sbm_export_sbm_faces: NULL argument");
+    return SBM_EINVAL;
+  }
+  std::memcpy(faces, h->faces.data(), h->faces.size() * sizeof(int32_t));
+  return SBM_OK;
+}
+
+sbm_status sbm_export_face_xi(sbm_handle h, double *xi) {
+  if (!h || !xi) {
+    set_error("sbm_export_face_xi: NULL argument");
+    return SBM_EINVAL;
+  }
+  std::memcpy(xi, h->face_xi.data(), h->face_xi.size() * sizeof(double));
+  return SBM_OK;
+}
+
+sbm_status sbm_export_cell_dofs(sbm_handle h, int64_t *dofs) {
+  if (!h || !dofs) {
+    set_error("sbm_export_cell_dofs: NULL argument");
+    return SBM_EINVAL;
+  }
+  const int n1 = h->n1, np = h->nq_face, nb = h->nb;
+  for (int64_t r = 0; r < h->n_cells; ++r)
+    for (int t = 0; t < np; ++t)
+      for (int i = 0; i < n1; ++i)
+        dofs[r * nb + (int64_t)n1 * t + i] = (h->disc == SBM_CG) ? (int64_t)h->runs[r * np + t] + i
+                                                                  : r * nb + (int64_t)n1 * t + i;
+  return SBM_OK;
+}
+
+size_t sbm_footprint_estimate(const sbm_mesh *mesh, int p, int disc, int64_t n_cells_hint,
+                              int64_t n_faces_hint) {
+  if (!mesh || p < 1 || p > kMaxP) return 0;
+  const int d = mesh->dim;
+  const int64_t n1 = p + 1;
+  const int64_t nb = (d == 3) ? n1 * n1 * n1 : n1 * n1;
+  const int64_t np = (d == 3) ? n1 * n1 : n1;
+  const int64_t nc = n_cells_hint;
+  const int64_t ndofs = (disc == SBM_CG) ? nc * (int64_t)std::pow((double)p, d) + 3 * np * nc / n1 : nc * nb;
+  size_t b = 0;
+  b += (disc == SBM_CG) ? 4 * nc * np : 4 * nc * 2 * d;
+  b += n_faces_hint * (8 + np * d * 8);
+  return b + (size_t)ndofs * 8;
+}
+
+}  // extern "C"

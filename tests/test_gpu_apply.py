@@ -1,0 +1,126 @@
+"""GPU parity of sbm_apply against the FP64 oracle (assembled matrix on small meshes,
+brute-force C apply at full size).  Bar: relative 2-norm error <= 1e-12 in FP64 and
+<= 5e-6 in FP32 (inputs rounded to FP32 once)."""
+
+import numpy as np
+import pytest
+
+from oracle import native
+from oracle import sbm_oracle as O
+from paper_2507_17053_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+sbm = pytest.importorskip("paper_2507_17053_amd.sbm")
+
+TOL = {torch.float64: 1e-12, torch.float32: 5e-6}
+
+UNION2 = {"kind": "sphere_union", "centres": np.array([[-0.3, 0.0], [0.35, 0.1], [0.0, 0.4]]),
+          "radii": np.array([0.5, 0.45, 0.3])}
+
+SMALL = [
+    (2, 16, inputs.sphere((0.05, -0.03), 0.7), 2),   # the 2D disk workload
+    (2, 13, inputs.ellipsoid((0.02, 0.01), (0.8, 0.45)), 1),
+    (2, 11, UNION2, 5),
+    (2, 9, inputs.sphere((0.05, -0.03), 0.7), 8),
+    (3, 9, inputs.sphere((0.0, 0.0, 0.0), 0.75), 4),
+    (3, 8, inputs.torus(0.55, 0.4), 3),
+    (3, 7, inputs.ellipsoid((0.0, 0.02, -0.01), (0.8, 0.6, 0.7)), 2),
+    (3, 16, inputs.sphere_union(1), 6),
+    (3, 5, inputs.halfspace((1.0, 0.0, 0.0), 0.3), 5),
+    (3, 6, inputs.sphere((0.0, 0.0, 0.0), 0.75), 1),
+    (3, 5, inputs.sphere((0.0, 0.0, 0.0), 0.75), 7),
+    (3, 5, inputs.sphere((0.0, 0.0, 0.0), 0.75), 8),
+]
+
+
+def _gpu_apply(op, u, dtype):
+    ud = torch.from_numpy(u).to("cuda").to(dtype)
+    vd = torch.full_like(ud, float("nan"))
+    op.apply(ud, vd)
+    torch.cuda.synchronize()
+    return vd.double().cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("disc", ["cg", "dg"])
+@pytest.mark.parametrize("d,n,ls,p", SMALL, ids=[f"{c[0]}d-n{c[1]}-{c[2]['kind']}-p{c[3]}" for c in SMALL])
+def test_apply_matches_assembled_oracle(d, n, ls, p, disc, dtype):
+    print(f"case d={d} n={n} ls={ls['kind']} p={p} disc={disc} dtype={dtype}", flush=True)
+    ref = O.setup(d, n, -1.0, 1.0, ls, p, disc=disc)
+    A = O.assemble(ref)
+    u = inputs.uniform_vector(ref.n_dofs, seed=0)
+    op = sbm.Operator(d, n, -1.0, 1.0, ls, p, disc=disc)
+    assert op.n_dofs == ref.n_dofs
+    v = _gpu_apply(op, u, dtype)
+    vref = A @ u
+    err = _rel(v, vref)
+    print(f"  rel err {err:.3e}", flush=True)
+    assert err <= TOL[dtype], err
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("disc,wname,over", [
+    ("cg", "sphere3d_q4", {}),
+    ("dg", "torus3d_dg", {"p": 3}),
+    ("dg", "torus3d_dg", {"p": 5}),
+    ("cg", "spheres3d_q6", {}),
+], ids=["sphere64-q4-cg", "torus32-q3-dg", "torus32-q5-dg", "spheres48-q6-cg"])
+def test_apply_full_size_matches_c_oracle(disc, wname, over, dtype):
+    """Full workload sizes, every output entry compared with the brute-force C oracle."""
+    native.build(force=False)
+    w = inputs.workload(wname, **over)
+    print(f"case {wname} {over} disc={disc} dtype={dtype}", flush=True)
+    ref = O.setup(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=disc)
+    u = inputs.uniform_vector(ref.n_dofs, seed=0)
+    vref = native.NativeApply(ref)(u)
+    op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=disc)
+    v = _gpu_apply(op, u, dtype)
+    err = _rel(v, vref)
+    print(f"  n_dofs {ref.n_dofs} rel err {err:.3e}", flush=True)
+    assert err <= TOL[dtype], err
+
+
+def test_apply_is_overwrite_and_repeatable():
+    """v is overwritten (not accumulated); two applies agree to rounding (atomics reorder sums)."""
+    op = sbm.Operator(3, 10, -1.0, 1.0, inputs.sphere((0, 0, 0), 0.75), 3)
+    u = torch.from_numpy(inputs.uniform_vector(op.n_dofs, seed=0)).cuda()
+    v1 = torch.full_like(u, 123.0)
+    v2 = torch.full_like(u, -7.0)
+    op.apply(u, v1)
+    op.apply(u, v2)
+    torch.cuda.synchronize()
+    assert (torch.linalg.norm(v1 - v2) / torch.linalg.norm(v1)).item() < 1e-14
+
+
+def test_empty_domain_apply():
+    """A level set that contains no whole cell gives an empty operator; apply is a no-op."""
+    op = sbm.Operator(3, 4, -1.0, 1.0, inputs.sphere((0, 0, 0), 0.2), 2)
+    assert op.n_dofs == 0 and op.n_cells == 0
+    u = torch.zeros(0, dtype=torch.float64, device="cuda")
+    v = torch.zeros(0, dtype=torch.float64, device="cuda")
+    op.apply(u, v)
+    torch.cuda.synchronize()
+
+
+def test_apply_rejects_aliasing():
+    op = sbm.Operator(2, 8, -1.0, 1.0, inputs.sphere((0, 0), 0.7), 2)
+    u = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    with pytest.raises(sbm.SbmError):
+        op.apply(u, u)
+
+
+def test_single_cell_domain():
+    """One active cell: every face is a surrogate face."""
+    ls = inputs.sphere((0.5, 0.5, 0.5), 0.9)
+    ref = O.setup(3, 2, -1.0, 1.0, ls, 3)
+    assert ref.cells.shape[0] == 1 and ref.sbm_faces.shape[0] == 6
+    op = sbm.Operator(3, 2, -1.0, 1.0, ls, 3)
+    u = inputs.uniform_vector(ref.n_dofs, seed=0)
+    v = _gpu_apply(op, u, torch.float64)
+    assert _rel(v, O.assemble(ref) @ u) <= 1e-12

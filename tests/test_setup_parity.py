@@ -1,0 +1,88 @@
+"""Setup parity (host side, no GPU): the library's active cells, surrogate faces and DoF
+maps must equal the oracle's exactly; shifted reference points agree to rounding."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import sbm_oracle as O
+from paper_2507_17053_amd import inputs
+
+sbm = pytest.importorskip("paper_2507_17053_amd.sbm", reason="libsbm.so not built")
+
+CASES = [
+    (2, 16, inputs.sphere((0.05, -0.03), 0.7), 2, "cg"),
+    (2, 12, inputs.ellipsoid((0.02, 0.01), (0.8, 0.45)), 3, "dg"),
+    (2, 14, {"kind": "sphere_union", "centres": np.array([[-0.3, 0.0], [0.35, 0.1], [0.0, 0.4]]),
+             "radii": np.array([0.5, 0.45, 0.3])}, 4, "cg"),
+    (3, 12, inputs.sphere((0.0, 0.0, 0.0), 0.75), 4, "cg"),
+    (3, 10, inputs.torus(0.6, 0.3), 3, "dg"),
+    (3, 10, inputs.ellipsoid((0.0, 0.02, -0.01), (0.8, 0.6, 0.7)), 2, "cg"),
+    (3, 12, inputs.sphere_union(1), 3, "cg"),
+    (3, 8, inputs.halfspace((1.0, 0.0, 0.0), 0.3), 2, "dg"),
+    (3, 16, inputs.sphere((0.0, 0.0, 0.0), 0.75), 1, "cg"),
+]
+
+
+@pytest.mark.parametrize("d,n,ls,p,disc", CASES)
+def test_setup_matches_oracle(d, n, ls, p, disc):
+    ref = O.setup(d, n, -1.0, 1.0, ls, p, disc=disc)
+    op = sbm.Operator(d, n, -1.0, 1.0, ls, p, disc=disc, host_only=True)
+    assert op.n_cells == ref.cells.shape[0]
+    assert op.n_dofs == ref.n_dofs
+    assert op.n_sbm_faces == ref.sbm_faces.shape[0]
+    assert op.n_interior_faces == ref.interior_faces.shape[0]
+    np.testing.assert_array_equal(op.export_cells(), ref.cells)
+    np.testing.assert_array_equal(op.export_sbm_faces(), ref.sbm_faces)
+    np.testing.assert_array_equal(op.export_cell_dofs(), ref.cell_dofs)
+    xi = op.export_face_xi()
+    assert np.abs(xi - ref.face_xi).max() <= 1e-12
+    np.testing.assert_allclose(op.dof_points(), O.dof_points(ref), atol=1e-15)
+    cq, bp = op.rhs_points()
+    np.testing.assert_allclose(bp, ref.face_x_true, atol=1e-13)
+
+
+def test_full_size_sphere_counts():
+    """Full 64^3 sphere workload: counts and maps equal the oracle's."""
+    w = inputs.workload("sphere3d_q4")
+    ref = O.setup(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"])
+    op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], host_only=True)
+    assert (op.n_cells, op.n_sbm_faces, op.n_dofs) == (52520, 10176, 3443241)
+    assert ref.n_dofs == op.n_dofs
+    np.testing.assert_array_equal(op.export_cell_dofs(), ref.cell_dofs)
+    assert np.abs(op.export_face_xi() - ref.face_xi).max() <= 1e-12
+
+
+@pytest.mark.parametrize("bad", ["p0", "p9", "dim4", "aniso", "radius"])
+def test_setup_rejects_bad_arguments(bad):
+    kw = dict(d=3, n=4, lo=-1.0, hi=1.0, levelset=inputs.sphere((0, 0, 0), 0.8), p=2)
+    if bad == "p0":
+        kw["p"] = 0
+    elif bad == "p9":
+        kw["p"] = 9
+    elif bad == "dim4":
+        kw["d"] = 4
+    elif bad == "aniso":
+        kw["n"] = [4, 4, 8]
+    elif bad == "radius":
+        kw["levelset"] = inputs.sphere((0, 0, 0), -1.0)
+    with pytest.raises((sbm.SbmError, IndexError)):
+        sbm.Operator(kw["d"], kw["n"], kw["lo"], kw["hi"], kw["levelset"], kw["p"], host_only=True)
+
+
+def test_host_only_handle_refuses_apply():
+    op = sbm.Operator(3, 4, -1.0, 1.0, inputs.sphere((0, 0, 0), 0.8), 2, host_only=True)
+    st = sbm._lib.sbm_apply(op.handle, ctypes.c_void_p(8), ctypes.c_void_p(16), 0, None)
+    assert st == sbm.SBM_EINVAL
+
+
+def test_library_exports_every_declared_symbol():
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "sbm.h")).read()
+    declared = set(re.findall(r"\b(sbm_[a-z_0-9]+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    for name in sorted(declared):
+        assert hasattr(sbm._lib, name), name
+    assert set(sbm.EXPORTED) <= declared
