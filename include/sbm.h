@@ -121,20 +121,33 @@ const char *sbm_last_error(void);
  * sbm_apply -- v = A u (Sec. 3.5 workflow: cell loop, then surrogate faces; for DG the
  * interior faces are evaluated cell by cell).  u and v are device vectors of n_dofs
  * entries of the precision prec (SBM_F64: double, SBM_F32: float); v is overwritten and
- * must not alias u.  Asynchronous on stream; never synchronises.
+ * must not alias u.  Asynchronous on stream; never synchronises.  A CG handle owns a
+ * scratch buffer used by every apply, so applies of the same handle must be ordered on
+ * one stream (applies of different handles may run concurrently).
  * Errors: EINVAL (NULL handle/pointer, u == v, bad prec), EHIP (launch failure).
  */
 sbm_status sbm_apply(sbm_handle h, const void *u, void *v, int prec, void *stream);
 
 /*
- * sbm_apply_parts -- diagnostic split of sbm_apply: runs only the launches selected in
- * parts (SBM_PART_ZERO: clear v (CG only); SBM_PART_CELLS: cell term, for DG including
- * the interior faces; SBM_PART_SBM_FACES: surrogate-boundary faces).  The parts
- * accumulate into v exactly as inside sbm_apply, so ZERO|CELLS|SBM_FACES == sbm_apply.
- * It exists to time the cell and surrogate-face work separately (the share of time spent
- * in surrogate faces, Sec. 4.3).  Same argument rules as sbm_apply.  Asynchronous.
+ * sbm_apply_parts -- diagnostic split of sbm_apply: v = (selected parts of A) u, with
+ * SBM_PART_CELLS the cell term (for DG including the interior faces) and
+ * SBM_PART_SBM_FACES the surrogate-boundary faces; SBM_PART_ALL gives sbm_apply.  For DG,
+ * SBM_PART_SBM_FACES alone adds the face term into v instead of overwriting it.  It exists
+ * to time the cell and surrogate-face work separately (the share of time spent in
+ * surrogate faces, Sec. 4.3).  Same argument rules as sbm_apply.  Asynchronous.
  */
-enum { SBM_PART_ZERO = 1, SBM_PART_CELLS = 2, SBM_PART_SBM_FACES = 4, SBM_PART_ALL = 7 };
+enum { SBM_PART_CELLS = 2, SBM_PART_SBM_FACES = 4, SBM_PART_ALL = 6,
+       SBM_PART_NO_ASSEMBLY = 8 /* CG: skip the final sum over brick-boundary DoFs (those
+                                   entries of v are then left unwritten): times the brick
+                                   kernel alone */ };
+
+/*
+ * sbm_layout_stats -- CG work decomposition (zeros for DG): number of bricks (blocks of
+ * background cells, one workgroup each), DoFs on brick boundaries (assembled by a second
+ * pass) and the slots that pass reads.  Any output pointer may be NULL.
+ */
+sbm_status sbm_layout_stats(sbm_handle h, int64_t *n_bricks, int64_t *n_boundary_dofs,
+                            int64_t *n_boundary_slots);
 sbm_status sbm_apply_parts(sbm_handle h, const void *u, void *v, int prec, int parts, void *stream);
 
 /*

@@ -1,25 +1,27 @@
 // Matrix-free SBM operator kernels for gfx950 (CDNA4, wave64).
 //
-//   cell_kernel     Laplace cell term on every active cell (Alg. 1), CG scatter by atomics
+//   brick_kernel    CG: one workgroup per brick of BX x BY x BZ background cells.  The
+//                   brick's active cells (Alg. 1) and its surrogate-boundary faces (Alg. 3)
+//                   are evaluated into an LDS copy of the brick's DoF lattice; points
+//                   strictly inside the brick are then stored to v directly, points on the
+//                   brick's boundary (shared with neighbouring bricks) are added atomically.
 //   dg_cell_kernel  DG: Laplace cell term plus the SIPG terms of the cell's interior faces,
-//                   evaluated cell by cell (Alg. 2 split per side), plain stores
-//   sbm_face_kernel surrogate-boundary faces (Alg. 3): normal derivative by sum
-//                   factorisation, E u by point evaluation at the shifted point, tested
-//                   against values and normal derivatives, atomics into v
+//                   evaluated cell by cell (Alg. 2 split per side); every cell writes only
+//                   its own block.
+//   sbm_face_kernel DG surrogate-boundary faces (Alg. 3), atomics into the cell blocks.
 //
-// Layout shared by all kernels: one "entity" (cell or face) is handled by NP = (p+1)^(d-1)
-// consecutive threads, EPB entities per workgroup.  Thread t of an entity owns one
-// pencil of p+1 values along a coordinate axis; the (p+1)^d tile of the cell lives in LDS.
-// The x-runs of a cell (p+1 consecutive DoFs along the first axis) are contiguous in
-// both numberings, so gathers and scatters read and write p+1 consecutive entries from a
-// per-run base index.
+// Work layout: an "entity" (cell or face) is handled by NP = (p+1)^(d-1) consecutive threads,
+// EPB entities at a time per workgroup.  Thread t of an entity owns one pencil of p+1
+// values along a coordinate axis; the (p+1)^d tile of the cell lives in LDS.  Within a
+// cell, the p+1 DoFs along the first axis (an "x-run") are consecutive in both
+// numberings, so gathers read p+1 consecutive entries from a per-run base index.
 //
 // Cell term in Kronecker-sum form: all active cells are translates of one reference cell
 // with Jacobian h I (Sec. 3.4), so the Gauss-point loop of Alg. 1 is a fixed diagonal
 // scaling and evaluate / quadrature / integrate collapse per axis into the 1D matrices
 //   M_ij = sum_q w_q l_i(g_q) l_j(g_q),   K_ij = sum_q w_q l'_i(g_q) l'_j(g_q)
 // (exact with p+1 Gauss points), A_K = h^(d-2) sum_k M x .. K(axis k) .. x M.  In 3D this
-// costs 7 one-dimensional sweeps instead of the 12 of the gradient form.
+// is 7 one-dimensional sweeps instead of the 12 of the gradient form.
 #include "sbm_internal.h"
 
 namespace sbm {
@@ -31,15 +33,27 @@ struct Shape {
   static constexpr int NB = NP * N1;
 };
 
-// Entities per workgroup: fill up to 256 threads, keep the static LDS below 64 KiB.
-template <typename T, int D, int N1, int NBUF>
+// Entities per workgroup: fill up to 256 threads, keep the static LDS below ~60 KB.
+template <typename T, int D, int N1, int NBUF, int EXTRA>
 constexpr int epb() {
   constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
   int e = 256 / NP;
   if (e < 1) e = 1;
-  while (e > 1 && (e * NBUF * NB + 4 * e * NP) * (int)sizeof(T) > 60000) --e;
+  while (e > 1 && (e * NBUF * NB + 4 * e * NP + EXTRA) * (int)sizeof(T) > 60000) --e;
   return e;
 }
+
+// Brick of background cells per CG workgroup, chosen per degree so that the LDS lattice
+// ((BX p + 1)(BY p + 1)(BZ p + 1) values) stays near 20 KB in FP64.
+template <int D, int P>
+struct BrickDims {
+  // 3D: p=1 8x8x8, p=2 8x4x4, p=3 4x4x4, p=4 4x4x2, p=5 4x2x2, p=6,7 2x2x2, p=8 2x2x1
+  // 2D: 8x8 up to p=2, 4x4 up to p=7, 3x3 for p=8 (a lattice row must fit 32 points)
+  static constexpr int BX = (D == 2) ? (P <= 2 ? 8 : (P <= 7 ? 4 : 3))
+                                     : (P <= 2 ? 8 : (P <= 5 ? 4 : 2));
+  static constexpr int BY = (D == 2) ? BX : (P == 1 ? 8 : (P <= 4 ? 4 : 2));
+  static constexpr int BZ = (D == 2) ? 1 : (P == 1 ? 8 : (P <= 3 ? 4 : (P <= 7 ? 2 : 1)));
+};
 
 // XCD-aware block order: the dispatcher hands block b to XCD (b mod 8), so give every XCD
 // one contiguous range of logical blocks; neighbouring cells then share that XCD's L2.
@@ -72,32 +86,15 @@ __device__ __forceinline__ void lagrange_at(const double (&z)[N1], const double 
 }
 
 // ------------------------------------------------------------------------------------
-// Cell term, Kronecker-sum sum factorisation.  CG: atomic scatter.  (DG uses dg_cell_kernel.)
+// Cell term for one entity.  x: thread t's input pencil along the last axis (3D: t =
+// i0 + N1 i1 holds u(i0, i1, k), k = 0..p; 2D: t = i0 holds u(i0, k)).  Returns in out
+// the p+1 outputs of x-run t (3D: t = i1 + N1 i2; 2D: t = i1).  A, B: this entity's
+// two (p+1)^d LDS tiles.  Contains barriers: every thread of the block must call it.
 // ------------------------------------------------------------------------------------
-template <typename T, int D, int N1, int EPB>
-__global__ __launch_bounds__(256) void cell_kernel(int n_cells, const int32_t *__restrict__ runs,
-                                                   const T *__restrict__ u, T *__restrict__ v,
-                                                   KTab<T, N1> tab, T scale) {
-  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
-  __shared__ T sa[EPB * NB];
-  __shared__ T sb[EPB * NB];
-  const int le = threadIdx.x / NP, t = threadIdx.x - le * NP;
-  const int cell = xcd_block() * EPB + le;
-  const bool act = cell < n_cells;
-  T *A = sa + le * NB;
-  T *B = sb + le * NB;
-
-  // phase 1: pencils along the last axis, gathered from global memory
-  T x[N1];
-  {
-    const int i0 = (D == 3) ? t % N1 : t;
-    const int r0 = (D == 3) ? t / N1 : 0;
-#pragma unroll
-    for (int k = 0; k < N1; ++k) {
-      const int run = (D == 3) ? r0 + N1 * k : k;
-      x[k] = act ? u[runs[(int64_t)cell * NP + run] + i0] : T(0);
-    }
-  }
+template <typename T, int D, int N1>
+__device__ __forceinline__ void kron_cell(const KTab<T, N1> &tab, int t, const T (&x)[N1], T *A, T *B, T scale,
+                                          T (&out)[N1]) {
+  constexpr int NP = Shape<D, N1>::NP;
 #pragma unroll
   for (int i = 0; i < N1; ++i) {
     T a = 0, b = 0;
@@ -111,7 +108,7 @@ __global__ __launch_bounds__(256) void cell_kernel(int n_cells, const int32_t *_
   }
   __syncthreads();
   if constexpr (D == 3) {
-    // phase 2: pencils along axis 1; c = M a, e = K a + M b
+    // pencils along axis 1; c = M a, e = K a + M b
     const int ix = t % N1, iz = t / N1;
     T a[N1], b[N1];
 #pragma unroll
@@ -133,22 +130,32 @@ __global__ __launch_bounds__(256) void cell_kernel(int n_cells, const int32_t *_
     }
     __syncthreads();
   }
-  // last phase: pencils along axis 0 (thread t = run index); out = K c + M e
+  // pencils along axis 0 (thread t = run index); out = K c + M e
   T c[N1], e[N1];
 #pragma unroll
   for (int j = 0; j < N1; ++j) {
     c[j] = A[j + N1 * t];
     e[j] = B[j + N1 * t];
   }
-  if (act) {
-    T *vp = v + runs[(int64_t)cell * NP + t];
 #pragma unroll
-    for (int i = 0; i < N1; ++i) {
-      T o = 0;
+  for (int i = 0; i < N1; ++i) {
+    T o = 0;
 #pragma unroll
-      for (int j = 0; j < N1; ++j) o += tab.K[i * N1 + j] * c[j] + tab.M[i * N1 + j] * e[j];
-      atomic_add(vp + i, scale * o);
-    }
+    for (int j = 0; j < N1; ++j) o += tab.K[i * N1 + j] * c[j] + tab.M[i * N1 + j] * e[j];
+    out[i] = scale * o;
+  }
+}
+
+// Thread t's input pencil (see kron_cell) gathered through the x-run bases of a CG cell.
+template <typename T, int D, int N1>
+__device__ __forceinline__ void gather_pencil(const int32_t *__restrict__ cell_runs, const T *__restrict__ u,
+                                              int t, bool act, T (&x)[N1]) {
+  const int i0 = (D == 3) ? t % N1 : t;
+  const int r0 = (D == 3) ? t / N1 : 0;
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    const int run = (D == 3) ? r0 + N1 * k : k;
+    x[k] = act ? u[cell_runs[run] + i0] : T(0);
   }
 }
 
@@ -163,8 +170,8 @@ struct FaceAxes {
     s = code & 1;
     Sa = (a == 0) ? 1 : (a == 1 ? N1 : N1 * N1);
     if (D == 3) {
-      Sb = (a == 0) ? N1 : 1;            // lower tangential axis
-      Sc = (a == 2) ? N1 : N1 * N1;      // upper tangential axis
+      Sb = (a == 0) ? N1 : 1;        // lower tangential axis
+      Sc = (a == 2) ? N1 : N1 * N1;  // upper tangential axis
     } else {
       Sb = (a == 0) ? N1 : 1;
       Sc = 0;
@@ -247,40 +254,20 @@ __device__ __forceinline__ void face_interpolate(const KTab<T, N1> &tab, int t, 
 }
 
 // ------------------------------------------------------------------------------------
-// Surrogate-boundary faces (Alg. 3).  One entity = one face of its active cell K.
+// One surrogate-boundary face (Alg. 3).  su: u_K in LDS (lexicographic), already synced.
+// Writes the face's contribution to all (p+1)^d local rows into sw.  xq: this face's
+// shifted reference points (NP x D doubles), used only when act.  Contains barriers.
+//   dn u   = (2s-1)/h d/dxi_a u at the face Gauss points (sum factorisation),
+//   E u    = u_K(xi_q), point evaluation with (p+1)^d terms per point,
+//   tested:  w_q (sigma E u - dn u) against v, -w_q E u against dn v.
 // ------------------------------------------------------------------------------------
-template <typename T, int D, int N1, int EPB, bool DG>
-__global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_t *__restrict__ face_cell,
-                                                       const int32_t *__restrict__ face_code,
-                                                       const double *__restrict__ face_xi,
-                                                       const int32_t *__restrict__ runs,
-                                                       const T *__restrict__ u, T *__restrict__ v,
-                                                       KTab<T, N1> tab, KScal sc) {
-  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, P = N1 - 1;
-  __shared__ T su_all[EPB * NB];
-  __shared__ T sw_all[EPB * NB];
-  __shared__ T f_all[4 * EPB * NP];
-  const int le = threadIdx.x / NP, t = threadIdx.x - le * NP;
-  const int f = xcd_block() * EPB + le;
-  const bool act = f < n_faces;
-  T *su = su_all + le * NB;
-  T *sw = sw_all + le * NB;
-  T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
-  const int cell = act ? face_cell[f] : 0;
-  const FaceAxes<D, N1> fa(act ? face_code[f] : 0);
+template <typename T, int D, int N1>
+__device__ __forceinline__ void sbm_face_eval(const KTab<T, N1> &tab, const KScal &sc, int t, bool act,
+                                              const FaceAxes<D, N1> &fa, const double *__restrict__ xq,
+                                              const T *su, T *sw, T *f1, T *f2, T *f3, T *f4) {
+  constexpr int NP = Shape<D, N1>::NP, P = N1 - 1;
   const T h = T(sc.h), sig = T(sc.sigma_gamma);
   const T sgn = fa.s ? T(1) : T(-1);
-
-  // gather u_K: thread t = run index
-  int64_t base = 0;
-  if (act) {
-    base = DG ? (int64_t)cell * NB + N1 * t : (int64_t)runs[(int64_t)cell * NP + t];
-#pragma unroll
-    for (int i = 0; i < N1; ++i) su[N1 * t + i] = u[base + i];
-  }
-  __syncthreads();
-
-  // normal derivative (reference, along axis a) at the face nodes t = jb + N1 jc
   const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
   const int node_off = jb * fa.Sb + jc * fa.Sc;
   {
@@ -295,14 +282,12 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
   face_interpolate<T, D, N1>(tab, t, f1, f2, f3, f4, dn, dn2);
   dn *= sgn / h;
 
-  // E u at the shifted point of Gauss point t (point evaluation, (p+1)^d terms)
-  T eu = 0;
-  T om = 0;
+  T eu = 0, om = 0;
   if (act) {
-    const double *xq = face_xi + ((int64_t)f * NP + t) * D;
+    const double *xp = xq + t * D;
     double l[D][N1];
 #pragma unroll
-    for (int k = 0; k < D; ++k) lagrange_at<N1>(tab.z, tab.cinv, xq[k], l[k]);
+    for (int k = 0; k < D; ++k) lagrange_at<N1>(tab.z, tab.cinv, xp[k], l[k]);
     T l0[N1], l1[N1];
 #pragma unroll
     for (int j = 0; j < N1; ++j) {
@@ -335,14 +320,165 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
     }
   }
   __syncthreads();  // f3/f4 reads of face_interpolate are done
-  f3[t] = om * (sig * eu - dn);   // tested against v
-  f4[t] = -om * eu * sgn / h;     // tested against the reference derivative along a
+  f3[t] = om * (sig * eu - dn);  // tested against v
+  f4[t] = -om * eu * sgn / h;    // tested against the reference derivative along a
   __syncthreads();
   T Rv, Rg;
   face_integrate<T, D, N1>(tab, t, f1, f2, f3, f4, Rv, Rg);
 #pragma unroll
   for (int ia = 0; ia < N1; ++ia)
     sw[ia * fa.Sa + node_off] = ((ia == fa.s * P) ? Rv : T(0)) + (fa.s ? tab.D1[ia] : tab.D0[ia]) * Rg;
+}
+
+// Brick description handed to the CG kernel.
+struct BrickArgs {
+  const int32_t *cell_off;   // n_bricks + 1
+  const int32_t *cells;      // active cell ranks, grouped by brick
+  const int32_t *cell_loc;   // lattice offset of each cell's corner inside its brick
+  const int32_t *face_off;   // n_bricks + 1
+  const int32_t *faces;      // surrogate-face indices, grouped by brick
+  const int32_t *face_loc;   // lattice offset of each face's cell inside its brick
+  const int32_t *row_base;   // n_bricks x rows: DoF id of the first globally present point
+  const uint32_t *row_gmask; // bit x: lattice point x of the row is a DoF
+  const uint32_t *row_bmask; // bit x: ... and is touched by an active cell of this brick
+  const int32_t *row_hbase;  // first halo slot of the row's brick-boundary points
+};
+
+// ------------------------------------------------------------------------------------
+// CG brick kernel
+// ------------------------------------------------------------------------------------
+template <typename T, int D, int N1, int EPB, bool FACES>
+__global__ __launch_bounds__(256) void brick_kernel(int brick0, BrickArgs br, const int32_t *__restrict__ runs,
+                                                    const int32_t *__restrict__ face_cell,
+                                                    const int32_t *__restrict__ face_code,
+                                                    const double *__restrict__ face_xi, const T *__restrict__ u,
+                                                    T *__restrict__ v, T *__restrict__ halo, KTab<T, N1> tab,
+                                                    KScal sc, T scale, int parts) {
+  constexpr int P = N1 - 1, NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
+  constexpr int BX = BrickDims<D, P>::BX, BY = BrickDims<D, P>::BY, BZ = BrickDims<D, P>::BZ;
+  constexpr int LX = BX * P + 1, LY = BY * P + 1, LZ = (D == 3) ? BZ * P + 1 : 1;
+  constexpr int NL = LX * LY * LZ, NROWS = LY * LZ;
+  static_assert(LX <= 32, "row masks hold 32 points");
+  __shared__ T acc[NL];
+  __shared__ T sa[EPB * NB];
+  __shared__ T sb[EPB * NB];
+  __shared__ T fbuf[FACES ? 4 * EPB * NP : 4];
+  const int brick = brick0 + xcd_block();
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int le = tid / NP, t = tid - le * NP;
+  T *A = sa + le * NB, *B = sb + le * NB;
+  T *f1 = fbuf + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
+  // lattice offset of thread t's x-run inside a cell tile
+  const int run_off = (D == 3) ? (t % N1) * LX + (t / N1) * LX * LY : t * LX;
+
+  for (int i = tid; i < NL; i += nthr) acc[i] = T(0);
+  __syncthreads();
+
+  if (parts & SBM_PART_CELLS) {
+    const int c0 = br.cell_off[brick], c1 = br.cell_off[brick + 1];
+    for (int b = c0; b < c1; b += EPB) {
+      const int idx = b + le;
+      const bool act = idx < c1;
+      const int cell = act ? br.cells[idx] : 0;
+      const int loc = act ? br.cell_loc[idx] : 0;
+      T x[N1], out[N1];
+      gather_pencil<T, D, N1>(runs + (int64_t)cell * NP, u, t, act, x);
+      kron_cell<T, D, N1>(tab, t, x, A, B, scale, out);
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < N1; ++i) atomicAdd(&acc[loc + run_off + i], out[i]);
+      }
+      __syncthreads();
+    }
+  }
+  if (FACES && (parts & SBM_PART_SBM_FACES)) {
+    const int f0 = br.face_off[brick], f1e = br.face_off[brick + 1];
+    for (int b = f0; b < f1e; b += EPB) {
+      const int idx = b + le;
+      const bool act = idx < f1e;
+      const int f = act ? br.faces[idx] : 0;
+      const int loc = act ? br.face_loc[idx] : 0;
+      const int cell = act ? face_cell[f] : 0;
+      const FaceAxes<D, N1> fa(act ? face_code[f] : 0);
+      if (act) {
+        const T *up = u + runs[(int64_t)cell * NP + t];
+#pragma unroll
+        for (int i = 0; i < N1; ++i) A[N1 * t + i] = up[i];
+      }
+      __syncthreads();
+      sbm_face_eval<T, D, N1>(tab, sc, t, act, fa, face_xi + (int64_t)f * NP * D, A, B, f1, f2, f3, f4);
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < N1; ++i) atomicAdd(&acc[loc + run_off + i], B[N1 * t + i]);
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  // write-out: lanes walk the lattice with x fastest, so stores are row-contiguous.
+  // Points strictly inside the brick box belong to this brick alone: final value.  Points
+  // on the box boundary go to their halo slot; halo_reduce_kernel adds the slots up.
+  const int64_t rb = (int64_t)brick * NROWS;
+  for (int pt = tid; pt < NL; pt += nthr) {
+    const int x = pt % LX, row = pt / LX;
+    const uint32_t bm = br.row_bmask[rb + row];
+    if (!((bm >> x) & 1u)) continue;
+    const uint32_t below = (1u << x) - 1u;
+    const int y = row % LY, z = row / LY;
+    const bool brow = y == 0 || y == LY - 1 || (D == 3 && (z == 0 || z == LZ - 1));
+    if (!brow && x > 0 && x < LX - 1) {
+      const uint32_t gm = br.row_gmask[rb + row];
+      v[br.row_base[rb + row] + __popc(gm & below)] = acc[pt];
+    } else {
+      const uint32_t hm = brow ? bm : (bm & (1u | (1u << (LX - 1))));
+      halo[br.row_hbase[rb + row] + __popc(hm & below)] = acc[pt];
+    }
+  }
+}
+
+// v[dof] = sum of the dof's halo slots, in increasing slot order (deterministic).
+template <typename T>
+__global__ __launch_bounds__(256) void halo_reduce_kernel(int n, const int32_t *__restrict__ dof,
+                                                          const int32_t *__restrict__ off,
+                                                          const int32_t *__restrict__ slot,
+                                                          const T *__restrict__ halo, T *__restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+  for (int j = off[i]; j < off[i + 1]; ++j) s += halo[slot[j]];
+  v[dof[i]] = s;
+}
+
+// ------------------------------------------------------------------------------------
+// DG surrogate-boundary faces: one entity = one face; atomics into the cell block.
+// ------------------------------------------------------------------------------------
+template <typename T, int D, int N1, int EPB>
+__global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_t *__restrict__ face_cell,
+                                                       const int32_t *__restrict__ face_code,
+                                                       const double *__restrict__ face_xi,
+                                                       const T *__restrict__ u, T *__restrict__ v,
+                                                       KTab<T, N1> tab, KScal sc) {
+  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
+  __shared__ T su_all[EPB * NB];
+  __shared__ T sw_all[EPB * NB];
+  __shared__ T f_all[4 * EPB * NP];
+  const int le = threadIdx.x / NP, t = threadIdx.x - le * NP;
+  const int f = xcd_block() * EPB + le;
+  const bool act = f < n_faces;
+  T *su = su_all + le * NB;
+  T *sw = sw_all + le * NB;
+  T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
+  const int cell = act ? face_cell[f] : 0;
+  const FaceAxes<D, N1> fa(act ? face_code[f] : 0);
+  const int64_t base = (int64_t)cell * NB + N1 * t;
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < N1; ++i) su[N1 * t + i] = u[base + i];
+  }
+  __syncthreads();
+  sbm_face_eval<T, D, N1>(tab, sc, t, act, fa, face_xi + (int64_t)(act ? f : 0) * NP * D, su, sw, f1, f2, f3,
+                          f4);
   __syncthreads();
   if (act) {
 #pragma unroll
@@ -375,67 +511,20 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
   T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
   const T h = T(sc.h), sigf = T(sc.sigma_f);
 
-  // gather own block (contiguous), thread t = run
+  // own block (contiguous), thread t = run
   if (act) {
     const T *up = u + (int64_t)cell * NB + N1 * t;
 #pragma unroll
     for (int i = 0; i < N1; ++i) su[N1 * t + i] = up[i];
   }
   __syncthreads();
-  // ---- volume term (Kronecker sum), same sweeps as cell_kernel, input from LDS ----
   {
-    T x[N1];
+    T x[N1], out[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) x[k] = su[t + NP * k];
+    kron_cell<T, D, N1>(tab, t, x, A, B, scale, out);
 #pragma unroll
-    for (int i = 0; i < N1; ++i) {
-      T a = 0, b = 0;
-#pragma unroll
-      for (int j = 0; j < N1; ++j) {
-        a += tab.M[i * N1 + j] * x[j];
-        b += tab.K[i * N1 + j] * x[j];
-      }
-      A[t + NP * i] = a;
-      B[t + NP * i] = b;
-    }
-  }
-  __syncthreads();
-  if constexpr (D == 3) {
-    const int ix = t % N1, iz = t / N1;
-    T a[N1], b[N1];
-#pragma unroll
-    for (int j = 0; j < N1; ++j) {
-      a[j] = A[ix + N1 * j + NP * iz];
-      b[j] = B[ix + N1 * j + NP * iz];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < N1; ++i) {
-      T c = 0, e = 0;
-#pragma unroll
-      for (int j = 0; j < N1; ++j) {
-        c += tab.M[i * N1 + j] * a[j];
-        e += tab.K[i * N1 + j] * a[j] + tab.M[i * N1 + j] * b[j];
-      }
-      A[ix + N1 * i + NP * iz] = c;
-      B[ix + N1 * i + NP * iz] = e;
-    }
-    __syncthreads();
-  }
-  {
-    T c[N1], e[N1];
-#pragma unroll
-    for (int j = 0; j < N1; ++j) {
-      c[j] = A[j + N1 * t];
-      e[j] = B[j + N1 * t];
-    }
-#pragma unroll
-    for (int i = 0; i < N1; ++i) {
-      T o = 0;
-#pragma unroll
-      for (int j = 0; j < N1; ++j) o += tab.K[i * N1 + j] * c[j] + tab.M[i * N1 + j] * e[j];
-      sw[N1 * t + i] = scale * o;
-    }
+    for (int i = 0; i < N1; ++i) sw[N1 * t + i] = out[i];
   }
   // ---- interior faces ----
   const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
@@ -461,8 +550,8 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
       }
       const T uK = su[fa.s * P * fa.Sa + node_off];
       const T uN = A[(1 - fa.s) * P * fa.Sa + node_off];
-      f1[t] = uK - uN;                          // [u]_K at the face nodes
-      f2[t] = T(0.5) * sgn * (dK + dN) / h;     // {du/dn_K} at the face nodes
+      f1[t] = uK - uN;                       // [u]_K at the face nodes
+      f2[t] = T(0.5) * sgn * (dK + dN) / h;  // {du/dn_K} at the face nodes
     }
     __syncthreads();
     T jq, aq;
@@ -518,30 +607,37 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
   const T scale = T(D == 3 ? c->h : 1.0);
   const int nc = (int)c->n_cells, nf = (int)c->n_sbm;
   if (c->disc == SBM_CG) {
-    if (parts & SBM_PART_ZERO) {
-      hipError_t e = vec_fill(v, c->n_dofs, 0.0, sizeof(T) == 8 ? SBM_F64 : SBM_F32, s);
-      if (e != hipSuccess) return e;
-    }
-    if (nc > 0 && (parts & SBM_PART_CELLS)) {
-      constexpr int E = epb<T, D, N1, 2>();
-      hipLaunchKernelGGL((cell_kernel<T, D, N1, E>), dim3((nc + E - 1) / E), dim3(E * NP), 0, s, nc,
-                         c->d_runs, u, v, tab, scale);
-    }
-    if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
-      constexpr int E = epb<T, D, N1, 2>();
-      hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E, false>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s,
-                         nf, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, v, tab, sc);
+    if (c->n_bricks > 0 && (parts & (SBM_PART_CELLS | SBM_PART_SBM_FACES))) {
+      constexpr int P = N1 - 1;
+      constexpr int NL = (BrickDims<D, P>::BX * P + 1) * (BrickDims<D, P>::BY * P + 1) *
+                         ((D == 3) ? BrickDims<D, P>::BZ * P + 1 : 1);
+      constexpr int E = epb<T, D, N1, 2, NL>();
+      const BrickArgs br{c->d_brick_cell_off, c->d_brick_cells,    c->d_brick_cell_loc,
+                         c->d_brick_face_off, c->d_brick_faces,    c->d_brick_face_loc,
+                         c->d_row_base,       c->d_row_gmask,      c->d_row_bmask,
+                         c->d_row_hbase};
+      T *halo = (T *)c->d_halo;
+      // one launch over all bricks (splitting face-free bricks into a leaner launch
+      // serialises the two halves and measured slower)
+      hipLaunchKernelGGL((brick_kernel<T, D, N1, E, true>), dim3((unsigned)c->n_bricks), dim3(E * NP), 0, s, 0, br,
+                         c->d_runs, c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, halo, tab, sc, scale,
+                         parts);
+      if (c->n_halo_dofs > 0 && !(parts & SBM_PART_NO_ASSEMBLY)) {
+        const int nh = (int)c->n_halo_dofs;
+        hipLaunchKernelGGL(halo_reduce_kernel<T>, dim3((nh + 255) / 256), dim3(256), 0, s, nh, c->d_halo_dof,
+                           c->d_halo_off, c->d_halo_slot, (const T *)halo, v);
+      }
     }
   } else {
     if (nc > 0 && (parts & SBM_PART_CELLS)) {
-      constexpr int E = epb<T, D, N1, 4>();
+      constexpr int E = epb<T, D, N1, 4, 0>();
       hipLaunchKernelGGL((dg_cell_kernel<T, D, N1, E>), dim3((nc + E - 1) / E), dim3(E * NP), 0, s, nc,
                          c->d_nbr, u, v, tab, sc, scale);
     }
     if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
-      constexpr int E = epb<T, D, N1, 2>();
-      hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E, true>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s,
-                         nf, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, v, tab, sc);
+      constexpr int E = epb<T, D, N1, 2, 0>();
+      hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s, nf,
+                         c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
     }
   }
   return hipGetLastError();
@@ -563,6 +659,20 @@ hipError_t apply_dim(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t 
 }
 
 }  // namespace
+
+void brick_dims(int dim, int p, int *bx, int *by, int *bz) {
+#define SBM_BD(D_, P_)                  \
+  if (dim == D_ && p == P_) {           \
+    *bx = BrickDims<D_, P_>::BX;        \
+    *by = BrickDims<D_, P_>::BY;        \
+    *bz = BrickDims<D_, P_>::BZ;        \
+    return;                             \
+  }
+  SBM_BD(2, 1) SBM_BD(2, 2) SBM_BD(2, 3) SBM_BD(2, 4) SBM_BD(2, 5) SBM_BD(2, 6) SBM_BD(2, 7) SBM_BD(2, 8)
+  SBM_BD(3, 1) SBM_BD(3, 2) SBM_BD(3, 3) SBM_BD(3, 4) SBM_BD(3, 5) SBM_BD(3, 6) SBM_BD(3, 7) SBM_BD(3, 8)
+#undef SBM_BD
+  *bx = *by = *bz = 1;
+}
 
 hipError_t launch_apply(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s) {
   if (prec == SBM_F64) {

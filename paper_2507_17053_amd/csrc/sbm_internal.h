@@ -86,6 +86,23 @@ struct sbm_ctx {
   std::vector<double> face_xtrue;  // n_sbm x nq x dim
   std::vector<int32_t> runs;       // CG: n_cells x (p+1)^(d-1) first DoF of each x-run
   std::vector<int32_t> nbr;        // n_cells x 2d neighbour rank or -1
+  // CG bricks: BX x BY x BZ blocks of background cells, one workgroup each
+  int brick[3] = {1, 1, 1};
+  int64_t n_bricks = 0;
+  int64_t n_bricks_plain = 0;  // bricks [0, n_bricks_plain) have no surrogate faces
+  std::vector<int32_t> brick_cell_off, brick_cells, brick_cell_loc;
+  std::vector<int32_t> brick_face_off, brick_faces, brick_face_loc;
+  std::vector<int32_t> row_base, row_hbase;
+  std::vector<uint32_t> row_gmask, row_bmask;
+  // halo assembly: DoFs on brick boundaries collect one slot per touching brick
+  int64_t n_halo_slots = 0, n_halo_dofs = 0;
+  std::vector<int32_t> halo_dof, halo_off, halo_slot;
+  int32_t *d_row_hbase = nullptr, *d_halo_dof = nullptr, *d_halo_off = nullptr, *d_halo_slot = nullptr;
+  void *d_halo = nullptr;  // n_halo_slots doubles (also used as floats); per-handle scratch
+  int32_t *d_brick_cell_off = nullptr, *d_brick_cells = nullptr, *d_brick_cell_loc = nullptr;
+  int32_t *d_brick_face_off = nullptr, *d_brick_faces = nullptr, *d_brick_face_loc = nullptr;
+  int32_t *d_row_base = nullptr;
+  uint32_t *d_row_gmask = nullptr, *d_row_bmask = nullptr;
   // device copies
   int32_t *d_runs = nullptr;       // CG
   int32_t *d_nbr = nullptr;        // DG
@@ -103,6 +120,8 @@ void set_error(const std::string &msg);
 // Launchers (kernels.hip).  All asynchronous on stream.
 hipError_t launch_apply(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s);
 hipError_t launch_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s);
+// Brick shape (cells per direction) used by the CG kernel for (dim, p).
+void brick_dims(int dim, int p, int *bx, int *by, int *bz);
 // Vector kernels (vec.hip)
 hipError_t vec_fill(void *x, int64_t n, double val, int prec, hipStream_t s);
 }  // namespace sbm

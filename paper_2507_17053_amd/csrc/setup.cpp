@@ -1,6 +1,7 @@
 // Host-side setup of the SBM operator (Sec. 2 surrogate domain, Sec. 2.1 closest-point
 // shifts, Sec. 3.4 per-face data) and the C-ABI entry points that do not launch kernels.
 #include <algorithm>
+#include <utility>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -409,14 +410,195 @@ static hipError_t upload(V **dst, const std::vector<V> &src, size_t &bytes) {
   return hipMemcpy(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice);
 }
 
+template <typename V>
+static void free_ptr(V *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
 static void free_device(sbm_ctx *c) {
-  if (c->d_runs) (void)hipFree(c->d_runs);
-  if (c->d_nbr) (void)hipFree(c->d_nbr);
-  if (c->d_face_cell) (void)hipFree(c->d_face_cell);
-  if (c->d_face_code) (void)hipFree(c->d_face_code);
-  if (c->d_face_xi) (void)hipFree(c->d_face_xi);
-  c->d_runs = c->d_nbr = c->d_face_cell = c->d_face_code = nullptr;
-  c->d_face_xi = nullptr;
+  free_ptr(c->d_runs);
+  free_ptr(c->d_nbr);
+  free_ptr(c->d_face_cell);
+  free_ptr(c->d_face_code);
+  free_ptr(c->d_face_xi);
+  free_ptr(c->d_brick_cell_off);
+  free_ptr(c->d_brick_cells);
+  free_ptr(c->d_brick_cell_loc);
+  free_ptr(c->d_brick_face_off);
+  free_ptr(c->d_brick_faces);
+  free_ptr(c->d_brick_face_loc);
+  free_ptr(c->d_row_base);
+  free_ptr(c->d_row_gmask);
+  free_ptr(c->d_row_bmask);
+  free_ptr(c->d_row_hbase);
+  free_ptr(c->d_halo_dof);
+  free_ptr(c->d_halo_off);
+  free_ptr(c->d_halo_slot);
+  free_ptr(c->d_halo);
+}
+
+// CG bricks: group the active cells into blocks of BX x BY x BZ background cells (one
+// workgroup each), list each brick's cells and surrogate faces, and describe every
+// lattice row of the brick box by (id of its first DoF, mask of points that are DoFs,
+// mask of points touched by the brick's own cells).  id: global lattice -> DoF id or -1.
+static void build_bricks(sbm_ctx *c, const std::vector<int32_t> &id, int64_t lx, int64_t ly, int64_t lz) {
+  const int d = c->dim, p = c->p;
+  int BX, BY, BZ;
+  brick_dims(d, p, &BX, &BY, &BZ);
+  if (d == 2) BZ = 1;
+  c->brick[0] = BX;
+  c->brick[1] = BY;
+  c->brick[2] = BZ;
+  const int LX = BX * p + 1, LY = BY * p + 1, LZ = (d == 3) ? BZ * p + 1 : 1;
+  const int nrows = LY * LZ;
+  const int64_t nbx = (c->n[0] + BX - 1) / BX, nby = (c->n[1] + BY - 1) / BY;
+  const int64_t nbz = (d == 3) ? (c->n[2] + BZ - 1) / BZ : 1;
+  const int64_t nc = c->n_cells;
+  std::vector<int64_t> bkey(nc);
+  std::vector<int32_t> count(nbx * nby * nbz, 0);
+  for (int64_t r = 0; r < nc; ++r) {
+    const int32_t *cc = &c->cells[r * d];
+    const int64_t bz = (d == 3) ? cc[2] / BZ : 0;
+    bkey[r] = (bz * nby + cc[1] / BY) * nbx + cc[0] / BX;
+    ++count[bkey[r]];
+  }
+  // Bricks without surrogate faces are numbered first (lexicographic), then those with
+  // faces, so that each group runs as its own specialised launch.
+  std::vector<int32_t> fcount(count.size(), 0);
+  for (int64_t f = 0; f < c->n_sbm; ++f) ++fcount[bkey[c->faces[3 * f]]];
+  std::vector<int32_t> bid(count.size(), -1);
+  std::vector<int64_t> key_of;
+  int32_t nb = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (size_t k = 0; k < count.size(); ++k)
+      if (count[k] > 0 && ((fcount[k] > 0) == (pass == 1))) {
+        bid[k] = nb++;
+        key_of.push_back((int64_t)k);
+      }
+  c->n_bricks = nb;
+  c->n_bricks_plain = 0;
+  for (size_t k = 0; k < count.size(); ++k)
+    if (count[k] > 0 && fcount[k] == 0) ++c->n_bricks_plain;
+  auto cell_loc = [&](int64_t r, int64_t key) {
+    const int32_t *cc = &c->cells[r * d];
+    const int64_t bx = key % nbx, by = (key / nbx) % nby, bz = key / (nbx * nby);
+    const int64_t ox = cc[0] - bx * BX, oy = cc[1] - by * BY, oz = (d == 3) ? cc[2] - bz * BZ : 0;
+    return (int32_t)(ox * p + oy * p * LX + oz * p * LX * LY);
+  };
+  c->brick_cell_off.assign(nb + 1, 0);
+  for (int64_t r = 0; r < nc; ++r) ++c->brick_cell_off[bid[bkey[r]] + 1];
+  for (int32_t b = 0; b < nb; ++b) c->brick_cell_off[b + 1] += c->brick_cell_off[b];
+  c->brick_cells.assign(nc, 0);
+  c->brick_cell_loc.assign(nc, 0);
+  {
+    std::vector<int32_t> fill(c->brick_cell_off.begin(), c->brick_cell_off.end() - 1);
+    for (int64_t r = 0; r < nc; ++r) {
+      const int32_t b = bid[bkey[r]];
+      c->brick_cells[fill[b]] = (int32_t)r;
+      c->brick_cell_loc[fill[b]] = cell_loc(r, bkey[r]);
+      ++fill[b];
+    }
+  }
+  const int64_t nf = c->n_sbm;
+  c->brick_face_off.assign(nb + 1, 0);
+  for (int64_t f = 0; f < nf; ++f) ++c->brick_face_off[bid[bkey[c->faces[3 * f]]] + 1];
+  for (int32_t b = 0; b < nb; ++b) c->brick_face_off[b + 1] += c->brick_face_off[b];
+  c->brick_faces.assign(nf, 0);
+  c->brick_face_loc.assign(nf, 0);
+  {
+    std::vector<int32_t> fill(c->brick_face_off.begin(), c->brick_face_off.end() - 1);
+    for (int64_t f = 0; f < nf; ++f) {
+      const int64_t r = c->faces[3 * f];
+      const int32_t b = bid[bkey[r]];
+      c->brick_faces[fill[b]] = (int32_t)f;
+      c->brick_face_loc[fill[b]] = cell_loc(r, bkey[r]);
+      ++fill[b];
+    }
+  }
+  c->row_base.assign((size_t)nb * nrows, 0);
+  c->row_gmask.assign((size_t)nb * nrows, 0u);
+  c->row_bmask.assign((size_t)nb * nrows, 0u);
+  std::vector<unsigned char> touched(LX * LY * LZ);
+  const int n1 = p + 1;
+  for (int32_t b = 0; b < nb; ++b) {
+    const int64_t key = key_of[b];
+    const int64_t bx = key % nbx, by = (key / nbx) % nby, bz = key / (nbx * nby);
+    std::fill(touched.begin(), touched.end(), 0);
+    for (int32_t i = c->brick_cell_off[b]; i < c->brick_cell_off[b + 1]; ++i) {
+      const int32_t loc = c->brick_cell_loc[i];
+      for (int k = 0; k < ((d == 3) ? n1 : 1); ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int ii = 0; ii < n1; ++ii) touched[loc + ii + j * LX + k * LX * LY] = 1;
+    }
+    for (int z = 0; z < LZ; ++z)
+      for (int y = 0; y < LY; ++y) {
+        const int row = y + LY * z;
+        const int64_t X0 = bx * BX * p, Y = by * BY * p + y, Z = (d == 3) ? bz * BZ * p + z : 0;
+        uint32_t gm = 0, bm = 0;
+        int32_t base = 0;
+        bool first = true;
+        if (Y < ly && Z < lz) {
+          for (int x = 0; x < LX; ++x) {
+            const int64_t X = X0 + x;
+            if (X >= lx) break;
+            const int32_t g = id[(Z * ly + Y) * lx + X];
+            if (g < 0) continue;
+            gm |= 1u << x;
+            if (first) {
+              base = g;
+              first = false;
+            }
+            if (touched[x + LX * (y + LY * z)]) bm |= 1u << x;
+          }
+        }
+        c->row_base[(size_t)b * nrows + row] = base;
+        c->row_gmask[(size_t)b * nrows + row] = gm;
+        c->row_bmask[(size_t)b * nrows + row] = bm;
+      }
+  }
+  // Halo slots: every touched point on a brick's boundary gets one slot, numbered brick
+  // by brick in row order (z, y) and x within the row; the kernel recomputes the slot from
+  // row_hbase and the row's boundary mask.  The reduction lists, per DoF, its slots in
+  // increasing slot order (a fixed summation order).
+  c->row_hbase.assign((size_t)nb * nrows, 0);
+  std::vector<std::pair<int32_t, int32_t>> pairs;  // (dof, slot)
+  int64_t slot = 0;
+  for (int32_t b = 0; b < nb; ++b)
+    for (int z = 0; z < LZ; ++z)
+      for (int y = 0; y < LY; ++y) {
+        const int row = y + LY * z;
+        const size_t ri = (size_t)b * nrows + row;
+        c->row_hbase[ri] = (int32_t)slot;
+        const bool brow = (y == 0 || y == LY - 1 || (d == 3 && (z == 0 || z == LZ - 1)));
+        const uint32_t bm = c->row_bmask[ri], gm = c->row_gmask[ri];
+        const uint32_t edge = 1u | (1u << (LX - 1));
+        const uint32_t hm = brow ? bm : (bm & edge);
+        for (int x = 0; x < LX; ++x) {
+          if (!((hm >> x) & 1u)) continue;
+          const uint32_t below = gm & ((1u << x) - 1u);
+          const int32_t dof = c->row_base[ri] + __builtin_popcount(below);
+          pairs.emplace_back(dof, (int32_t)slot);
+          ++slot;
+        }
+      }
+  c->n_halo_slots = slot;
+  std::stable_sort(pairs.begin(), pairs.end(),
+                   [](const std::pair<int32_t, int32_t> &a, const std::pair<int32_t, int32_t> &b) {
+                     return a.first < b.first;
+                   });
+  c->halo_dof.clear();
+  c->halo_off.assign(1, 0);
+  c->halo_slot.resize(pairs.size());
+  for (size_t i = 0; i < pairs.size(); ++i) {
+    if (i == 0 || pairs[i].first != pairs[i - 1].first) {
+      if (i > 0) c->halo_off.push_back((int32_t)i);
+      c->halo_dof.push_back(pairs[i].first);
+    }
+    c->halo_slot[i] = pairs[i].second;
+  }
+  if (!pairs.empty()) c->halo_off.push_back((int32_t)pairs.size());
+  c->n_halo_dofs = (int64_t)c->halo_dof.size();
 }
 
 namespace sbm {
@@ -665,6 +847,7 @@ static sbm_status host_setup(sbm_ctx *c, const sbm_mesh *mesh, const sbm_levelse
         c->runs[r * np + t] = id[(m2 * ly + m1) * lx + m0];
       }
     }
+    build_bricks(c, id, lx, ly, lz);
   } else {
     if (nc * (int64_t)c->nb >= (int64_t)std::numeric_limits<int32_t>::max()) {
       set_error("sbm_setup: more than 2^31-1 DoFs");
@@ -716,7 +899,26 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
   }
   hipError_t e = hipSuccess;
   size_t bytes = 0;
-  if (c->disc == SBM_CG) e = upload(&c->d_runs, c->runs, bytes);
+  if (c->disc == SBM_CG) {
+    e = upload(&c->d_runs, c->runs, bytes);
+    if (e == hipSuccess) e = upload(&c->d_brick_cell_off, c->brick_cell_off, bytes);
+    if (e == hipSuccess) e = upload(&c->d_brick_cells, c->brick_cells, bytes);
+    if (e == hipSuccess) e = upload(&c->d_brick_cell_loc, c->brick_cell_loc, bytes);
+    if (e == hipSuccess) e = upload(&c->d_brick_face_off, c->brick_face_off, bytes);
+    if (e == hipSuccess) e = upload(&c->d_brick_faces, c->brick_faces, bytes);
+    if (e == hipSuccess) e = upload(&c->d_brick_face_loc, c->brick_face_loc, bytes);
+    if (e == hipSuccess) e = upload(&c->d_row_base, c->row_base, bytes);
+    if (e == hipSuccess) e = upload(&c->d_row_gmask, c->row_gmask, bytes);
+    if (e == hipSuccess) e = upload(&c->d_row_bmask, c->row_bmask, bytes);
+    if (e == hipSuccess) e = upload(&c->d_row_hbase, c->row_hbase, bytes);
+    if (e == hipSuccess) e = upload(&c->d_halo_dof, c->halo_dof, bytes);
+    if (e == hipSuccess) e = upload(&c->d_halo_off, c->halo_off, bytes);
+    if (e == hipSuccess) e = upload(&c->d_halo_slot, c->halo_slot, bytes);
+    if (e == hipSuccess && c->n_halo_slots > 0) {
+      e = hipMalloc(&c->d_halo, (size_t)c->n_halo_slots * sizeof(double));
+      bytes += (size_t)c->n_halo_slots * sizeof(double);
+    }
+  }
   if (e == hipSuccess && c->disc == SBM_DG) e = upload(&c->d_nbr, c->nbr, bytes);
   if (e == hipSuccess) e = upload(&c->d_face_cell, fcell, bytes);
   if (e == hipSuccess) e = upload(&c->d_face_code, fcode, bytes);
@@ -782,12 +984,24 @@ sbm_status sbm_apply(sbm_handle h, const void *u, void *v, int prec, void *strea
 
 sbm_status sbm_apply_parts(sbm_handle h, const void *u, void *v, int prec, int parts, void *stream) {
   if (!h || h->host_only || (h->n_dofs > 0 && (!u || !v)) || (u == v && h->n_dofs > 0) ||
-      (prec != SBM_F64 && prec != SBM_F32) || (parts & ~SBM_PART_ALL)) {
+      (prec != SBM_F64 && prec != SBM_F32) || (parts & ~(SBM_PART_ALL | SBM_PART_NO_ASSEMBLY))) {
     set_error("sbm_apply_parts: invalid argument");
     return SBM_EINVAL;
   }
   if (h->n_dofs == 0) return SBM_OK;
   SBM_HIP_CHECK(launch_apply(h, u, v, prec, parts, (hipStream_t)stream));
+  return SBM_OK;
+}
+
+sbm_status sbm_layout_stats(sbm_handle h, int64_t *n_bricks, int64_t *n_boundary_dofs,
+                            int64_t *n_boundary_slots) {
+  if (!h) {
+    set_error("sbm_layout_stats: NULL handle");
+    return SBM_EINVAL;
+  }
+  if (n_bricks) *n_bricks = h->n_bricks;
+  if (n_boundary_dofs) *n_boundary_dofs = h->n_halo_dofs;
+  if (n_boundary_slots) *n_boundary_slots = h->n_halo_slots;
   return SBM_OK;
 }
 

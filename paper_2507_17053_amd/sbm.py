@@ -87,9 +87,10 @@ _lib.sbm_footprint_estimate.restype = ctypes.c_size_t
 for _n in ("sbm_export_cells", "sbm_export_sbm_faces", "sbm_export_face_xi", "sbm_export_cell_dofs"):
     getattr(_lib, _n).argtypes = [_P, _P]
 
-PART_ZERO, PART_CELLS, PART_SBM_FACES, PART_ALL = 1, 2, 4, 7
+PART_CELLS, PART_SBM_FACES, PART_ALL, PART_NO_ASSEMBLY = 2, 4, 6, 8
+_lib.sbm_layout_stats.argtypes = [_P, _I64P, _I64P, _I64P]
 EXPORTED = ["sbm_setup", "sbm_info", "sbm_destroy", "sbm_last_error", "sbm_apply", "sbm_apply_parts",
-            "sbm_apply_batch",
+            "sbm_apply_batch", "sbm_layout_stats",
             "sbm_dof_points", "sbm_rhs_points", "sbm_rhs", "sbm_solve", "sbm_diagonal",
             "sbm_footprint_estimate", "sbm_export_cells", "sbm_export_sbm_faces", "sbm_export_face_xi",
             "sbm_export_cell_dofs"]
@@ -222,6 +223,13 @@ class Operator:
         prec = SBM_F64 if u.dtype == torch.float64 else SBM_F32
         _check(_lib.sbm_apply_parts(self._h, _dptr(u), _dptr(v), prec, int(parts), _stream_ptr(stream)),
                "sbm_apply_parts")
+
+    def layout_stats(self):
+        """(bricks, DoFs on brick boundaries, boundary slots) of the CG work decomposition."""
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.sbm_layout_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "sbm_layout_stats")
+        return a.value, b.value, c.value
 
     def diagonal(self, out, stream=None):
         import torch
