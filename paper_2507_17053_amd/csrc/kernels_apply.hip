@@ -643,6 +643,133 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------
+// Diagonal of A (for Jacobi preconditioning), one thread per (entity, local DoF):
+//   cell:  h^(d-2) sum_k K_ii(axis k) prod_{m != k} M_ii(axis m)            (same every cell)
+//   DG interior face (a, s) of K:  sum_q w_q (sigma_F psi_i^2 - psi_i dpsi_i/dn_K)
+//   surrogate face:  sum_q w_q [ -dn psi_i psi_i(x~) - dn psi_i psi_i(x) + sigma psi_i(x) psi_i(x~) ]
+// with psi_i(x~) on the face Gauss points and psi_i(x) at the shifted points.  Computed
+// once per solve, so it uses plain loops and global atomics.
+// ------------------------------------------------------------------------------------
+template <typename T, int D, int N1>
+__global__ void diag_cell_kernel(int n_cells, int disc_dg, const int32_t *__restrict__ runs,
+                                 const int32_t *__restrict__ nbr, T *__restrict__ diag, KTab<T, N1> tab, KScal sc,
+                                 T scale) {
+  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, P = N1 - 1;
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)n_cells * NB) return;
+  const int cell = (int)(gid / NB), i = (int)(gid % NB);
+  const int ik[3] = {i % N1, (i / N1) % N1, (D == 3) ? i / (N1 * N1) : 0};
+  double val = 0.0;
+  for (int k = 0; k < D; ++k) {
+    double t = tab.K[ik[k] * N1 + ik[k]];
+    for (int m = 0; m < D; ++m)
+      if (m != k) t *= tab.M[ik[m] * N1 + ik[m]];
+    val += t;
+  }
+  val *= (double)scale;
+  if (disc_dg) {
+    const double h = sc.h;
+    for (int code = 0; code < 2 * D; ++code) {
+      if (nbr[(int64_t)cell * 2 * D + code] < 0) continue;
+      const int a = code >> 1, s = code & 1;
+      if (ik[a] != s * P) {
+        // psi_i vanishes on this face: only the derivative term times psi_i = 0
+        continue;
+      }
+      const double sgn = s ? 1.0 : -1.0;
+      const double ds = s ? (double)tab.D1[ik[a]] : (double)tab.D0[ik[a]];
+      for (int q = 0; q < NP; ++q) {
+        const int qt[2] = {q % N1, (D == 3) ? q / N1 : 0};
+        double tang = 1.0, om = 1.0;
+        int t = 0;
+        for (int m = 0; m < D; ++m) {
+          if (m == a) continue;
+          tang *= (double)tab.N[qt[t] * N1 + ik[m]];
+          om *= (double)tab.w[qt[t]] * h;
+          ++t;
+        }
+        val += om * (sc.sigma_f * tang * tang - tang * sgn / h * ds * tang);
+      }
+    }
+    diag[(int64_t)cell * NB + i] = (T)val;
+  } else {
+    atomic_add(diag + runs[(int64_t)cell * NP + i / N1] + i % N1, (T)val);
+  }
+}
+
+template <typename T, int D, int N1>
+__global__ void diag_face_kernel(int n_faces, int disc_dg, const int32_t *__restrict__ face_cell,
+                                 const int32_t *__restrict__ face_code, const double *__restrict__ face_xi,
+                                 const int32_t *__restrict__ runs, T *__restrict__ diag, KTab<T, N1> tab, KScal sc) {
+  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, P = N1 - 1;
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)n_faces * NB) return;
+  const int f = (int)(gid / NB), i = (int)(gid % NB);
+  const int cell = face_cell[f], code = face_code[f], a = code >> 1, s = code & 1;
+  const int ik[3] = {i % N1, (i / N1) % N1, (D == 3) ? i / (N1 * N1) : 0};
+  const double h = sc.h, sgn = s ? 1.0 : -1.0;
+  const double ds = s ? (double)tab.D1[ik[a]] : (double)tab.D0[ik[a]];
+  double val = 0.0;
+  for (int q = 0; q < NP; ++q) {
+    const int qt[2] = {q % N1, (D == 3) ? q / N1 : 0};
+    double tang = 1.0, om = 1.0;
+    int t = 0;
+    for (int m = 0; m < D; ++m) {
+      if (m == a) continue;
+      tang *= (double)tab.N[qt[t] * N1 + ik[m]];
+      om *= (double)tab.w[qt[t]] * h;
+      ++t;
+    }
+    const double vt = (ik[a] == s * P) ? tang : 0.0;  // psi_i(x~_q)
+    const double dn = sgn / h * ds * tang;            // d psi_i / dn~ (x~_q)
+    double vs = 1.0;                                  // psi_i(x_q), shifted point
+    const double *xq = face_xi + ((int64_t)f * NP + q) * D;
+    for (int m = 0; m < D; ++m) {
+      double l[N1];
+      lagrange_at<N1>(tab.z, tab.cinv, xq[m], l);
+      vs *= l[ik[m]];
+    }
+    val += om * (-dn * vt - dn * vs + sc.sigma_gamma * vs * vt);
+  }
+  const int64_t dof = disc_dg ? (int64_t)cell * NB + i : (int64_t)runs[(int64_t)cell * NP + i / N1] + i % N1;
+  atomic_add(diag + dof, (T)val);
+}
+
+template <typename T, int D, int N1>
+hipError_t diag_impl(const sbm_ctx *c, T *diag, hipStream_t s) {
+  constexpr int NB = Shape<D, N1>::NB;
+  const KTab<T, N1> tab = make_ktab<T, N1>(c->rules);
+  const KScal sc{c->h, c->sigma_gamma, c->sigma_f};
+  const T scale = T(D == 3 ? c->h : 1.0);
+  const int dg = c->disc == SBM_DG;
+  hipError_t e = vec_fill(diag, c->n_dofs, 0.0, sizeof(T) == 8 ? SBM_F64 : SBM_F32, s);
+  if (e != hipSuccess) return e;
+  const int64_t nc = c->n_cells * NB, nf = c->n_sbm * NB;
+  if (nc > 0)
+    hipLaunchKernelGGL((diag_cell_kernel<T, D, N1>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s,
+                       (int)c->n_cells, dg, c->d_runs, c->d_nbr, diag, tab, sc, scale);
+  if (nf > 0)
+    hipLaunchKernelGGL((diag_face_kernel<T, D, N1>), dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s,
+                       (int)c->n_sbm, dg, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, diag, tab, sc);
+  return hipGetLastError();
+}
+
+template <typename T, int D>
+hipError_t diag_dim(const sbm_ctx *c, T *diag, hipStream_t s) {
+  switch (c->p) {
+    case 1: return diag_impl<T, D, 2>(c, diag, s);
+    case 2: return diag_impl<T, D, 3>(c, diag, s);
+    case 3: return diag_impl<T, D, 4>(c, diag, s);
+    case 4: return diag_impl<T, D, 5>(c, diag, s);
+    case 5: return diag_impl<T, D, 6>(c, diag, s);
+    case 6: return diag_impl<T, D, 7>(c, diag, s);
+    case 7: return diag_impl<T, D, 8>(c, diag, s);
+    case 8: return diag_impl<T, D, 9>(c, diag, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T, int D>
 hipError_t apply_dim(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t s) {
   switch (c->p) {
@@ -672,6 +799,12 @@ void brick_dims(int dim, int p, int *bx, int *by, int *bz) {
   SBM_BD(3, 1) SBM_BD(3, 2) SBM_BD(3, 3) SBM_BD(3, 4) SBM_BD(3, 5) SBM_BD(3, 6) SBM_BD(3, 7) SBM_BD(3, 8)
 #undef SBM_BD
   *bx = *by = *bz = 1;
+}
+
+hipError_t launch_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s) {
+  if (prec == SBM_F64)
+    return c->dim == 3 ? diag_dim<double, 3>(c, (double *)diag, s) : diag_dim<double, 2>(c, (double *)diag, s);
+  return c->dim == 3 ? diag_dim<float, 3>(c, (float *)diag, s) : diag_dim<float, 2>(c, (float *)diag, s);
 }
 
 hipError_t launch_apply(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s) {

@@ -1,18 +1,336 @@
-// Right-hand side, batched applies and (later) Krylov solvers.
+// Right-hand side, batched applies and the Krylov solvers around the operator.
+//
+// The SBM operator of Eq. (1) is nonsymmetric (the extension E acts on the trial side
+// only) and, with full polynomial extrapolation, indefinite, so the default solver is
+// restarted GMRES(m) with classical Gram-Schmidt and one re-orthogonalisation pass
+// (CGS2: two fused multi-dot / multi-axpy sweeps over the basis).  The mixed-precision
+// mode runs GMRES on the FP32 operator inside FP64 iterative refinement: the outer
+// residual r = b - A x, its norm and the update x += c are FP64 on the device.
+// Reductions are two-pass (block partial sums, then one block in a fixed order), so a
+// solve is deterministic given a deterministic apply.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "sbm_internal.h"
 
 namespace sbm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxBlocks = 1024;
+
+inline int nblocks(int64_t n) {
+  int64_t b = (n + kThreads * 8 - 1) / (kThreads * 8);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxBlocks));
+}
+
+// partial[blk * ncol + i] = sum over this block's entries of V_i . w  (i < ncol)
+template <typename T, int NCOL_MAX>
+__global__ __launch_bounds__(kThreads) void multidot_kernel(const T *__restrict__ V, int64_t ld, int ncol,
+                                                            const T *__restrict__ w, int64_t n,
+                                                            double *__restrict__ partial) {
+  __shared__ double red[kThreads / 64][NCOL_MAX];
+  double acc[NCOL_MAX];
+#pragma unroll
+  for (int i = 0; i < NCOL_MAX; ++i) acc[i] = 0.0;
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
+    const double wk = (double)w[k];
+#pragma unroll
+    for (int i = 0; i < NCOL_MAX; ++i)
+      if (i < ncol) acc[i] += (double)V[i * ld + k] * wk;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NCOL_MAX; ++i) {
+    if (i >= ncol) break;
+    double s = acc[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) red[wave][i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ncol; i += kThreads) {
+    double s = 0.0;
+    for (int wv = 0; wv < kThreads / 64; ++wv) s += red[wv][i];
+    partial[(int64_t)blockIdx.x * ncol + i] = s;
+  }
+}
+
+// out[i] = sum_b partial[b * ncol + i], fixed order
+__global__ void reduce_partials_kernel(const double *__restrict__ partial, int nblk, int ncol,
+                                       double *__restrict__ out) {
+  const int i = threadIdx.x;
+  if (i >= ncol) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * ncol + i];
+  out[i] = s;
+}
+
+// w -= sum_i coef[i] V_i
+template <typename T>
+__global__ __launch_bounds__(kThreads) void multiaxpy_kernel(const T *__restrict__ V, int64_t ld, int ncol,
+                                                             const double *__restrict__ coef, T *__restrict__ w,
+                                                             int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
+    double s = (double)w[k];
+    for (int i = 0; i < ncol; ++i) s -= coef[i] * (double)V[i * ld + k];
+    w[k] = (T)s;
+  }
+}
+
+// y = x * (1 / *nrm)  (nrm on the device)
+template <typename T>
+__global__ void scale_kernel(const T *__restrict__ x, const double *__restrict__ nrm, T *__restrict__ y, int64_t n) {
+  const double inv = 1.0 / sqrt(*nrm);
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    y[k] = (T)((double)x[k] * inv);
+}
+
+// x += sum_i y[i] Z_i  (Z_i = V_i, optionally scaled by dinv), y on the device
+template <typename T>
+__global__ void update_kernel(const T *__restrict__ V, int64_t ld, int ncol, const double *__restrict__ y,
+                              const T *__restrict__ dinv, T *__restrict__ x, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
+    double s = 0.0;
+    for (int i = 0; i < ncol; ++i) s += y[i] * (double)V[i * ld + k];
+    if (dinv) s *= (double)dinv[k];
+    x[k] = (T)((double)x[k] + s);
+  }
+}
+
+// r = b - v
+template <typename T>
+__global__ void residual_kernel(const T *__restrict__ b, const T *__restrict__ v, T *__restrict__ r, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    r[k] = b[k] - v[k];
+}
+
+// z = dinv .* v
+template <typename T>
+__global__ void diag_scale_kernel(const T *__restrict__ dinv, const T *__restrict__ v, T *__restrict__ z, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    z[k] = dinv[k] * v[k];
+}
+
+// r32 = (float)(r64 / nrm)
+__global__ void to_f32_kernel(const double *__restrict__ r, const double *__restrict__ nrm2, float *__restrict__ o,
+                              int64_t n) {
+  const double inv = 1.0 / sqrt(*nrm2);
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    o[k] = (float)(r[k] * inv);
+}
+
+// x64 += sqrt(nrm2) * c32
+__global__ void add_f32_kernel(const float *__restrict__ c, const double *__restrict__ nrm2, double *__restrict__ x,
+                               int64_t n) {
+  const double s = sqrt(*nrm2);
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    x[k] += s * (double)c[k];
+}
+
+__global__ void invert_kernel(double *__restrict__ d, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    d[k] = d[k] != 0.0 ? 1.0 / d[k] : 0.0;
+}
+
+__global__ void cast_f64_f32_kernel(const double *__restrict__ a, float *__restrict__ b, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    b[k] = (float)a[k];
+}
+
+__global__ void fill_f32_kernel(float *__restrict__ a, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    a[k] = 0.0f;
+}
+
+template <typename T>
+__global__ void copy_kernel(const T *__restrict__ a, T *__restrict__ b, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    b[k] = a[k];
+}
+
+// CG updates with device scalars: x += alpha p, r -= alpha q with alpha = rr / pq
+__global__ void cg_xr_kernel(double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
+                             const double *__restrict__ q, const double *__restrict__ rr,
+                             const double *__restrict__ pq, int64_t n) {
+  const double alpha = *rr / *pq;
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
+    x[k] += alpha * p[k];
+    r[k] -= alpha * q[k];
+  }
+}
+
+// p = r + (rr_new / rr_old) p
+__global__ void cg_p_kernel(double *__restrict__ p, const double *__restrict__ r, const double *__restrict__ rr_new,
+                            const double *__restrict__ rr_old, int64_t n) {
+  const double beta = *rr_new / *rr_old;
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    p[k] = r[k] + beta * p[k];
+}
+
+}  // namespace
 
 struct Workspace {
-  int dummy = 0;
+  int64_t n = 0;
+  int m = 0;
+  // FP64
+  double *V = nullptr;   // (m+1) x n
+  double *w = nullptr, *r = nullptr, *t = nullptr, *z = nullptr;
+  double *dinv = nullptr;
+  // FP32
+  float *V32 = nullptr;  // (m+1) x n
+  float *w32 = nullptr, *c32 = nullptr, *z32 = nullptr, *r32 = nullptr, *dinv32 = nullptr;
+  // reductions
+  double *partial = nullptr;  // kMaxBlocks x (m+2)
+  double *h = nullptr;        // m+2 device scalars (also scratch)
+  double *y = nullptr;        // m+1 coefficients for the update
+  bool have_diag = false;
 };
 
 void free_workspace(sbm_ctx *c) {
-  delete c->ws;
+  Workspace *ws = c->ws;
+  if (!ws) return;
+  void *ptrs[] = {ws->V,   ws->w,   ws->r,    ws->t,       ws->z, ws->dinv, ws->V32, ws->w32,
+                  ws->c32, ws->z32, ws->r32, ws->dinv32, ws->partial, ws->h, ws->y};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete ws;
   c->ws = nullptr;
+}
+
+static hipError_t ensure_workspace(sbm_ctx *c, int m, bool need32) {
+  Workspace *ws = c->ws;
+  if (ws && ws->m >= m && (!need32 || ws->V32)) return hipSuccess;
+  free_workspace(c);
+  ws = new Workspace();
+  c->ws = ws;
+  ws->n = c->n_dofs;
+  ws->m = m;
+  const size_t n = (size_t)std::max<int64_t>(1, c->n_dofs);
+  hipError_t e = hipMalloc(&ws->V, sizeof(double) * n * (m + 1));
+  if (e == hipSuccess) e = hipMalloc(&ws->w, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&ws->r, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&ws->t, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&ws->z, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&ws->partial, sizeof(double) * kMaxBlocks * (m + 2));
+  if (e == hipSuccess) e = hipMalloc(&ws->h, sizeof(double) * (m + 2));
+  if (e == hipSuccess) e = hipMalloc(&ws->y, sizeof(double) * (m + 2));
+  if (e == hipSuccess && need32) {
+    e = hipMalloc(&ws->V32, sizeof(float) * n * (m + 1));
+    if (e == hipSuccess) e = hipMalloc(&ws->w32, sizeof(float) * n);
+    if (e == hipSuccess) e = hipMalloc(&ws->c32, sizeof(float) * n);
+    if (e == hipSuccess) e = hipMalloc(&ws->z32, sizeof(float) * n);
+    if (e == hipSuccess) e = hipMalloc(&ws->r32, sizeof(float) * n);
+  }
+  return e;
+}
+
+// device dot products: out[i] = V_i . w for i < ncol (out on the device)
+template <typename T>
+static hipError_t multidot(const T *V, int64_t ld, int ncol, const T *w, int64_t n, double *partial, double *out,
+                           hipStream_t s) {
+  const int nb = nblocks(n);
+  if (ncol <= 8)
+    hipLaunchKernelGGL((multidot_kernel<T, 8>), dim3(nb), dim3(kThreads), 0, s, V, ld, ncol, w, n, partial);
+  else if (ncol <= 16)
+    hipLaunchKernelGGL((multidot_kernel<T, 16>), dim3(nb), dim3(kThreads), 0, s, V, ld, ncol, w, n, partial);
+  else if (ncol <= 32)
+    hipLaunchKernelGGL((multidot_kernel<T, 32>), dim3(nb), dim3(kThreads), 0, s, V, ld, ncol, w, n, partial);
+  else
+    hipLaunchKernelGGL((multidot_kernel<T, 64>), dim3(nb), dim3(kThreads), 0, s, V, ld, ncol, w, n, partial);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, s, partial, nb, ncol, out);
+  return hipGetLastError();
+}
+
+// One restarted-GMRES run in precision T on A_T (prec) with optional right Jacobi
+// preconditioning.  Solves A c = rhs to ||rhs - A c|| <= tol_abs starting from c (device),
+// at most max_it iterations.  Returns the final true residual norm in *res (FP64, device
+// computed) and the iteration count in *its.
+template <typename T>
+static sbm_status gmres_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *V, T *w, T *z, const T *dinv, int m,
+                            double tol_abs, int max_it, hipStream_t s, int *its, int *applies, double *res) {
+  Workspace *ws = c->ws;
+  const int64_t n = c->n_dofs;
+  const int nb = nblocks(n);
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), hcol(m + 2);
+  *its = 0;
+  double beta = 0.0;
+  while (true) {
+    // r = rhs - A x  -> V_0
+    SBM_HIP_CHECK(launch_apply(c, x, w, prec, SBM_PART_ALL, s));
+    ++*applies;
+    hipLaunchKernelGGL(residual_kernel<T>, dim3(nb), dim3(kThreads), 0, s, rhs, w, V, n);
+    SBM_HIP_CHECK(multidot<T>(V, n, 1, V, n, ws->partial, ws->h, s));
+    SBM_HIP_CHECK(hipMemcpyAsync(&beta, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
+    SBM_HIP_CHECK(hipStreamSynchronize(s));
+    beta = std::sqrt(beta);
+    *res = beta;
+    if (!(beta > tol_abs) || *its >= max_it) return std::isfinite(beta) ? SBM_OK : SBM_ENOCONV;
+    hipLaunchKernelGGL(scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, ws->h, V, n);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    for (; j < m && *its < max_it; ++j) {
+      T *vj = V + (int64_t)j * n, *vn = V + (int64_t)(j + 1) * n;
+      const T *src = vj;
+      if (dinv) {
+        hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, dinv, vj, z, n);
+        src = z;
+      }
+      SBM_HIP_CHECK(launch_apply(c, src, w, prec, SBM_PART_ALL, s));
+      ++*applies;
+      // CGS2: two projection passes; h accumulates both coefficient vectors
+      std::fill(hcol.begin(), hcol.end(), 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        SBM_HIP_CHECK(multidot<T>(V, n, j + 1, w, n, ws->partial, ws->h, s));
+        hipLaunchKernelGGL(multiaxpy_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, n, j + 1, ws->h, w, n);
+        std::vector<double> hp(j + 1);
+        SBM_HIP_CHECK(hipMemcpyAsync(hp.data(), ws->h, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+        SBM_HIP_CHECK(hipStreamSynchronize(s));
+        for (int i = 0; i <= j; ++i) hcol[i] += hp[i];
+      }
+      SBM_HIP_CHECK(multidot<T>(w, n, 1, w, n, ws->partial, ws->h + (m + 1), s));
+      double nrm2 = 0.0;
+      SBM_HIP_CHECK(hipMemcpyAsync(&nrm2, ws->h + (m + 1), sizeof(double), hipMemcpyDeviceToHost, s));
+      SBM_HIP_CHECK(hipStreamSynchronize(s));
+      hcol[j + 1] = std::sqrt(nrm2);
+      if (hcol[j + 1] > 0.0)
+        hipLaunchKernelGGL(scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, w, ws->h + (m + 1), vn, n);
+      // Givens rotations
+      for (int i = 0; i < j; ++i) {
+        const double a = hcol[i], b = hcol[i + 1];
+        hcol[i] = cs[i] * a + sn[i] * b;
+        hcol[i + 1] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = hcol[j], b = hcol[j + 1];
+      const double rr = std::hypot(a, b);
+      cs[j] = rr > 0 ? a / rr : 1.0;
+      sn[j] = rr > 0 ? b / rr : 0.0;
+      hcol[j] = rr;
+      hcol[j + 1] = 0.0;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++*its;
+      if (std::fabs(g[j + 1]) <= tol_abs || !(rr > 0.0)) {
+        ++j;
+        break;
+      }
+    }
+    // back substitution and update x += M^-1 V y
+    std::vector<double> y(j, 0.0);
+    for (int i = j - 1; i >= 0; --i) {
+      double sacc = g[i];
+      for (int k = i + 1; k < j; ++k) sacc -= H[(size_t)i * m + k] * y[k];
+      y[i] = H[(size_t)i * m + i] != 0.0 ? sacc / H[(size_t)i * m + i] : 0.0;
+    }
+    if (j > 0) {
+      SBM_HIP_CHECK(hipMemcpyAsync(ws->y, y.data(), sizeof(double) * j, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(update_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, n, j, ws->y, dinv, x, n);
+    }
+  }
 }
 
 }  // namespace sbm
@@ -22,8 +340,8 @@ using namespace sbm;
 extern "C" {
 
 sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double *b, void *stream) {
-  if (!h || !f_qp || !b || (h->n_sbm > 0 && !g_bp)) {
-    set_error("sbm_rhs: NULL argument");
+  if (!h || !f_qp || !b || (h->n_sbm > 0 && !g_bp) || h->host_only) {
+    set_error("sbm_rhs: NULL argument or host-only handle");
     return SBM_EINVAL;
   }
   const int d = h->dim, n1 = h->n1, nb = h->nb, np = h->nq_face, P = h->p;
@@ -102,28 +420,161 @@ sbm_status sbm_apply_batch(int n, const sbm_handle *hs, const void *const *u, vo
 }
 
 sbm_status sbm_diagonal(sbm_handle h, void *diag, int prec, void *stream) {
-  (void)h;
-  (void)diag;
-  (void)prec;
-  (void)stream;
-  set_error("sbm_diagonal: not available in this build");
-  return SBM_EUNSUPPORTED;
+  if (!h || (!diag && h->n_dofs > 0) || h->host_only || (prec != SBM_F64 && prec != SBM_F32)) {
+    set_error("sbm_diagonal: invalid argument");
+    return SBM_EINVAL;
+  }
+  if (h->n_dofs == 0) return SBM_OK;
+  hipError_t e = launch_diagonal(h, diag, prec, (hipStream_t)stream);
+  if (e == hipErrorNotSupported) {
+    set_error("sbm_diagonal: not available for this discretisation");
+    return SBM_EUNSUPPORTED;
+  }
+  SBM_HIP_CHECK(e);
+  return SBM_OK;
 }
 
 sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, int max_it, int mode,
                      int restart, int jacobi, void *stream, sbm_solve_info *info) {
-  (void)h;
-  (void)b;
-  (void)x;
-  (void)rel_tol;
-  (void)max_it;
-  (void)mode;
-  (void)restart;
-  (void)jacobi;
-  (void)stream;
-  (void)info;
-  set_error("sbm_solve: not available in this build");
-  return SBM_EUNSUPPORTED;
+  const auto t0 = std::chrono::steady_clock::now();
+  sbm_solve_info loc{};
+  if (!info) info = &loc;
+  std::memset(info, 0, sizeof(*info));
+  if (!h || h->host_only || (h->n_dofs > 0 && (!b || !x)) || !(rel_tol > 0) || max_it < 1 ||
+      (mode != SBM_SOLVE_GMRES_F64 && mode != SBM_SOLVE_GMRES_IR && mode != SBM_SOLVE_CG_F64)) {
+    set_error("sbm_solve: invalid argument");
+    info->status = SBM_EINVAL;
+    return SBM_EINVAL;
+  }
+  if (h->n_dofs == 0) {
+    info->status = SBM_OK;
+    return SBM_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int m = restart > 0 ? std::min(restart, 64) : 50;
+  hipError_t e = ensure_workspace(h, m, mode == SBM_SOLVE_GMRES_IR);
+  if (e != hipSuccess) {
+    set_error(std::string("sbm_solve: workspace allocation failed: ") + hipGetErrorString(e));
+    info->status = SBM_ENOMEM;
+    return SBM_ENOMEM;
+  }
+  Workspace *ws = h->ws;
+  const int64_t n = h->n_dofs;
+  const int nb = nblocks(n);
+  // Jacobi: inverse diagonal
+  const double *dinv = nullptr;
+  const float *dinv32 = nullptr;
+  if (jacobi) {
+    if (!ws->dinv) {
+      if (hipMalloc(&ws->dinv, sizeof(double) * n) != hipSuccess) {
+        set_error("sbm_solve: out of device memory");
+        return SBM_ENOMEM;
+      }
+    }
+    sbm_status st = sbm_diagonal(h, ws->dinv, SBM_F64, stream);
+    if (st != SBM_OK) {
+      info->status = st;
+      return st;
+    }
+    hipLaunchKernelGGL(invert_kernel, dim3(nb), dim3(kThreads), 0, s, ws->dinv, n);
+    dinv = ws->dinv;
+    if (mode == SBM_SOLVE_GMRES_IR) {
+      if (!ws->dinv32 && hipMalloc(&ws->dinv32, sizeof(float) * n) != hipSuccess) {
+        set_error("sbm_solve: out of device memory");
+        return SBM_ENOMEM;
+      }
+      hipLaunchKernelGGL(cast_f64_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->dinv, ws->dinv32, n);
+      dinv32 = ws->dinv32;
+    }
+  }
+  // ||b||
+  SBM_HIP_CHECK(multidot<double>(b, n, 1, b, n, ws->partial, ws->h, s));
+  double bn2 = 0.0;
+  SBM_HIP_CHECK(hipMemcpyAsync(&bn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
+  SBM_HIP_CHECK(hipStreamSynchronize(s));
+  const double bnorm = std::sqrt(bn2);
+  const double tol_abs = rel_tol * (bnorm > 0 ? bnorm : 1.0);
+  sbm_status st = SBM_OK;
+  double res = 0.0;
+  if (mode == SBM_SOLVE_GMRES_F64) {
+    int its = 0, applies = 0;
+    st = gmres_run<double>(h, SBM_F64, b, x, ws->V, ws->w, ws->z, dinv, m, tol_abs, max_it, s, &its, &applies,
+                           &res);
+    info->inner_its = its;
+    info->outer_its = (its + m - 1) / m;
+    info->applies_f64 = applies;
+  } else if (mode == SBM_SOLVE_GMRES_IR) {
+    // FP64 refinement: r = b - A x (FP64), c ~= A32^-1 (r / |r|) by FP32 GMRES, x += |r| c
+    int total_its = 0;
+    for (int outer = 0;; ++outer) {
+      SBM_HIP_CHECK(launch_apply(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
+      ++info->applies_f64;
+      hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
+      SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));
+      double rn2 = 0.0;
+      SBM_HIP_CHECK(hipMemcpyAsync(&rn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
+      SBM_HIP_CHECK(hipStreamSynchronize(s));
+      res = std::sqrt(rn2);
+      info->outer_its = outer;
+      if (!(res > tol_abs) || total_its >= max_it || !std::isfinite(res)) break;
+      // keep |r|^2 on the device for the scaling kernels (slot m+1 of h is GMRES scratch)
+      SBM_HIP_CHECK(hipMemcpyAsync(ws->y + (m + 1), ws->h, sizeof(double), hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(to_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->r, ws->y + (m + 1), ws->r32, n);
+      hipLaunchKernelGGL(fill_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, n);
+      int its = 0, applies = 0;
+      double inner_res = 0.0;
+      // inner solve of A32 c = r / |r| to 1e-4 (unit right-hand side), at most 4 restart cycles
+      (void)gmres_run<float>(h, SBM_F32, ws->r32, ws->c32, ws->V32, ws->w32, ws->z32, dinv32, m, 1e-4,
+                             std::min(4 * m, max_it - total_its), s, &its, &applies, &inner_res);
+      total_its += its;
+      info->applies_f32 += applies;
+      hipLaunchKernelGGL(add_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, ws->y + (m + 1), x, n);
+      if (its == 0) break;
+    }
+    info->inner_its = total_its;
+  } else {
+    // CG (symmetric operators only)
+    double *r = ws->r, *p = ws->z, *q = ws->t;
+    double *dev = ws->h;  // [0]=rr, [1]=pq, [2]=rr_new
+    SBM_HIP_CHECK(launch_apply(h, x, q, SBM_F64, SBM_PART_ALL, s));
+    ++info->applies_f64;
+    hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, q, r, n);
+    hipLaunchKernelGGL(copy_kernel<double>, dim3(nb), dim3(kThreads), 0, s, r, p, n);
+    SBM_HIP_CHECK(multidot<double>(r, n, 1, r, n, ws->partial, dev, s));
+    int it = 0;
+    for (; it < max_it; ++it) {
+      double rr = 0.0;
+      if (it % 10 == 0) {
+        SBM_HIP_CHECK(hipMemcpyAsync(&rr, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+        SBM_HIP_CHECK(hipStreamSynchronize(s));
+        res = std::sqrt(rr);
+        if (!(res > tol_abs) || !std::isfinite(res)) break;
+      }
+      SBM_HIP_CHECK(launch_apply(h, p, q, SBM_F64, SBM_PART_ALL, s));
+      ++info->applies_f64;
+      SBM_HIP_CHECK(multidot<double>(p, n, 1, q, n, ws->partial, dev + 1, s));
+      hipLaunchKernelGGL(cg_xr_kernel, dim3(nb), dim3(kThreads), 0, s, x, r, p, q, dev, dev + 1, n);
+      SBM_HIP_CHECK(multidot<double>(r, n, 1, r, n, ws->partial, dev + 2, s));
+      hipLaunchKernelGGL(cg_p_kernel, dim3(nb), dim3(kThreads), 0, s, p, r, dev + 2, dev, n);
+      SBM_HIP_CHECK(hipMemcpyAsync(dev, dev + 2, sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    info->inner_its = it;
+    info->outer_its = 1;
+  }
+  // final true residual in FP64
+  SBM_HIP_CHECK(launch_apply(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
+  ++info->applies_f64;
+  hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
+  SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));
+  double rn2 = 0.0;
+  SBM_HIP_CHECK(hipMemcpyAsync(&rn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
+  SBM_HIP_CHECK(hipStreamSynchronize(s));
+  info->rel_residual = std::sqrt(rn2) / (bnorm > 0 ? bnorm : 1.0);
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st == SBM_OK && !(info->rel_residual <= rel_tol)) st = SBM_ENOCONV;
+  if (st == SBM_ENOCONV) set_error("sbm_solve: tolerance not reached within max_it");
+  info->status = st;
+  return st;
 }
 
 }  // extern "C"
