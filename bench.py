@@ -51,6 +51,20 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
+def measured_traffic():
+    """HBM bytes per brick-kernel launch from the committed FETCH_SIZE / WRITE_SIZE summary,
+    only if it was taken on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", "brick_kernel_sphere3d_q4_traffic.md")
+    if not os.path.exists(p):
+        return None
+    for line in open(p):
+        if line.startswith("machine-readable:"):
+            rec = json.loads(line.split(":", 1)[1])
+            if rec.get("kernel_src") == kernel_source_hash():
+                return rec.get("traffic_bytes_per_launch")
+    return None
+
+
 def time_launches(torch, fn, k, graph_batch=20):
     """Average time per fn() call over k calls: captured into a HIP graph of graph_batch
     calls, replayed; timed with events recorded on the launch stream."""
@@ -114,6 +128,55 @@ def cpu_baseline(w, budget_s=12.0):
             "seconds": el}
 
 
+SOLVE_CASES = [
+    # (name, workload, overrides, max_it)
+    ("disk2d_q2", "disk2d_q2", {}, 8000),  # converges with restart 64
+    ("torus3d_dg_q3", "torus3d_dg", {"p": 3}, 3000),
+    ("sphere3d_q4", "sphere3d_q4", {}, 1500),
+]
+
+
+def solve_section(torch, sbm, inputs):
+    """FP64 GMRES vs FP32-inner GMRES with FP64 refinement, same restart length, to 1e-10."""
+    out = []
+    for name, wname, over, max_it in SOLVE_CASES:
+        w = inputs.workload(wname, **over)
+        op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"])
+        u_fn, f_fn = inputs.manufactured(w["d"])
+        cq, bp = op.rhs_points()
+        b = torch.empty(op.n_dofs, dtype=torch.float64, device="cuda")
+        op.rhs(f_fn(cq.reshape(-1, w["d"])), u_fn(bp.reshape(-1, w["d"])), b)
+        rec = {"case": name, "n_dofs": op.n_dofs}
+        for mode in ("gmres", "gmres_ir"):
+            x = torch.zeros_like(b)
+            info = op.solve(b, x, rel_tol=1e-10, max_it=max_it, mode=mode, restart=64)
+            rec[mode] = {"status": sbm.status_name(info["status"]), "seconds": info["seconds"],
+                         "krylov_its": info["inner_its"], "refinements": info["outer_its"],
+                         "applies_f64": info["applies_f64"], "applies_f32": info["applies_f32"],
+                         "rel_residual_f64": info["rel_residual"]}
+            print(f"solve {name} {mode}: {rec[mode]}", file=sys.stderr, flush=True)
+        g, r = rec["gmres"], rec["gmres_ir"]
+        if g["status"] == "SBM_OK" and r["status"] == "SBM_OK":
+            rec["ir_speedup"] = g["seconds"] / r["seconds"]
+        out.append(rec)
+        op.close()
+    return out
+
+
+def profile_run(torch, sbm, inputs, n=5):
+    """A few eager FP64 applies and plain device copies of n_dofs doubles, for counter runs."""
+    w = inputs.workload("sphere3d_q4")
+    op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"])
+    u = torch.from_numpy(inputs.uniform_vector(op.n_dofs, seed=0)).to("cuda")
+    v = torch.empty_like(u)
+    for _ in range(n):
+        op.apply(u, v)
+    for _ in range(n):
+        v.copy_(u)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": True, "n_dofs": op.n_dofs, "copy_bytes_each_way": 8 * op.n_dofs}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +186,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--solve", action="store_true", help="also time the FP64 and FP32+IR solves")
+    ap.add_argument("--profile-run", action="store_true", help="few eager applies + copies (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -131,6 +195,10 @@ def main():
     import torch
 
     from paper_2507_17053_amd import inputs, sbm
+
+    if args.profile_run:
+        profile_run(torch, sbm, inputs)
+        return
 
     w = inputs.workload(args.workload)
     t_setup = time.perf_counter()
@@ -180,7 +248,8 @@ def main():
                    if gb else "eager"},
         "roofline": {"bound": "hbm", "kernel": "brick_kernel (FP64: cells + surrogate faces)",
                      "achieved": brick_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": brick_gbs / HBM_PEAK_GBS, "traffic": None, "kernel_ms": r["t_brick"] * 1e3,
+                     "frac": brick_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel_ms": r["t_brick"] * 1e3,
                      "algorithmic_bytes_per_launch": r["b_brick"], "kernel_src": kernel_source_hash()},
         "apply_effective_GBs": apply_gbs,
         "apply_hbm_frac": apply_gbs / HBM_PEAK_GBS,
@@ -197,6 +266,8 @@ def main():
                  "brick_kernel_frac": res["f32"]["b_brick"] / res["f32"]["t_brick"] / 1e9 / HBM_PEAK_GBS},
         "setup_s": t_setup,
     }
+    if args.solve:
+        out["solve"] = solve_section(torch, sbm, inputs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
