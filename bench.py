@@ -163,6 +163,26 @@ def solve_section(torch, sbm, inputs):
     return out
 
 
+def serve_section(n_req, max_it, rate, slots, budget_gb):
+    """Request stream (p in 2..6, 16^3..64^3 cells, ellipsoid or 8-ball union, CG or SIPG,
+    FP32 GMRES inside FP64 refinement to 1e-10 with an iteration cap), Poisson arrivals."""
+    from paper_2507_17053_amd import inputs
+    from paper_2507_17053_amd.serving import Server
+
+    reqs = inputs.serving_requests(n_req, seed=2, rate=rate)
+    srv = Server(budget_bytes=int(budget_gb * (1 << 30)), slots=slots, mode="gmres_ir", rel_tol=1e-10,
+                 max_it=max_it, restart=32)
+    s = srv.run(reqs, time_scale=1.0)
+    res = list(s["results"].values())
+    return {"requests": s["requests"], "served": s["served"], "converged_to_1e-10": s["converged"],
+            "errors": s["errors"], "solves_per_s": s["solves_per_s"], "latency_p50_s": s["latency_p50_s"],
+            "latency_p99_s": s["latency_p99_s"], "arrival_rate_per_s": rate, "slots": slots,
+            "hbm_budget_GB": budget_gb, "krylov_cap": max_it,
+            "median_rel_residual": float(sorted(r["info"].get("rel_residual", float("nan")) for r in res)[len(res) // 2])
+            if res else None,
+            "total_dofs": int(sum(r["info"].get("n_dofs", 0) for r in res))}
+
+
 def profile_run(torch, sbm, inputs, n=5):
     """A few eager FP64 applies and plain device copies of n_dofs doubles, for counter runs."""
     w = inputs.workload("sphere3d_q4")
@@ -187,6 +207,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--solve", action="store_true", help="also time the FP64 and FP32+IR solves")
     ap.add_argument("--profile-run", action="store_true", help="few eager applies + copies (counter runs)")
+    ap.add_argument("--serve", type=int, default=24, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve-max-it", type=int, default=100)
+    ap.add_argument("--serve-rate", type=float, default=8.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -268,6 +291,8 @@ def main():
     }
     if args.solve:
         out["solve"] = solve_section(torch, sbm, inputs)
+    if args.serve > 0:
+        out["serving"] = serve_section(args.serve, args.serve_max_it, args.serve_rate, slots=4, budget_gb=96.0)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -1,0 +1,229 @@
+"""Continuous-batching request loop for SBM Poisson solves.
+
+Requests (mesh, level set, degree, CG|DG) arrive over time.  The scheduler admits an
+arrived request when a slot is free and its device footprint fits in the remaining HBM
+budget; each slot owns a HIP stream and a host worker that runs setup -> right-hand side ->
+solve for its request through the C ABI, so the device work of all admitted requests
+overlaps.  When a solve completes, its operator and vectors are released and the next
+arrived request is admitted.  Latency = completion - arrival.
+
+The admission and ordering logic (Scheduler) is plain host code and is tested on the CPU
+with fake footprints; Server binds it to the library.
+"""
+
+from __future__ import annotations
+
+import heapq
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass(order=True)
+class _Pending:
+    arrival: float
+    rid: int
+    footprint: int = field(compare=False)
+    payload: object = field(compare=False, default=None)
+
+
+class Scheduler:
+    """First-come-first-served admission by arrival time, bounded by slots and a byte budget.
+
+    A request whose footprint exceeds the whole budget is rejected (never admitted).
+    Head-of-line: a request that does not fit yet blocks later ones (keeps FCFS order)."""
+
+    def __init__(self, budget_bytes: int, slots: int):
+        if budget_bytes <= 0 or slots <= 0:
+            raise ValueError("budget and slots must be positive")
+        self.budget = int(budget_bytes)
+        self.slots = int(slots)
+        self.used = 0
+        self.active = {}
+        self.pending = []
+        self.rejected = []
+
+    def submit(self, rid, arrival, footprint, payload=None):
+        if footprint > self.budget:
+            self.rejected.append(rid)
+            return False
+        heapq.heappush(self.pending, _Pending(float(arrival), int(rid), int(footprint), payload))
+        return True
+
+    def admit(self, now):
+        """Pop every request that has arrived by `now` and fits; returns [(rid, payload)]."""
+        out = []
+        while self.pending and self.pending[0].arrival <= now and len(self.active) < self.slots:
+            head = self.pending[0]
+            if self.used + head.footprint > self.budget:
+                break
+            heapq.heappop(self.pending)
+            self.used += head.footprint
+            self.active[head.rid] = head.footprint
+            out.append((head.rid, head.payload))
+        return out
+
+    def release(self, rid):
+        self.used -= self.active.pop(rid)
+
+    def idle(self):
+        return not self.pending and not self.active
+
+
+def footprint_bytes(n_dofs: int, device_bytes: int, restart: int, mixed: bool) -> int:
+    """Device bytes a solve holds: operator data + b, x + GMRES workspace (FP64 basis and
+    work vectors, plus the FP32 copies in the mixed mode)."""
+    ws = 8 * n_dofs * (restart + 1 + 4)
+    if mixed:
+        ws += 4 * n_dofs * (restart + 1 + 4)
+    return int(device_bytes + 16 * n_dofs + ws)
+
+
+def _phi_sign(ls, x):
+    """Level-set value for the admission estimate (sign only matters)."""
+    d = x.shape[1]
+    k = ls["kind"]
+    if k == "sphere":
+        return np.linalg.norm(x - np.asarray(ls["centre"][:d]), axis=1) - ls["radius"]
+    if k == "ellipsoid":
+        return np.sum(((x - np.asarray(ls["centre"][:d])) / np.asarray(ls["semi_axes"][:d])) ** 2, axis=1) - 1.0
+    if k == "torus":
+        y = x - np.asarray(ls["centre"])
+        return np.hypot(np.hypot(y[:, 0], y[:, 1]) - ls["R"], y[:, 2]) - ls["r"]
+    if k == "halfspace":
+        return x @ np.asarray(ls["normal"][:d]) - ls["offset"]
+    if k == "sphere_union":
+        cs = np.asarray(ls["centres"])[:, :d]
+        return np.min(np.linalg.norm(x[:, None, :] - cs[None], axis=2) - np.asarray(ls["radii"])[None], axis=1)
+    raise KeyError(k)
+
+
+def count_inside_cells(req) -> int:
+    """Background cells with all vertices strictly inside the domain."""
+    d, n = req["d"], int(req["n"])
+    lo, hi = float(req["lo"]), float(req["hi"])
+    g = lo + (hi - lo) / n * np.arange(n + 1)
+    pts = np.stack(np.meshgrid(*([g] * d), indexing="ij"), -1).reshape(-1, d)
+    inside = (_phi_sign(req["levelset"], pts) < 0).reshape([n + 1] * d)
+    act = np.ones([n] * d, dtype=bool)
+    for off in np.ndindex(*([2] * d)):
+        act &= inside[tuple(slice(o, o + n) for o in off)]
+    return int(act.sum())
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else float("nan")
+
+
+class Server:
+    """Runs a request stream on the GPU through the library (see module docstring)."""
+
+    def __init__(self, budget_bytes, slots=4, mode="gmres_ir", rel_tol=1e-10, max_it=400, restart=32):
+        self.sched = Scheduler(budget_bytes, slots)
+        self.mode, self.rel_tol, self.max_it, self.restart = mode, rel_tol, max_it, restart
+        self.lock = threading.Lock()
+        self.done = threading.Condition(self.lock)
+        self.results = {}
+
+    def _estimate(self, req):
+        """Upper-bound footprint from the number of background cells whose vertices are all
+        inside the domain (vectorised vertex test; no setup)."""
+        n_cells = count_inside_cells(req)
+        nb = (req["p"] + 1) ** req["d"]
+        n_dofs = n_cells * nb  # bound for CG, exact for DG
+        dev = n_cells * nb * 8 + n_cells * 64 * nb // (req["p"] + 1)  # maps, bricks, face data
+        return footprint_bytes(n_dofs, dev, self.restart, self.mode == "gmres_ir"), n_dofs
+
+    def solve_one(self, req, stream=None):
+        """Setup, right-hand side and solve of one request on `stream`; returns (x, info)."""
+        import torch
+
+        from . import inputs, sbm
+        op = sbm.Operator(req["d"], req["n"], req["lo"], req["hi"], req["levelset"], req["p"], disc=req["disc"])
+        try:
+            u_fn, f_fn = inputs.manufactured(req["d"])
+            cq, bp = op.rhs_points()
+            with torch.cuda.stream(stream) if stream is not None else _null():
+                b = torch.empty(op.n_dofs, dtype=torch.float64, device="cuda")
+                op.rhs(f_fn(cq.reshape(-1, req["d"])), u_fn(bp.reshape(-1, req["d"])), b, stream=stream)
+                x = torch.zeros_like(b)
+                info = op.solve(b, x, rel_tol=self.rel_tol, max_it=self.max_it, mode=self.mode,
+                                restart=self.restart, stream=stream)
+                xh = x.cpu().numpy() if stream is None else _to_host(x, stream)
+            info["n_dofs"] = op.n_dofs
+            return xh, info
+        finally:
+            op.close()
+
+    def run(self, requests, time_scale=1.0, keep_solutions=False):
+        """Serve `requests` (dicts with 'id' and 'arrival' seconds).  Arrival times are
+        scaled by time_scale (0 = all present at t=0, closed loop).  Returns a summary."""
+        import torch
+
+        reqs = {r["id"]: r for r in requests}
+        for r in requests:
+            fp, nd = self._estimate(r)
+            r["_footprint"], r["_n_dofs"] = fp, nd
+            self.sched.submit(r["id"], r["arrival"] * time_scale, fp, r)
+        streams = [torch.cuda.Stream() for _ in range(self.sched.slots)]
+        free_streams = list(range(self.sched.slots))
+        t0 = time.perf_counter()
+        threads = []
+
+        def worker(rid, req, si):
+            t_start = time.perf_counter() - t0
+            try:
+                x, info = self.solve_one(req, streams[si])
+                err = None
+            except Exception as exc:  # a failed request is reported, the server keeps running
+                x, info, err = None, {}, repr(exc)
+            t_end = time.perf_counter() - t0
+            with self.lock:
+                self.results[rid] = dict(id=rid, arrival=req["arrival"] * time_scale, start=t_start, end=t_end,
+                                         latency=t_end - req["arrival"] * time_scale, error=err,
+                                         info=info, x=x if keep_solutions else None)
+                self.sched.release(rid)
+                free_streams.append(si)
+                self.done.notify_all()
+
+        with self.lock:
+            while not self.sched.idle():
+                now = time.perf_counter() - t0
+                for rid, req in self.sched.admit(now):
+                    si = free_streams.pop()
+                    th = threading.Thread(target=worker, args=(rid, req, si), daemon=True)
+                    threads.append(th)
+                    th.start()
+                if self.sched.idle():
+                    break
+                nxt = self.sched.pending[0].arrival - now if self.sched.pending else None
+                self.done.wait(timeout=max(1e-3, nxt) if nxt is not None and nxt > 0 else 0.05)
+        for th in threads:
+            th.join()
+        wall = time.perf_counter() - t0
+        lat = [r["latency"] for r in self.results.values() if r["error"] is None]
+        ok = [r for r in self.results.values() if r["error"] is None and r["info"].get("status") == 0]
+        first_arrival = min((r["arrival"] for r in self.results.values()), default=0.0)
+        last_end = max((r["end"] for r in self.results.values()), default=0.0)
+        return {
+            "requests": len(requests), "served": len(self.results), "rejected": list(self.sched.rejected),
+            "converged": len(ok), "errors": sum(1 for r in self.results.values() if r["error"]),
+            "solves_per_s": len(self.results) / max(1e-9, last_end - first_arrival),
+            "latency_p50_s": percentile(lat, 50), "latency_p99_s": percentile(lat, 99),
+            "wall_s": wall, "results": self.results,
+        }
+
+
+class _null:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False
+
+
+def _to_host(x, stream):
+    stream.synchronize()
+    return x.cpu().numpy()
