@@ -1,14 +1,17 @@
 // Matrix-free SBM operator kernels for gfx950 (CDNA4, wave64).
 //
 //   brick_kernel    CG: one workgroup per brick of BX x BY x BZ background cells.  The
-//                   brick's active cells (Alg. 1) and its surrogate-boundary faces (Alg. 3)
-//                   are evaluated into an LDS copy of the brick's DoF lattice; points
-//                   strictly inside the brick are then stored to v directly, points on the
-//                   brick's boundary (shared with neighbouring bricks) are added atomically.
+//                   brick's active cells (Alg. 1) are evaluated into an LDS copy of the
+//                   brick's DoF lattice (a brick whose cells are all active by 1D line
+//                   sweeps over the whole lattice, others cell by cell), its surrogate-face
+//                   results are added; points strictly inside the brick are then stored to
+//                   v directly, points on the brick's boundary (shared with neighbouring
+//                   bricks) go to halo slots that halo_reduce_kernel sums.
+//   sbm_face_kernel Surrogate-boundary faces (Alg. 3).  CG: per-face results to a buffer
+//                   that brick_kernel adds; DG: atomics into the cell blocks.
 //   dg_cell_kernel  DG: Laplace cell term plus the SIPG terms of the cell's interior faces,
 //                   evaluated cell by cell (Alg. 2 split per side); every cell writes only
 //                   its own block.
-//   sbm_face_kernel DG surrogate-boundary faces (Alg. 3), atomics into the cell blocks.
 //
 // Work layout: an "entity" (cell or face) is handled by NP = (p+1)^(d-1) consecutive threads,
 // EPB entities at a time per workgroup.  Thread t of an entity owns one pencil of p+1
@@ -91,20 +94,79 @@ __device__ __forceinline__ void lagrange_at(const double (&z)[N1], const double 
 // the p+1 outputs of x-run t (3D: t = i1 + N1 i2; 2D: t = i1).  A, B: this entity's
 // two (p+1)^d LDS tiles.  Contains barriers: every thread of the block must call it.
 // ------------------------------------------------------------------------------------
+// Even/odd pieces of a pencil: e_k = x_k + x_{p-k}, o_k = x_k - x_{p-k} (k < p+1 div 2),
+// plus the middle value when p+1 is odd.
+template <typename T, int N1>
+struct EvenOdd {
+  static constexpr int HC = (N1 + 1) / 2, HF = N1 / 2;
+  T e[HC], o[HF > 0 ? HF : 1];
+  __device__ __forceinline__ explicit EvenOdd(const T (&x)[N1]) {
+#pragma unroll
+    for (int k = 0; k < HF; ++k) {
+      e[k] = x[k] + x[N1 - 1 - k];
+      o[k] = x[k] - x[N1 - 1 - k];
+    }
+    if constexpr (N1 % 2 == 1) e[HF] = x[HF];
+  }
+};
+
+// ye += E e, yo += O o for one centrosymmetric matrix given by its even/odd parts.
+template <typename T, int N1>
+__device__ __forceinline__ void eo_acc(const T *E, const T *O, const EvenOdd<T, N1> &v, T (&ye)[(N1 + 1) / 2],
+                                       T (&yo)[N1 / 2 > 0 ? N1 / 2 : 1]) {
+  constexpr int HC = (N1 + 1) / 2, HF = N1 / 2;
+#pragma unroll
+  for (int i = 0; i < HC; ++i)
+#pragma unroll
+    for (int k = 0; k < HC; ++k) ye[i] += E[i * HC + k] * v.e[k];
+#pragma unroll
+  for (int i = 0; i < HF; ++i)
+#pragma unroll
+    for (int k = 0; k < HF; ++k) yo[i] += O[i * HF + k] * v.o[k];
+}
+
+// y_i = ye_i + yo_i, y_{p-i} = ye_i - yo_i (and the middle row), times s.
+template <typename T, int N1>
+__device__ __forceinline__ void eo_combine(const T (&ye)[(N1 + 1) / 2], const T (&yo)[N1 / 2 > 0 ? N1 / 2 : 1],
+                                           T s, T (&y)[N1]) {
+  constexpr int HF = N1 / 2;
+#pragma unroll
+  for (int i = 0; i < HF; ++i) {
+    y[i] = s * (ye[i] + yo[i]);
+    y[N1 - 1 - i] = s * (ye[i] - yo[i]);
+  }
+  if constexpr (N1 % 2 == 1) y[HF] = s * ye[HF];
+}
+
+template <typename T, int N1>
+struct EOAcc {
+  T ye[(N1 + 1) / 2], yo[N1 / 2 > 0 ? N1 / 2 : 1];
+  __device__ __forceinline__ EOAcc() {
+#pragma unroll
+    for (int i = 0; i < (N1 + 1) / 2; ++i) ye[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < (N1 / 2 > 0 ? N1 / 2 : 1); ++i) yo[i] = T(0);
+  }
+};
+
 template <typename T, int D, int N1>
 __device__ __forceinline__ void kron_cell(const KTab<T, N1> &tab, int t, const T (&x)[N1], T *A, T *B, T scale,
                                           T (&out)[N1]) {
   constexpr int NP = Shape<D, N1>::NP;
+  {
+    // last axis: a = M x, b = K x
+    const EvenOdd<T, N1> ex(x);
+    EOAcc<T, N1> ya, yb;
+    eo_acc<T, N1>(tab.EM, tab.OM, ex, ya.ye, ya.yo);
+    eo_acc<T, N1>(tab.EK, tab.OK, ex, yb.ye, yb.yo);
+    T a[N1], b[N1];
+    eo_combine<T, N1>(ya.ye, ya.yo, T(1), a);
+    eo_combine<T, N1>(yb.ye, yb.yo, T(1), b);
 #pragma unroll
-  for (int i = 0; i < N1; ++i) {
-    T a = 0, b = 0;
-#pragma unroll
-    for (int j = 0; j < N1; ++j) {
-      a += tab.M[i * N1 + j] * x[j];
-      b += tab.K[i * N1 + j] * x[j];
+    for (int i = 0; i < N1; ++i) {
+      A[t + NP * i] = a[i];
+      B[t + NP * i] = b[i];
     }
-    A[t + NP * i] = a;
-    B[t + NP * i] = b;
   }
   __syncthreads();
   if constexpr (D == 3) {
@@ -117,16 +179,18 @@ __device__ __forceinline__ void kron_cell(const KTab<T, N1> &tab, int t, const T
       b[j] = B[ix + N1 * j + NP * iz];
     }
     __syncthreads();
+    const EvenOdd<T, N1> ea(a), eb(b);
+    EOAcc<T, N1> yc, ye;
+    eo_acc<T, N1>(tab.EM, tab.OM, ea, yc.ye, yc.yo);
+    eo_acc<T, N1>(tab.EK, tab.OK, ea, ye.ye, ye.yo);
+    eo_acc<T, N1>(tab.EM, tab.OM, eb, ye.ye, ye.yo);
+    T c[N1], e[N1];
+    eo_combine<T, N1>(yc.ye, yc.yo, T(1), c);
+    eo_combine<T, N1>(ye.ye, ye.yo, T(1), e);
 #pragma unroll
     for (int i = 0; i < N1; ++i) {
-      T c = 0, e = 0;
-#pragma unroll
-      for (int j = 0; j < N1; ++j) {
-        c += tab.M[i * N1 + j] * a[j];
-        e += tab.K[i * N1 + j] * a[j] + tab.M[i * N1 + j] * b[j];
-      }
-      A[ix + N1 * i + NP * iz] = c;
-      B[ix + N1 * i + NP * iz] = e;
+      A[ix + N1 * i + NP * iz] = c[i];
+      B[ix + N1 * i + NP * iz] = e[i];
     }
     __syncthreads();
   }
@@ -137,13 +201,11 @@ __device__ __forceinline__ void kron_cell(const KTab<T, N1> &tab, int t, const T
     c[j] = A[j + N1 * t];
     e[j] = B[j + N1 * t];
   }
-#pragma unroll
-  for (int i = 0; i < N1; ++i) {
-    T o = 0;
-#pragma unroll
-    for (int j = 0; j < N1; ++j) o += tab.K[i * N1 + j] * c[j] + tab.M[i * N1 + j] * e[j];
-    out[i] = scale * o;
-  }
+  const EvenOdd<T, N1> ec(c), ee(e);
+  EOAcc<T, N1> yo;
+  eo_acc<T, N1>(tab.EK, tab.OK, ec, yo.ye, yo.yo);
+  eo_acc<T, N1>(tab.EM, tab.OM, ee, yo.ye, yo.yo);
+  eo_combine<T, N1>(yo.ye, yo.yo, scale, out);
 }
 
 // Thread t's input pencil (see kron_cell) gathered through the x-run bases of a CG cell.
@@ -255,16 +317,16 @@ __device__ __forceinline__ void face_interpolate(const KTab<T, N1> &tab, int t, 
 
 // ------------------------------------------------------------------------------------
 // One surrogate-boundary face (Alg. 3).  su: u_K in LDS (lexicographic), already synced.
-// Writes the face's contribution to all (p+1)^d local rows into sw.  xq: this face's
-// shifted reference points (NP x D doubles), used only when act.  Contains barriers.
+// Writes the face's contribution to all (p+1)^d local rows into sw.  xp: the shifted
+// reference point of this thread's face Gauss point t, used only when act.  Contains barriers.
 //   dn u   = (2s-1)/h d/dxi_a u at the face Gauss points (sum factorisation),
 //   E u    = u_K(xi_q), point evaluation with (p+1)^d terms per point,
 //   tested:  w_q (sigma E u - dn u) against v, -w_q E u against dn v.
 // ------------------------------------------------------------------------------------
 template <typename T, int D, int N1>
 __device__ __forceinline__ void sbm_face_eval(const KTab<T, N1> &tab, const KScal &sc, int t, bool act,
-                                              const FaceAxes<D, N1> &fa, const double *__restrict__ xq,
-                                              const T *su, T *sw, T *f1, T *f2, T *f3, T *f4) {
+                                              const FaceAxes<D, N1> &fa, const double (&xp)[D], const T *su,
+                                              T *sw, T *f1, T *f2, T *f3, T *f4) {
   constexpr int NP = Shape<D, N1>::NP, P = N1 - 1;
   const T h = T(sc.h), sig = T(sc.sigma_gamma);
   const T sgn = fa.s ? T(1) : T(-1);
@@ -284,7 +346,6 @@ __device__ __forceinline__ void sbm_face_eval(const KTab<T, N1> &tab, const KSca
 
   T eu = 0, om = 0;
   if (act) {
-    const double *xp = xq + t * D;
     double l[D][N1];
 #pragma unroll
     for (int k = 0; k < D; ++k) lagrange_at<N1>(tab.z, tab.cinv, xp[k], l[k]);
@@ -333,7 +394,7 @@ __device__ __forceinline__ void sbm_face_eval(const KTab<T, N1> &tab, const KSca
 // Brick description handed to the CG kernel.
 struct BrickArgs {
   const int32_t *cell_off;   // n_bricks + 1
-  const int32_t *cells;      // active cell ranks, grouped by brick
+  const int32_t *runs;       // run bases of the active cells ((p+1)^(d-1) each), grouped by brick
   const int32_t *cell_loc;   // lattice offset of each cell's corner inside its brick
   const int32_t *face_off;   // n_bricks + 1
   const int32_t *faces;      // surrogate-face indices, grouped by brick
@@ -347,93 +408,267 @@ struct BrickArgs {
 // ------------------------------------------------------------------------------------
 // CG brick kernel
 // ------------------------------------------------------------------------------------
-template <typename T, int D, int N1, int EPB, bool FACES>
-__global__ __launch_bounds__(256) void brick_kernel(int brick0, BrickArgs br, const int32_t *__restrict__ runs,
-                                                    const int32_t *__restrict__ face_cell,
-                                                    const int32_t *__restrict__ face_code,
-                                                    const double *__restrict__ face_xi, const T *__restrict__ u,
-                                                    T *__restrict__ v, T *__restrict__ halo, KTab<T, N1> tab,
-                                                    KScal sc, T scale, int parts) {
-  constexpr int P = N1 - 1, NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
-  constexpr int BX = BrickDims<D, P>::BX, BY = BrickDims<D, P>::BY, BZ = BrickDims<D, P>::BZ;
-  constexpr int LX = BX * P + 1, LY = BY * P + 1, LZ = (D == 3) ? BZ * P + 1 : 1;
-  constexpr int NL = LX * LY * LZ, NROWS = LY * LZ;
+// Geometry of the CG brick kernel for (D, P): lattice extents, block size (enough threads
+// for the longest set of lattice lines, at most 256 so that several workgroups share a CU),
+// cells per batch on the per-cell path, and the LDS size (the larger of the two paths,
+// which share one buffer).
+template <typename T, int D, int N1>
+struct BrickCfg {
+  static constexpr int P = N1 - 1, NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
+  static constexpr int BX = BrickDims<D, P>::BX, BY = BrickDims<D, P>::BY, BZ = BrickDims<D, P>::BZ;
+  static constexpr int LX = BX * P + 1, LY = BY * P + 1, LZ = (D == 3) ? BZ * P + 1 : 1;
+  static constexpr int NL = LX * LY * LZ, NROWS = LY * LZ;
+  static constexpr int LINES = (D == 3) ? ((LX * LY > LX * LZ ? LX * LY : LX * LZ) > LY * LZ
+                                               ? (LX * LY > LX * LZ ? LX * LY : LX * LZ)
+                                               : LY * LZ)
+                                        : (LX > LY ? LX : LY);
+  static constexpr int NT0 = ((LINES + 63) / 64) * 64;
+  static constexpr int NT = NT0 < 128 ? 128 : (NT0 > 256 ? 256 : NT0);
+  static constexpr int EPB0 = NT / NP;
+  static constexpr int EPB = EPB0 < 1 ? 1 : EPB0;   // cells per batch
+  static constexpr int NG = (NT + NP - 1) / NP;      // thread groups (the last may be partial)
+  static constexpr int SMEM = (2 * NL > NL + 2 * NG * NB) ? 2 * NL : NL + 2 * NG * NB;
+};
+
+// Lattice-line segments of a full brick.  A line of B cells has B p + 1 nodes; the segment of
+// cell j is nodes j p .. j p + p, and neighbouring segments share one node.  One lane per
+// segment, the B lanes of a line side by side in a group of G = pow2 >= B lanes of one
+// wavefront: each lane forms its cell's p + 1 outputs, takes the previous lane's last output
+// for its first node (the sum of both cells' rows there), and stores nodes j p .. j p + p - 1
+// (the last lane also node B p).  Every input is read before any lane of the line stores.
+template <int G, typename T>
+__device__ __forceinline__ T from_prev_lane(T y, int j) {
+  if constexpr (G == 1) {
+    return T(0);
+  } else {
+    const T w = __shfl_up(y, 1, G);
+    return j > 0 ? w : T(0);
+  }
+}
+
+template <int B>
+struct LaneGroup {
+  static constexpr int G = B <= 1 ? 1 : (B <= 2 ? 2 : (B <= 4 ? 4 : (B <= 8 ? 8 : 16)));
+  static_assert(B <= 16 && 64 % G == 0, "segment groups must tile a wavefront");
+};
+
+template <typename T, int D, int N1>
+__global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
+    BrickArgs br, const T *__restrict__ fbuf, const T *__restrict__ u,
+    T *__restrict__ v, T *__restrict__ halo, KTab<T, N1> tab, T scale, int parts) {
+  using C = BrickCfg<T, D, N1>;
+  constexpr int P = C::P, NP = C::NP, NB = C::NB, EPB = C::EPB;
+  constexpr int BX = C::BX, BY = C::BY, BZ = C::BZ, LX = C::LX, LY = C::LY, LZ = C::LZ;
+  constexpr int NL = C::NL, NROWS = C::NROWS;
   static_assert(LX <= 32, "row masks hold 32 points");
-  __shared__ T acc[NL];
-  __shared__ T sa[EPB * NB];
-  __shared__ T sb[EPB * NB];
-  __shared__ T fbuf[FACES ? 4 * EPB * NP : 4];
-  const int brick = brick0 + xcd_block();
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  __shared__ T smem[C::SMEM];
+  T *acc = smem;  // the brick lattice (both paths)
+  const int brick = xcd_block();
+  const int tid = threadIdx.x;
+  constexpr int nthr = C::NT;  // the launch uses exactly NT threads
   const int le = tid / NP, t = tid - le * NP;
-  T *A = sa + le * NB, *B = sb + le * NB;
-  T *f1 = fbuf + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
+  const int64_t rb = (int64_t)brick * NROWS;
   // lattice offset of thread t's x-run inside a cell tile
   const int run_off = (D == 3) ? (t % N1) * LX + (t / N1) * LX * LY : t * LX;
-
-  for (int i = tid; i < NL; i += nthr) acc[i] = T(0);
+  const int c0 = br.cell_off[brick], c1 = br.cell_off[brick + 1];
+  const bool full = (c1 - c0) == BX * BY * BZ;
+  // the brick's row descriptors, staged once: every later lattice access indexes them
+  __shared__ int32_t s_base[NROWS], s_hbase[NROWS];
+  __shared__ uint32_t s_gmask[NROWS], s_bmask[NROWS];
+  for (int r = tid; r < NROWS; r += nthr) {
+    s_base[r] = br.row_base[rb + r];
+    s_hbase[r] = br.row_hbase[rb + r];
+    s_gmask[r] = br.row_gmask[rb + r];
+    s_bmask[r] = br.row_bmask[rb + r];
+  }
   __syncthreads();
 
-  if (parts & SBM_PART_CELLS) {
-    const int c0 = br.cell_off[brick], c1 = br.cell_off[brick + 1];
+  if (full && (parts & SBM_PART_CELLS)) {
+    // ---- full brick: the sum of the cell operators over a tensor-product block of cells is
+    // the Kronecker sum of the 1D operators assembled along each direction; sweep the
+    // brick lattice line by line (a = M u, b = K u along the last axis, then c = M a,
+    // e = K a + M b, then h (K c + M e)), in place in LDS. ----
+    T *LA = smem, *LB = smem + NL;
+    // last axis (z in 3D, y in 2D): a = M u, b = K u, gathered from u (every point of a full
+    // brick is a DoF: id = row base + x)
+    {
+      constexpr int NC = (D == 3) ? BZ : BY, G = LaneGroup<NC>::G;
+      constexpr int NLINE = (D == 3) ? LX * LY : LX;
+      for (int q = tid; q < NLINE * G; q += nthr) {
+        const int j = q % G, line = q / G;
+        const int x = line % LX, y = (D == 3) ? line / LX : 0;
+        const bool live = j < NC;
+        T xu[N1], ya[N1], yb[N1];
+#pragma unroll
+        for (int i = 0; i < N1; ++i) {
+          const int row = (D == 3) ? y + LY * (j * P + i) : (j * P + i);
+          xu[i] = live ? u[s_base[row] + x] : T(0);
+        }
+        {
+          const EvenOdd<T, N1> ex(xu);
+          EOAcc<T, N1> aa, ab;
+          eo_acc<T, N1>(tab.EM, tab.OM, ex, aa.ye, aa.yo);
+          eo_acc<T, N1>(tab.EK, tab.OK, ex, ab.ye, ab.yo);
+          eo_combine<T, N1>(aa.ye, aa.yo, T(1), ya);
+          eo_combine<T, N1>(ab.ye, ab.yo, T(1), yb);
+        }
+        ya[0] += from_prev_lane<G>(ya[P], j);
+        yb[0] += from_prev_lane<G>(yb[P], j);
+        if (live) {
+          const int pt0 = (D == 3) ? x + LX * (y + LY * (j * P)) : x + LX * (j * P);
+          constexpr int SL = (D == 3) ? LX * LY : LX;
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            LA[pt0 + i * SL] = ya[i];
+            LB[pt0 + i * SL] = yb[i];
+          }
+          if (j == NC - 1) {
+            LA[pt0 + P * SL] = ya[P];
+            LB[pt0 + P * SL] = yb[P];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if constexpr (D == 3) {
+      // y: c = M a, e = K a + M b, in place
+      constexpr int G = LaneGroup<BY>::G;
+      for (int q = tid; q < LX * LZ * G; q += nthr) {
+        const int j = q % G, line = q / G;
+        const int x = line % LX, z = line / LX;
+        const bool live = j < BY;
+        const int o = x + LX * LY * z + j * P * LX;
+        T xa[N1], xb[N1], yc[N1], ye[N1];
+#pragma unroll
+        for (int i = 0; i < N1; ++i) {
+          xa[i] = live ? LA[o + i * LX] : T(0);
+          xb[i] = live ? LB[o + i * LX] : T(0);
+        }
+        {
+          const EvenOdd<T, N1> ea(xa), eb(xb);
+          EOAcc<T, N1> ac, ae;
+          eo_acc<T, N1>(tab.EM, tab.OM, ea, ac.ye, ac.yo);
+          eo_acc<T, N1>(tab.EK, tab.OK, ea, ae.ye, ae.yo);
+          eo_acc<T, N1>(tab.EM, tab.OM, eb, ae.ye, ae.yo);
+          eo_combine<T, N1>(ac.ye, ac.yo, T(1), yc);
+          eo_combine<T, N1>(ae.ye, ae.yo, T(1), ye);
+        }
+        yc[0] += from_prev_lane<G>(yc[P], j);
+        ye[0] += from_prev_lane<G>(ye[P], j);
+        if (live) {
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            LA[o + i * LX] = yc[i];
+            LB[o + i * LX] = ye[i];
+          }
+          if (j == BY - 1) {
+            LA[o + P * LX] = yc[P];
+            LB[o + P * LX] = ye[P];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // x: out = h (K c + M e), written over c
+    {
+      constexpr int G = LaneGroup<BX>::G;
+      for (int q = tid; q < NROWS * G; q += nthr) {
+        const int j = q % G, row = q / G;
+        const bool live = j < BX;
+        const int o = LX * row + j * P;
+        T xc[N1], xe[N1], yo[N1];
+#pragma unroll
+        for (int i = 0; i < N1; ++i) {
+          xc[i] = live ? LA[o + i] : T(0);
+          xe[i] = live ? LB[o + i] : T(0);
+        }
+        {
+          const EvenOdd<T, N1> ec(xc), ee(xe);
+          EOAcc<T, N1> ao;
+          eo_acc<T, N1>(tab.EK, tab.OK, ec, ao.ye, ao.yo);
+          eo_acc<T, N1>(tab.EM, tab.OM, ee, ao.ye, ao.yo);
+          eo_combine<T, N1>(ao.ye, ao.yo, scale, yo);
+        }
+        yo[0] += from_prev_lane<G>(yo[P], j);
+        if (live) {
+#pragma unroll
+          for (int i = 0; i < P; ++i) LA[o + i] = yo[i];
+          if (j == BX - 1) LA[o + P] = yo[P];
+        }
+      }
+    }
+    __syncthreads();
+  } else {
+    for (int i = tid; i < NL; i += nthr) acc[i] = T(0);
+    __syncthreads();
+  }
+
+  if (!full && (parts & SBM_PART_CELLS)) {
+    // ---- partial brick: cell by cell (EPB cells per batch; a trailing group of fewer than
+    // NP threads only takes part in the barriers) ----
+    constexpr int NG = C::NG;
+    T *A = smem + NL + le * NB, *B = smem + NL + NG * NB + le * NB;
+    const bool grp = le < EPB;
+    // software pipeline: the pencils of batch b+1 are in flight while batch b computes
+    T x[N1];
+    {
+      const bool act = grp && c0 + le < c1;
+      gather_pencil<T, D, N1>(br.runs + (int64_t)(act ? c0 + le : 0) * NP, u, t, act, x);
+    }
     for (int b = c0; b < c1; b += EPB) {
       const int idx = b + le;
-      const bool act = idx < c1;
-      const int cell = act ? br.cells[idx] : 0;
+      const bool act = grp && idx < c1;
       const int loc = act ? br.cell_loc[idx] : 0;
-      T x[N1], out[N1];
-      gather_pencil<T, D, N1>(runs + (int64_t)cell * NP, u, t, act, x);
+      const int idn = idx + EPB;
+      const bool actn = grp && idn < c1;
+      T xn[N1], out[N1];
+      gather_pencil<T, D, N1>(br.runs + (int64_t)(actn ? idn : 0) * NP, u, t, actn, xn);
       kron_cell<T, D, N1>(tab, t, x, A, B, scale, out);
       if (act) {
 #pragma unroll
         for (int i = 0; i < N1; ++i) atomicAdd(&acc[loc + run_off + i], out[i]);
       }
+#pragma unroll
+      for (int i = 0; i < N1; ++i) x[i] = xn[i];
       __syncthreads();
     }
   }
-  if (FACES && (parts & SBM_PART_SBM_FACES)) {
+  if (parts & SBM_PART_SBM_FACES) {
+    // the brick's surrogate faces were evaluated by sbm_face_kernel into fbuf (one tile of
+    // (p+1)^d local rows per face); add them to the lattice
     const int f0 = br.face_off[brick], f1e = br.face_off[brick + 1];
     for (int b = f0; b < f1e; b += EPB) {
       const int idx = b + le;
-      const bool act = idx < f1e;
-      const int f = act ? br.faces[idx] : 0;
-      const int loc = act ? br.face_loc[idx] : 0;
-      const int cell = act ? face_cell[f] : 0;
-      const FaceAxes<D, N1> fa(act ? face_code[f] : 0);
-      if (act) {
-        const T *up = u + runs[(int64_t)cell * NP + t];
+      if (le < EPB && idx < f1e) {
+        const int f = br.faces[idx];
+        const int loc = br.face_loc[idx];
+        const T *fp = fbuf + (int64_t)f * NB + N1 * t;
 #pragma unroll
-        for (int i = 0; i < N1; ++i) A[N1 * t + i] = up[i];
+        for (int i = 0; i < N1; ++i) atomicAdd(&acc[loc + run_off + i], fp[i]);
       }
-      __syncthreads();
-      sbm_face_eval<T, D, N1>(tab, sc, t, act, fa, face_xi + (int64_t)f * NP * D, A, B, f1, f2, f3, f4);
-      __syncthreads();
-      if (act) {
-#pragma unroll
-        for (int i = 0; i < N1; ++i) atomicAdd(&acc[loc + run_off + i], B[N1 * t + i]);
-      }
-      __syncthreads();
     }
   }
   __syncthreads();
   // write-out: lanes walk the lattice with x fastest, so stores are row-contiguous.
   // Points strictly inside the brick box belong to this brick alone: final value.  Points
   // on the box boundary go to their halo slot; halo_reduce_kernel adds the slots up.
-  const int64_t rb = (int64_t)brick * NROWS;
-  for (int pt = tid; pt < NL; pt += nthr) {
-    const int x = pt % LX, row = pt / LX;
-    const uint32_t bm = br.row_bmask[rb + row];
-    if (!((bm >> x) & 1u)) continue;
+  // Unrolled over the thread's points so that all LDS reads issue back to back; the stores
+  // are predicated.
+  constexpr int NIT = (NL + C::NT - 1) / C::NT;
+#pragma unroll
+  for (int k = 0; k < NIT; ++k) {
+    const int pt = tid + k * C::NT;
+    const int ptc = pt < NL ? pt : 0;
+    const int x = ptc % LX, row = ptc / LX;
+    const uint32_t bm = s_bmask[row];
     const uint32_t below = (1u << x) - 1u;
     const int y = row % LY, z = row / LY;
     const bool brow = y == 0 || y == LY - 1 || (D == 3 && (z == 0 || z == LZ - 1));
-    if (!brow && x > 0 && x < LX - 1) {
-      const uint32_t gm = br.row_gmask[rb + row];
-      v[br.row_base[rb + row] + __popc(gm & below)] = acc[pt];
-    } else {
-      const uint32_t hm = brow ? bm : (bm & (1u | (1u << (LX - 1))));
-      halo[br.row_hbase[rb + row] + __popc(hm & below)] = acc[pt];
-    }
+    const bool inner = !brow && x > 0 && x < LX - 1;
+    const uint32_t hm = brow ? bm : (bm & (1u | (1u << (LX - 1))));
+    T *dst = inner ? v + s_base[row] + __popc(s_gmask[row] & below) : halo + s_hbase[row] + __popc(hm & below);
+    const T val = acc[ptc];
+    if (pt < NL && ((bm >> x) & 1u)) *dst = val;
   }
 }
 
@@ -451,14 +686,17 @@ __global__ __launch_bounds__(256) void halo_reduce_kernel(int n, const int32_t *
 }
 
 // ------------------------------------------------------------------------------------
-// DG surrogate-boundary faces: one entity = one face; atomics into the cell block.
+// Surrogate-boundary faces: one entity = one face.  DG: atomics into the cell block of v.
+// CG: runs holds the run bases of each face's cell ((p+1)^(d-1) per face); the face's
+// (p+1)^d local results are stored to out = fbuf[f] (no conflicts); brick_kernel adds them
+// into its lattice.
 // ------------------------------------------------------------------------------------
-template <typename T, int D, int N1, int EPB>
+template <typename T, int D, int N1, int EPB, bool CG>
 __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_t *__restrict__ face_cell,
                                                        const int32_t *__restrict__ face_code,
                                                        const double *__restrict__ face_xi,
-                                                       const T *__restrict__ u, T *__restrict__ v,
-                                                       KTab<T, N1> tab, KScal sc) {
+                                                       const int32_t *__restrict__ runs, const T *__restrict__ u,
+                                                       T *__restrict__ out, KTab<T, N1> tab, KScal sc) {
   constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
   __shared__ T su_all[EPB * NB];
   __shared__ T sw_all[EPB * NB];
@@ -469,20 +707,33 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
   T *su = su_all + le * NB;
   T *sw = sw_all + le * NB;
   T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
-  const int cell = act ? face_cell[f] : 0;
+  // every load that does not depend on another is issued up front
+  double xp[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xp[k] = act ? face_xi[((int64_t)f * NP + t) * D + k] : 0.0;
   const FaceAxes<D, N1> fa(act ? face_code[f] : 0);
-  const int64_t base = (int64_t)cell * NB + N1 * t;
+  int64_t base;
+  if constexpr (CG) {
+    base = act ? (int64_t)runs[(int64_t)f * NP + t] : 0;  // runs: run bases of the face's cell
+  } else {
+    base = (int64_t)(act ? face_cell[f] : 0) * NB + N1 * t;
+  }
   if (act) {
 #pragma unroll
     for (int i = 0; i < N1; ++i) su[N1 * t + i] = u[base + i];
   }
   __syncthreads();
-  sbm_face_eval<T, D, N1>(tab, sc, t, act, fa, face_xi + (int64_t)(act ? f : 0) * NP * D, su, sw, f1, f2, f3,
-                          f4);
+  sbm_face_eval<T, D, N1>(tab, sc, t, act, fa, xp, su, sw, f1, f2, f3, f4);
   __syncthreads();
   if (act) {
+    if constexpr (CG) {
+      T *op = out + (int64_t)f * NB + N1 * t;
 #pragma unroll
-    for (int i = 0; i < N1; ++i) atomic_add(v + base + i, sw[N1 * t + i]);
+      for (int i = 0; i < N1; ++i) op[i] = sw[N1 * t + i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < N1; ++i) atomic_add(out + base + i, sw[N1 * t + i]);
+    }
   }
 }
 
@@ -584,6 +835,17 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
 template <typename T, int N1>
 KTab<T, N1> make_ktab(const Rules1D &r) {
   KTab<T, N1> k;
+  constexpr int HC = (N1 + 1) / 2, HF = N1 / 2, P = N1 - 1;
+  const std::vector<double> *mats[2] = {&r.M, &r.K};
+  T *E[2] = {k.EM, k.EK}, *O[2] = {k.OM, k.OK};
+  for (int m = 0; m < 2; ++m) {
+    const std::vector<double> &A = *mats[m];
+    for (int i = 0; i < HC; ++i)
+      for (int c = 0; c < HC; ++c)
+        E[m][i * HC + c] = T(c < HF ? 0.5 * (A[i * N1 + c] + A[i * N1 + (P - c)]) : A[i * N1 + c]);
+    for (int i = 0; i < HF; ++i)
+      for (int c = 0; c < HF; ++c) O[m][i * HF + c] = T(0.5 * (A[i * N1 + c] - A[i * N1 + (P - c)]));
+  }
   for (int i = 0; i < N1 * N1; ++i) {
     k.M[i] = T(r.M[i]);
     k.K[i] = T(r.K[i]);
@@ -608,20 +870,20 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
   const int nc = (int)c->n_cells, nf = (int)c->n_sbm;
   if (c->disc == SBM_CG) {
     if (c->n_bricks > 0 && (parts & (SBM_PART_CELLS | SBM_PART_SBM_FACES))) {
-      constexpr int P = N1 - 1;
-      constexpr int NL = (BrickDims<D, P>::BX * P + 1) * (BrickDims<D, P>::BY * P + 1) *
-                         ((D == 3) ? BrickDims<D, P>::BZ * P + 1 : 1);
-      constexpr int E = epb<T, D, N1, 2, NL>();
-      const BrickArgs br{c->d_brick_cell_off, c->d_brick_cells,    c->d_brick_cell_loc,
+      constexpr int NT = BrickCfg<T, D, N1>::NT;
+      const BrickArgs br{c->d_brick_cell_off, c->d_brick_runs,     c->d_brick_cell_loc,
                          c->d_brick_face_off, c->d_brick_faces,    c->d_brick_face_loc,
                          c->d_row_base,       c->d_row_gmask,      c->d_row_bmask,
                          c->d_row_hbase};
       T *halo = (T *)c->d_halo;
-      // one launch over all bricks (splitting face-free bricks into a leaner launch
-      // serialises the two halves and measured slower)
-      hipLaunchKernelGGL((brick_kernel<T, D, N1, E, true>), dim3((unsigned)c->n_bricks), dim3(E * NP), 0, s, 0, br,
-                         c->d_runs, c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, halo, tab, sc, scale,
-                         parts);
+      T *fbuf = (T *)c->d_fbuf;
+      if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
+        constexpr int EF = epb<T, D, N1, 2, 0>();
+        hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, EF, true>), dim3((nf + EF - 1) / EF), dim3(EF * NP), 0, s,
+                           nf, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_face_runs, u, fbuf, tab, sc);
+      }
+      hipLaunchKernelGGL((brick_kernel<T, D, N1>), dim3((unsigned)c->n_bricks), dim3(NT), 0, s, br,
+                         (const T *)fbuf, u, v, halo, tab, scale, parts);
       if (c->n_halo_dofs > 0 && !(parts & SBM_PART_NO_ASSEMBLY)) {
         const int nh = (int)c->n_halo_dofs;
         hipLaunchKernelGGL(halo_reduce_kernel<T>, dim3((nh + 255) / 256), dim3(256), 0, s, nh, c->d_halo_dof,
@@ -636,8 +898,8 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
     }
     if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
       constexpr int E = epb<T, D, N1, 2, 0>();
-      hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s, nf,
-                         c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
+      hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E, false>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s, nf,
+                         c->d_face_cell, c->d_face_code, c->d_face_xi, (const int32_t *)nullptr, u, v, tab, sc);
     }
   }
   return hipGetLastError();

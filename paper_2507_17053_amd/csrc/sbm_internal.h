@@ -46,6 +46,12 @@ struct LevelSet {
 // segment; all table indices in the kernels are compile-time constants after unrolling).
 template <typename T, int N1>
 struct KTab {
+  // M and K are centrosymmetric (symmetric node set), so y = A x splits into an even part
+  // (E, on e_k = x_k + x_{p-k} and the middle value) and an odd part (O, on
+  // o_k = x_k - x_{p-k}): y_i = ye_i + yo_i, y_{p-i} = ye_i - yo_i.
+  static constexpr int HC = (N1 + 1) / 2, HF = N1 / 2;
+  T EM[HC * HC], OM[HF * HF];
+  T EK[HC * HC], OK[HF * HF];
   T M[N1 * N1];
   T K[N1 * N1];
   T N[N1 * N1];
@@ -89,8 +95,10 @@ struct sbm_ctx {
   // CG bricks: BX x BY x BZ blocks of background cells, one workgroup each
   int brick[3] = {1, 1, 1};
   int64_t n_bricks = 0;
-  int64_t n_bricks_plain = 0;  // bricks [0, n_bricks_plain) have no surrogate faces
+  int64_t n_bricks_faces = 0;  // bricks [0, n_bricks_faces) carry surrogate faces
   std::vector<int32_t> brick_cell_off, brick_cells, brick_cell_loc;
+  std::vector<int32_t> brick_runs;  // run bases of the cells in brick order (n_cells x (p+1)^(d-1))
+  std::vector<int32_t> face_runs;   // run bases of each surrogate face's cell (n_sbm x (p+1)^(d-1))
   std::vector<int32_t> brick_face_off, brick_faces, brick_face_loc;
   std::vector<int32_t> row_base, row_hbase;
   std::vector<uint32_t> row_gmask, row_bmask;
@@ -99,7 +107,9 @@ struct sbm_ctx {
   std::vector<int32_t> halo_dof, halo_off, halo_slot;
   int32_t *d_row_hbase = nullptr, *d_halo_dof = nullptr, *d_halo_off = nullptr, *d_halo_slot = nullptr;
   void *d_halo = nullptr;  // n_halo_slots doubles (also used as floats); per-handle scratch
-  int32_t *d_brick_cell_off = nullptr, *d_brick_cells = nullptr, *d_brick_cell_loc = nullptr;
+  void *d_fbuf = nullptr;  // CG: n_sbm x (p+1)^d doubles, surrogate-face results; per-handle scratch
+  int32_t *d_brick_cell_off = nullptr, *d_brick_runs = nullptr, *d_brick_cell_loc = nullptr;
+  int32_t *d_face_runs = nullptr;
   int32_t *d_brick_face_off = nullptr, *d_brick_faces = nullptr, *d_brick_face_loc = nullptr;
   int32_t *d_row_base = nullptr;
   uint32_t *d_row_gmask = nullptr, *d_row_bmask = nullptr;

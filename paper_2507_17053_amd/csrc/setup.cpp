@@ -423,7 +423,8 @@ static void free_device(sbm_ctx *c) {
   free_ptr(c->d_face_code);
   free_ptr(c->d_face_xi);
   free_ptr(c->d_brick_cell_off);
-  free_ptr(c->d_brick_cells);
+  free_ptr(c->d_brick_runs);
+  free_ptr(c->d_face_runs);
   free_ptr(c->d_brick_cell_loc);
   free_ptr(c->d_brick_face_off);
   free_ptr(c->d_brick_faces);
@@ -436,6 +437,7 @@ static void free_device(sbm_ctx *c) {
   free_ptr(c->d_halo_off);
   free_ptr(c->d_halo_slot);
   free_ptr(c->d_halo);
+  free_ptr(c->d_fbuf);
 }
 
 // CG bricks: group the active cells into blocks of BX x BY x BZ background cells (one
@@ -463,8 +465,10 @@ static void build_bricks(sbm_ctx *c, const std::vector<int32_t> &id, int64_t lx,
     bkey[r] = (bz * nby + cc[1] / BY) * nbx + cc[0] / BX;
     ++count[bkey[r]];
   }
-  // Bricks without surrogate faces are numbered first (lexicographic), then those with
-  // faces, so that each group runs as its own specialised launch.
+  // Bricks with surrogate faces are numbered first (lexicographic), then those without:
+  // the dispatcher starts workgroups in order, and the face-carrying bricks (partial, cell by
+  // cell, plus their faces) are the slow ones, so they start early and the launch ends on
+  // short work.
   std::vector<int32_t> fcount(count.size(), 0);
   for (int64_t f = 0; f < c->n_sbm; ++f) ++fcount[bkey[c->faces[3 * f]]];
   std::vector<int32_t> bid(count.size(), -1);
@@ -472,14 +476,14 @@ static void build_bricks(sbm_ctx *c, const std::vector<int32_t> &id, int64_t lx,
   int32_t nb = 0;
   for (int pass = 0; pass < 2; ++pass)
     for (size_t k = 0; k < count.size(); ++k)
-      if (count[k] > 0 && ((fcount[k] > 0) == (pass == 1))) {
+      if (count[k] > 0 && ((fcount[k] > 0) == (pass == 0))) {
         bid[k] = nb++;
         key_of.push_back((int64_t)k);
       }
   c->n_bricks = nb;
-  c->n_bricks_plain = 0;
+  c->n_bricks_faces = 0;
   for (size_t k = 0; k < count.size(); ++k)
-    if (count[k] > 0 && fcount[k] == 0) ++c->n_bricks_plain;
+    if (count[k] > 0 && fcount[k] > 0) ++c->n_bricks_faces;
   auto cell_loc = [&](int64_t r, int64_t key) {
     const int32_t *cc = &c->cells[r * d];
     const int64_t bx = key % nbx, by = (key / nbx) % nby, bz = key / (nbx * nby);
@@ -500,6 +504,17 @@ static void build_bricks(sbm_ctx *c, const std::vector<int32_t> &id, int64_t lx,
       ++fill[b];
     }
   }
+  // run bases of the cells in brick order (the kernel reads them without the cell rank)
+  const int npr = (d == 3) ? (p + 1) * (p + 1) : (p + 1);
+  c->brick_runs.resize((size_t)nc * npr);
+  for (int64_t i = 0; i < nc; ++i)
+    std::copy(c->runs.begin() + (size_t)c->brick_cells[i] * npr, c->runs.begin() + (size_t)(c->brick_cells[i] + 1) * npr,
+              c->brick_runs.begin() + (size_t)i * npr);
+  // and of each surrogate face's cell
+  c->face_runs.resize((size_t)c->n_sbm * npr);
+  for (int64_t f = 0; f < c->n_sbm; ++f)
+    std::copy(c->runs.begin() + (size_t)c->faces[3 * f] * npr, c->runs.begin() + (size_t)(c->faces[3 * f] + 1) * npr,
+              c->face_runs.begin() + (size_t)f * npr);
   const int64_t nf = c->n_sbm;
   c->brick_face_off.assign(nb + 1, 0);
   for (int64_t f = 0; f < nf; ++f) ++c->brick_face_off[bid[bkey[c->faces[3 * f]]] + 1];
@@ -902,7 +917,8 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
   if (c->disc == SBM_CG) {
     e = upload(&c->d_runs, c->runs, bytes);
     if (e == hipSuccess) e = upload(&c->d_brick_cell_off, c->brick_cell_off, bytes);
-    if (e == hipSuccess) e = upload(&c->d_brick_cells, c->brick_cells, bytes);
+    if (e == hipSuccess) e = upload(&c->d_brick_runs, c->brick_runs, bytes);
+    if (e == hipSuccess) e = upload(&c->d_face_runs, c->face_runs, bytes);
     if (e == hipSuccess) e = upload(&c->d_brick_cell_loc, c->brick_cell_loc, bytes);
     if (e == hipSuccess) e = upload(&c->d_brick_face_off, c->brick_face_off, bytes);
     if (e == hipSuccess) e = upload(&c->d_brick_faces, c->brick_faces, bytes);
@@ -917,6 +933,11 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
     if (e == hipSuccess && c->n_halo_slots > 0) {
       e = hipMalloc(&c->d_halo, (size_t)c->n_halo_slots * sizeof(double));
       bytes += (size_t)c->n_halo_slots * sizeof(double);
+    }
+    if (e == hipSuccess && c->n_sbm > 0) {
+      const size_t fb = (size_t)c->n_sbm * c->nb * sizeof(double);
+      e = hipMalloc(&c->d_fbuf, fb);
+      bytes += fb;
     }
   }
   if (e == hipSuccess && c->disc == SBM_DG) e = upload(&c->d_nbr, c->nbr, bytes);
@@ -1100,7 +1121,14 @@ size_t sbm_footprint_estimate(const sbm_mesh *mesh, int p, int disc, int64_t n_c
   const int64_t nc = n_cells_hint;
   const int64_t ndofs = (disc == SBM_CG) ? nc * (int64_t)std::pow((double)p, d) + 3 * np * nc / n1 : nc * nb;
   size_t b = 0;
-  b += (disc == SBM_CG) ? 4 * nc * np : 4 * nc * 2 * d;
+  if (disc == SBM_CG) {
+    // run bases (cell order and brick order), per-face run bases and face results, halo slots
+    // (at most about one per DoF), brick row descriptors (16 bytes per lattice row, about
+    // (p+1) rows per cell)
+    b += 8 * nc * np + n_faces_hint * (4 * np + 8 * nb) + 8 * ndofs + 16 * nc * n1 * (d == 3 ? n1 : 1);
+  } else {
+    b += 4 * nc * 2 * d;
+  }
   b += n_faces_hint * (8 + np * d * 8);
   return b + (size_t)ndofs * 8;
 }
