@@ -3,12 +3,11 @@
 //   brick_kernel    CG: one workgroup per brick of BX x BY x BZ background cells.  The
 //                   brick's active cells (Alg. 1) are evaluated into an LDS copy of the
 //                   brick's DoF lattice (a brick whose cells are all active by 1D line
-//                   sweeps over the whole lattice, others cell by cell), its surrogate-face
-//                   results are added; points strictly inside the brick are then stored to
-//                   v directly, points on the brick's boundary (shared with neighbouring
-//                   bricks) go to halo slots that halo_reduce_kernel sums.
-//   sbm_face_kernel Surrogate-boundary faces (Alg. 3).  CG: per-face results to a buffer
-//                   that brick_kernel adds; DG: atomics into the cell blocks.
+//                   sweeps over the whole lattice, others cell by cell), then its
+//                   surrogate-boundary faces (Alg. 3); points strictly inside the brick are
+//                   then stored to v directly, points on the brick's boundary (shared with
+//                   neighbouring bricks) go to halo slots that halo_reduce_kernel sums.
+//   sbm_face_kernel DG surrogate-boundary faces (Alg. 3), atomics into the cell blocks.
 //   dg_cell_kernel  DG: Laplace cell term plus the SIPG terms of the cell's interior faces,
 //                   evaluated cell by cell (Alg. 2 split per side); every cell writes only
 //                   its own block.
@@ -317,8 +316,9 @@ __device__ __forceinline__ void face_interpolate(const KTab<T, N1> &tab, int t, 
 
 // ------------------------------------------------------------------------------------
 // One surrogate-boundary face (Alg. 3).  su: u_K in LDS (lexicographic), already synced.
-// Writes the face's contribution to all (p+1)^d local rows into sw.  xp: the shifted
-// reference point of this thread's face Gauss point t, used only when act.  Contains barriers.
+// Returns Rv, Rg at this thread's face node t (face_row turns them into the (p+1)^d local
+// rows).  xp: the shifted reference point of face Gauss point t, used only when act.
+// f1..f4: NP values each of scratch.  Contains barriers.
 //   dn u   = (2s-1)/h d/dxi_a u at the face Gauss points (sum factorisation),
 //   E u    = u_K(xi_q), point evaluation with (p+1)^d terms per point,
 //   tested:  w_q (sigma E u - dn u) against v, -w_q E u against dn v.
@@ -326,10 +326,10 @@ __device__ __forceinline__ void face_interpolate(const KTab<T, N1> &tab, int t, 
 template <typename T, int D, int N1>
 __device__ __forceinline__ void sbm_face_eval(const KTab<T, N1> &tab, const KScal &sc, int t, bool act,
                                               const FaceAxes<D, N1> &fa, const double (&xp)[D], const T *su,
-                                              T *sw, T *f1, T *f2, T *f3, T *f4) {
-  constexpr int NP = Shape<D, N1>::NP, P = N1 - 1;
+                                              T *f1, T *f2, T *f3, T *f4, T &Rv, T &Rg) {
+  constexpr int NP = Shape<D, N1>::NP;
   const T h = T(sc.h), sig = T(sc.sigma_gamma);
-  const T sgn = fa.s ? T(1) : T(-1);
+  const T sh = (fa.s ? T(1) : T(-1)) / h;  // normal sign over h
   const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
   const int node_off = jb * fa.Sb + jc * fa.Sc;
   {
@@ -342,7 +342,7 @@ __device__ __forceinline__ void sbm_face_eval(const KTab<T, N1> &tab, const KSca
   __syncthreads();
   T dn, dn2;
   face_interpolate<T, D, N1>(tab, t, f1, f2, f3, f4, dn, dn2);
-  dn *= sgn / h;
+  dn *= sh;
 
   T eu = 0, om = 0;
   if (act) {
@@ -382,13 +382,17 @@ __device__ __forceinline__ void sbm_face_eval(const KTab<T, N1> &tab, const KSca
   }
   __syncthreads();  // f3/f4 reads of face_interpolate are done
   f3[t] = om * (sig * eu - dn);  // tested against v
-  f4[t] = -om * eu * sgn / h;    // tested against the reference derivative along a
+  f4[t] = -om * eu * sh;         // tested against the reference derivative along a
   __syncthreads();
-  T Rv, Rg;
   face_integrate<T, D, N1>(tab, t, f1, f2, f3, f4, Rv, Rg);
-#pragma unroll
-  for (int ia = 0; ia < N1; ++ia)
-    sw[ia * fa.Sa + node_off] = ((ia == fa.s * P) ? Rv : T(0)) + (fa.s ? tab.D1[ia] : tab.D0[ia]) * Rg;
+}
+
+// The face's result for the local row at position ia along the face normal, at this
+// thread's face node: Rv on the face itself (ia = s p), plus Rg times the normal derivative
+// of the 1D basis function ia at the face.
+template <typename T, int D, int N1>
+__device__ __forceinline__ T face_row(const KTab<T, N1> &tab, const FaceAxes<D, N1> &fa, int ia, T Rv, T Rg) {
+  return ((ia == fa.s * (N1 - 1)) ? Rv : T(0)) + (fa.s ? tab.D1[ia] : tab.D0[ia]) * Rg;
 }
 
 // Brick description handed to the CG kernel.
@@ -396,9 +400,10 @@ struct BrickArgs {
   const int32_t *cell_off;   // n_bricks + 1
   const int32_t *runs;       // run bases of the active cells ((p+1)^(d-1) each), grouped by brick
   const int32_t *cell_loc;   // lattice offset of each cell's corner inside its brick
+  // surrogate faces, numbered in brick order (a brick's faces are face_off[b] .. face_off[b+1])
   const int32_t *face_off;   // n_bricks + 1
-  const int32_t *faces;      // surrogate-face indices, grouped by brick
   const int32_t *face_loc;   // lattice offset of each face's cell inside its brick
+  const int32_t *face_code;  // per face: 2 axis + side
   const int32_t *row_base;   // n_bricks x rows: DoF id of the first globally present point
   const uint32_t *row_gmask; // bit x: lattice point x of the row is a DoF
   const uint32_t *row_bmask; // bit x: ... and is touched by an active cell of this brick
@@ -454,8 +459,8 @@ struct LaneGroup {
 
 template <typename T, int D, int N1>
 __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
-    BrickArgs br, const T *__restrict__ fbuf, const T *__restrict__ u,
-    T *__restrict__ v, T *__restrict__ halo, KTab<T, N1> tab, T scale, int parts) {
+    BrickArgs br, const T *__restrict__ fbuf, const T *__restrict__ u, T *__restrict__ v, T *__restrict__ halo,
+    KTab<T, N1> tab, T scale, int parts) {
   using C = BrickCfg<T, D, N1>;
   constexpr int P = C::P, NP = C::NP, NB = C::NB, EPB = C::EPB;
   constexpr int BX = C::BX, BY = C::BY, BZ = C::BZ, LX = C::LX, LY = C::LY, LZ = C::LZ;
@@ -634,17 +639,25 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     }
   }
   if (parts & SBM_PART_SBM_FACES) {
-    // the brick's surrogate faces were evaluated by sbm_face_kernel into fbuf (one tile of
-    // (p+1)^d local rows per face); add them to the lattice
+    // ---- the brick's surrogate faces: sbm_face_cg_kernel left (Rv, Rg) per face node in
+    // fbuf; expand them into the (p+1)^d local rows and add those into the lattice ----
     const int f0 = br.face_off[brick], f1e = br.face_off[brick + 1];
+    constexpr int SL1 = LX, SL2 = LX * LY;  // lattice strides of axes 1 and 2
     for (int b = f0; b < f1e; b += EPB) {
-      const int idx = b + le;
-      if (le < EPB && idx < f1e) {
-        const int f = br.faces[idx];
-        const int loc = br.face_loc[idx];
-        const T *fp = fbuf + (int64_t)f * NB + N1 * t;
+      const int f = b + le;
+      if (le < EPB && f < f1e) {
+        const FaceAxes<D, N1> fa(br.face_code[f]);
+        const int loc = br.face_loc[f];
+        const T Rv = fbuf[(int64_t)f * 2 * NP + t], Rg = fbuf[(int64_t)f * 2 * NP + NP + t];
+        const int a = fa.a;
+        const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
+        // normal axis a; tangential axes in increasing order (b < c), as in FaceAxes
+        const int Sa = (a == 0) ? 1 : (a == 1 ? SL1 : SL2);
+        const int Sb = (a == 0) ? SL1 : 1;
+        const int Sc = (D == 3) ? ((a == 2) ? SL1 : SL2) : 0;
+        const int node = loc + jb * Sb + jc * Sc;
 #pragma unroll
-        for (int i = 0; i < N1; ++i) atomicAdd(&acc[loc + run_off + i], fp[i]);
+        for (int ia = 0; ia < N1; ++ia) atomicAdd(&acc[node + ia * Sa], face_row<T, D, N1>(tab, fa, ia, Rv, Rg));
       }
     }
   }
@@ -686,17 +699,178 @@ __global__ __launch_bounds__(256) void halo_reduce_kernel(int n, const int32_t *
 }
 
 // ------------------------------------------------------------------------------------
-// Surrogate-boundary faces: one entity = one face.  DG: atomics into the cell block of v.
-// CG: runs holds the run bases of each face's cell ((p+1)^(d-1) per face); the face's
-// (p+1)^d local results are stored to out = fbuf[f] (no conflicts); brick_kernel adds them
-// into its lattice.
+// CG surrogate-boundary faces (Alg. 3), EPB faces per workgroup, faces in brick order.
+// Output per face: Rv and Rg at its NP face nodes (fbuf[f][0][t], fbuf[f][1][t]);
+// brick_kernel expands them into the (p+1)^d local rows (face_row).
+// Two thread layouts: "node" (le = tid / NP, t = tid % NP: one face node or Gauss point
+// each) for the sum-factorised face sweeps, and "pair" (HP = ceil(NP / 2) threads per face,
+// Gauss points 2k and 2k + 1 each) for the point evaluation E u, which reads the cell's
+// (p+1)^d values once for both points.
 // ------------------------------------------------------------------------------------
-template <typename T, int D, int N1, int EPB, bool CG>
+template <typename T, int D, int N1, int EPB>
+// (at least 4 waves per SIMD: keeps the scheduler from holding the whole tile in registers)
+__global__ __launch_bounds__(256, 4) void sbm_face_cg_kernel(int n_faces, const int32_t *__restrict__ face_code,
+                                                          const int32_t *__restrict__ face_runs,
+                                                          const double *__restrict__ face_xi,
+                                                          const T *__restrict__ u, T *__restrict__ fbuf,
+                                                          KTab<T, N1> tab, KScal sc) {
+  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, HP = (NP + 1) / 2;
+  __shared__ T su_all[EPB * NB];
+  __shared__ T fw_all[6 * EPB * NP];  // per face: g, sweep, E u, integrands v / dn v, scratch
+  const int tid = threadIdx.x;
+  const int f0 = xcd_block() * EPB;
+  // node layout
+  const int le = tid / NP, t = tid - le * NP;
+  const int f = f0 + le;
+  const bool act = le < EPB && f < n_faces;
+  T *su = su_all + (le < EPB ? le : 0) * NB;
+  T *fw = fw_all + (le < EPB ? le : 0) * 6 * NP;
+  T *fg = fw, *fs = fw + NP, *fe = fw + 2 * NP, *f5 = fw + 3 * NP, *f6 = fw + 4 * NP, *fx = fw + 5 * NP;
+  // pair layout
+  const int pf = tid / HP, pk = tid - pf * HP;
+  const int q0 = 2 * pk, q1 = 2 * pk + 1;
+  const bool pact = pf < EPB && f0 + pf < n_faces;
+  const bool has1 = pact && q1 < NP;
+  // loads first: face code, the cell's u (one x-run per node thread), the pair's points
+  const int code = act ? face_code[f] : 0;
+  if (act) {
+    const int64_t base = face_runs[(int64_t)f * NP + t];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) su[N1 * t + i] = u[base + i];
+  }
+  double xa[D], xb[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    xa[k] = pact ? face_xi[((int64_t)(f0 + pf) * NP + q0) * D + k] : 0.0;
+    xb[k] = has1 ? face_xi[((int64_t)(f0 + pf) * NP + q1) * D + k] : 0.0;
+  }
+  __syncthreads();
+  const FaceAxes<D, N1> fa(code);
+  const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
+  // normal derivative (reference, times the outward sign / h below) at face node t
+  {
+    T g = 0;
+    const int node_off = jb * fa.Sb + jc * fa.Sc;
+#pragma unroll
+    for (int ia = 0; ia < N1; ++ia) g += (fa.s ? tab.D1[ia] : tab.D0[ia]) * su[ia * fa.Sa + node_off];
+    if (le < EPB) fg[t] = g;
+  }
+  // E u at the pair's two shifted points
+  if (pact) {
+    const T *sp = su_all + pf * NB;
+    double la[D][N1], lb[D][N1];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      lagrange_at<N1>(tab.z, tab.cinv, xa[k], la[k]);
+      lagrange_at<N1>(tab.z, tab.cinv, xb[k], lb[k]);
+    }
+    T a0[N1], a1[N1], b0[N1], b1[N1];
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      a0[j] = T(la[0][j]);
+      a1[j] = T(la[1][j]);
+      b0[j] = T(lb[0][j]);
+      b1[j] = T(lb[1][j]);
+    }
+    T ea = 0, eb = 0;
+    if constexpr (D == 3) {
+      T a2[N1], b2[N1];
+#pragma unroll
+      for (int j = 0; j < N1; ++j) {
+        a2[j] = T(la[2][j]);
+        b2[j] = T(lb[2][j]);
+      }
+      // one (p+1)^2 slab per iteration, so that at most one slab of loads is in flight
+#pragma unroll 1
+      for (int i2 = 0; i2 < N1; ++i2) {
+        const T *sl = sp + NP * i2;
+        T ra = 0, rb = 0;
+#pragma unroll
+        for (int i1 = 0; i1 < N1; ++i1) {
+          T sa = 0, sb = 0;
+#pragma unroll
+          for (int i0 = 0; i0 < N1; ++i0) {
+            const T w = sl[i0 + N1 * i1];
+            sa += a0[i0] * w;
+            sb += b0[i0] * w;
+          }
+          ra += a1[i1] * sa;
+          rb += b1[i1] * sb;
+        }
+        T wa = 0, wb = 0;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) {
+          wa = (j == i2) ? a2[j] : wa;
+          wb = (j == i2) ? b2[j] : wb;
+        }
+        ea += wa * ra;
+        eb += wb * rb;
+      }
+    } else {
+#pragma unroll
+      for (int i1 = 0; i1 < N1; ++i1) {
+        T sa = 0, sb = 0;
+#pragma unroll
+        for (int i0 = 0; i0 < N1; ++i0) {
+          const T w = sp[i0 + N1 * i1];
+          sa += a0[i0] * w;
+          sb += b0[i0] * w;
+        }
+        ea += a1[i1] * sa;
+        eb += b1[i1] * sb;
+      }
+    }
+    T *pe = fw_all + pf * 6 * NP + 2 * NP;
+    pe[q0] = ea;
+    if (has1) pe[q1] = eb;
+  }
+  __syncthreads();
+  // GLL -> Gauss interpolation of the normal derivative on the face
+  T dn;
+  if constexpr (D == 3) {
+    const int qb = t % N1;
+    T r = 0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) r += tab.N[qb * N1 + j] * fg[j + N1 * jc];
+    if (le < EPB) fs[t] = r;  // (qb, jc)
+    __syncthreads();
+    const int qc = t / N1;
+    dn = 0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) dn += tab.N[qc * N1 + j] * fs[qb + N1 * j];
+  } else {
+    dn = 0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) dn += tab.N[t * N1 + j] * fg[j];
+  }
+  // integrands at Gauss point t
+  {
+    const T h = T(sc.h), sig = T(sc.sigma_gamma);
+    const T sh = (fa.s ? T(1) : T(-1)) / h;
+    const T om = act ? ((D == 3) ? h * h * tab.w[t % N1] * tab.w[t / N1] : h * tab.w[t]) : T(0);
+    const T eu = fe[t];
+    dn *= sh;
+    if (le < EPB) {
+      f5[t] = om * (sig * eu - dn);  // tested against v
+      f6[t] = -om * eu * sh;         // tested against the reference derivative along a
+    }
+  }
+  __syncthreads();
+  T Rv, Rg;
+  face_integrate<T, D, N1>(tab, t, fg, fx, f5, f6, Rv, Rg);
+  if (act) {
+    fbuf[(int64_t)f * 2 * NP + t] = Rv;
+    fbuf[(int64_t)f * 2 * NP + NP + t] = Rg;
+  }
+}
+
+// DG surrogate-boundary faces: one entity = one face, atomics into the cell block of v.
+// ------------------------------------------------------------------------------------
+template <typename T, int D, int N1, int EPB>
 __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_t *__restrict__ face_cell,
                                                        const int32_t *__restrict__ face_code,
-                                                       const double *__restrict__ face_xi,
-                                                       const int32_t *__restrict__ runs, const T *__restrict__ u,
-                                                       T *__restrict__ out, KTab<T, N1> tab, KScal sc) {
+                                                       const double *__restrict__ face_xi, const T *__restrict__ u,
+                                                       T *__restrict__ v, KTab<T, N1> tab, KScal sc) {
   constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
   __shared__ T su_all[EPB * NB];
   __shared__ T sw_all[EPB * NB];
@@ -707,33 +881,28 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
   T *su = su_all + le * NB;
   T *sw = sw_all + le * NB;
   T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
-  // every load that does not depend on another is issued up front
   double xp[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) xp[k] = act ? face_xi[((int64_t)f * NP + t) * D + k] : 0.0;
   const FaceAxes<D, N1> fa(act ? face_code[f] : 0);
-  int64_t base;
-  if constexpr (CG) {
-    base = act ? (int64_t)runs[(int64_t)f * NP + t] : 0;  // runs: run bases of the face's cell
-  } else {
-    base = (int64_t)(act ? face_cell[f] : 0) * NB + N1 * t;
-  }
+  const int64_t base = (int64_t)(act ? face_cell[f] : 0) * NB + N1 * t;
   if (act) {
 #pragma unroll
     for (int i = 0; i < N1; ++i) su[N1 * t + i] = u[base + i];
   }
   __syncthreads();
-  sbm_face_eval<T, D, N1>(tab, sc, t, act, fa, xp, su, sw, f1, f2, f3, f4);
+  T Rv, Rg;
+  sbm_face_eval<T, D, N1>(tab, sc, t, act, fa, xp, su, f1, f2, f3, f4, Rv, Rg);
+  {
+    const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
+    const int node_off = jb * fa.Sb + jc * fa.Sc;
+#pragma unroll
+    for (int ia = 0; ia < N1; ++ia) sw[ia * fa.Sa + node_off] = face_row<T, D, N1>(tab, fa, ia, Rv, Rg);
+  }
   __syncthreads();
   if (act) {
-    if constexpr (CG) {
-      T *op = out + (int64_t)f * NB + N1 * t;
 #pragma unroll
-      for (int i = 0; i < N1; ++i) op[i] = sw[N1 * t + i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < N1; ++i) atomic_add(out + base + i, sw[N1 * t + i]);
-    }
+    for (int i = 0; i < N1; ++i) atomic_add(v + base + i, sw[N1 * t + i]);
   }
 }
 
@@ -871,16 +1040,15 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
   if (c->disc == SBM_CG) {
     if (c->n_bricks > 0 && (parts & (SBM_PART_CELLS | SBM_PART_SBM_FACES))) {
       constexpr int NT = BrickCfg<T, D, N1>::NT;
-      const BrickArgs br{c->d_brick_cell_off, c->d_brick_runs,     c->d_brick_cell_loc,
-                         c->d_brick_face_off, c->d_brick_faces,    c->d_brick_face_loc,
-                         c->d_row_base,       c->d_row_gmask,      c->d_row_bmask,
-                         c->d_row_hbase};
+      const BrickArgs br{c->d_brick_cell_off, c->d_brick_runs, c->d_brick_cell_loc, c->d_brick_face_off,
+                         c->d_brick_face_loc, c->d_face_code,  c->d_row_base,       c->d_row_gmask,
+                         c->d_row_bmask,      c->d_row_hbase};
       T *halo = (T *)c->d_halo;
       T *fbuf = (T *)c->d_fbuf;
       if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
         constexpr int EF = epb<T, D, N1, 2, 0>();
-        hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, EF, true>), dim3((nf + EF - 1) / EF), dim3(EF * NP), 0, s,
-                           nf, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_face_runs, u, fbuf, tab, sc);
+        hipLaunchKernelGGL((sbm_face_cg_kernel<T, D, N1, EF>), dim3((nf + EF - 1) / EF), dim3(EF * NP), 0, s, nf,
+                           c->d_face_code, c->d_face_runs, c->d_face_xi, u, fbuf, tab, sc);
       }
       hipLaunchKernelGGL((brick_kernel<T, D, N1>), dim3((unsigned)c->n_bricks), dim3(NT), 0, s, br,
                          (const T *)fbuf, u, v, halo, tab, scale, parts);
@@ -898,8 +1066,8 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
     }
     if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
       constexpr int E = epb<T, D, N1, 2, 0>();
-      hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E, false>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s, nf,
-                         c->d_face_cell, c->d_face_code, c->d_face_xi, (const int32_t *)nullptr, u, v, tab, sc);
+      hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s, nf,
+                         c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
     }
   }
   return hipGetLastError();

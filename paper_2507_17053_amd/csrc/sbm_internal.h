@@ -98,7 +98,7 @@ struct sbm_ctx {
   int64_t n_bricks_faces = 0;  // bricks [0, n_bricks_faces) carry surrogate faces
   std::vector<int32_t> brick_cell_off, brick_cells, brick_cell_loc;
   std::vector<int32_t> brick_runs;  // run bases of the cells in brick order (n_cells x (p+1)^(d-1))
-  std::vector<int32_t> face_runs;   // run bases of each surrogate face's cell (n_sbm x (p+1)^(d-1))
+  std::vector<int32_t> face_runs;   // run bases of each surrogate face's cell, faces in brick order
   std::vector<int32_t> brick_face_off, brick_faces, brick_face_loc;
   std::vector<int32_t> row_base, row_hbase;
   std::vector<uint32_t> row_gmask, row_bmask;
@@ -107,10 +107,10 @@ struct sbm_ctx {
   std::vector<int32_t> halo_dof, halo_off, halo_slot;
   int32_t *d_row_hbase = nullptr, *d_halo_dof = nullptr, *d_halo_off = nullptr, *d_halo_slot = nullptr;
   void *d_halo = nullptr;  // n_halo_slots doubles (also used as floats); per-handle scratch
-  void *d_fbuf = nullptr;  // CG: n_sbm x (p+1)^d doubles, surrogate-face results; per-handle scratch
+  void *d_fbuf = nullptr;  // CG: n_sbm x 2 x (p+1)^(d-1) doubles, surrogate-face results; per-handle scratch
   int32_t *d_brick_cell_off = nullptr, *d_brick_runs = nullptr, *d_brick_cell_loc = nullptr;
   int32_t *d_face_runs = nullptr;
-  int32_t *d_brick_face_off = nullptr, *d_brick_faces = nullptr, *d_brick_face_loc = nullptr;
+  int32_t *d_brick_face_off = nullptr, *d_brick_face_loc = nullptr;
   int32_t *d_row_base = nullptr;
   uint32_t *d_row_gmask = nullptr, *d_row_bmask = nullptr;
   // device copies

@@ -427,7 +427,6 @@ static void free_device(sbm_ctx *c) {
   free_ptr(c->d_face_runs);
   free_ptr(c->d_brick_cell_loc);
   free_ptr(c->d_brick_face_off);
-  free_ptr(c->d_brick_faces);
   free_ptr(c->d_brick_face_loc);
   free_ptr(c->d_row_base);
   free_ptr(c->d_row_gmask);
@@ -510,11 +509,6 @@ static void build_bricks(sbm_ctx *c, const std::vector<int32_t> &id, int64_t lx,
   for (int64_t i = 0; i < nc; ++i)
     std::copy(c->runs.begin() + (size_t)c->brick_cells[i] * npr, c->runs.begin() + (size_t)(c->brick_cells[i] + 1) * npr,
               c->brick_runs.begin() + (size_t)i * npr);
-  // and of each surrogate face's cell
-  c->face_runs.resize((size_t)c->n_sbm * npr);
-  for (int64_t f = 0; f < c->n_sbm; ++f)
-    std::copy(c->runs.begin() + (size_t)c->faces[3 * f] * npr, c->runs.begin() + (size_t)(c->faces[3 * f] + 1) * npr,
-              c->face_runs.begin() + (size_t)f * npr);
   const int64_t nf = c->n_sbm;
   c->brick_face_off.assign(nb + 1, 0);
   for (int64_t f = 0; f < nf; ++f) ++c->brick_face_off[bid[bkey[c->faces[3 * f]]] + 1];
@@ -530,6 +524,14 @@ static void build_bricks(sbm_ctx *c, const std::vector<int32_t> &id, int64_t lx,
       c->brick_face_loc[fill[b]] = cell_loc(r, bkey[r]);
       ++fill[b];
     }
+  }
+  // run bases of each surrogate face's cell, faces in brick order (the device copies of the
+  // face arrays of a CG operator are stored in brick order, see the upload)
+  c->face_runs.resize((size_t)nf * npr);
+  for (int64_t i = 0; i < nf; ++i) {
+    const int64_t r = c->faces[3 * (int64_t)c->brick_faces[i]];
+    std::copy(c->runs.begin() + (size_t)r * npr, c->runs.begin() + (size_t)(r + 1) * npr,
+              c->face_runs.begin() + (size_t)i * npr);
   }
   c->row_base.assign((size_t)nb * nrows, 0);
   c->row_gmask.assign((size_t)nb * nrows, 0u);
@@ -907,10 +909,18 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
     return SBM_OK;
   }
   // ---- upload ----
+  // Device face arrays: CG in brick order (face i of the device arrays is host face
+  // brick_faces[i], so a brick's faces are contiguous), DG in host order.  Host arrays and
+  // the exports keep the host order.
+  const bool cg = c->disc == SBM_CG;
   std::vector<int32_t> fcell(c->n_sbm), fcode(c->n_sbm);
-  for (int64_t f = 0; f < c->n_sbm; ++f) {
-    fcell[f] = c->faces[3 * f];
-    fcode[f] = 2 * c->faces[3 * f + 1] + c->faces[3 * f + 2];
+  std::vector<double> fxi(c->face_xi.size());
+  const size_t xq = (size_t)c->nq_face * c->dim;
+  for (int64_t i = 0; i < c->n_sbm; ++i) {
+    const int64_t f = cg ? c->brick_faces[i] : i;
+    fcell[i] = c->faces[3 * f];
+    fcode[i] = 2 * c->faces[3 * f + 1] + c->faces[3 * f + 2];
+    std::copy(c->face_xi.begin() + f * xq, c->face_xi.begin() + (f + 1) * xq, fxi.begin() + i * xq);
   }
   hipError_t e = hipSuccess;
   size_t bytes = 0;
@@ -921,7 +931,6 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
     if (e == hipSuccess) e = upload(&c->d_face_runs, c->face_runs, bytes);
     if (e == hipSuccess) e = upload(&c->d_brick_cell_loc, c->brick_cell_loc, bytes);
     if (e == hipSuccess) e = upload(&c->d_brick_face_off, c->brick_face_off, bytes);
-    if (e == hipSuccess) e = upload(&c->d_brick_faces, c->brick_faces, bytes);
     if (e == hipSuccess) e = upload(&c->d_brick_face_loc, c->brick_face_loc, bytes);
     if (e == hipSuccess) e = upload(&c->d_row_base, c->row_base, bytes);
     if (e == hipSuccess) e = upload(&c->d_row_gmask, c->row_gmask, bytes);
@@ -935,7 +944,7 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
       bytes += (size_t)c->n_halo_slots * sizeof(double);
     }
     if (e == hipSuccess && c->n_sbm > 0) {
-      const size_t fb = (size_t)c->n_sbm * c->nb * sizeof(double);
+      const size_t fb = (size_t)c->n_sbm * 2 * c->nq_face * sizeof(double);
       e = hipMalloc(&c->d_fbuf, fb);
       bytes += fb;
     }
@@ -943,7 +952,7 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
   if (e == hipSuccess && c->disc == SBM_DG) e = upload(&c->d_nbr, c->nbr, bytes);
   if (e == hipSuccess) e = upload(&c->d_face_cell, fcell, bytes);
   if (e == hipSuccess) e = upload(&c->d_face_code, fcode, bytes);
-  if (e == hipSuccess) e = upload(&c->d_face_xi, c->face_xi, bytes);
+  if (e == hipSuccess) e = upload(&c->d_face_xi, fxi, bytes);
   if (e != hipSuccess) {
     set_error(std::string("sbm_setup: device upload failed: ") + hipGetErrorString(e));
     free_device(c);
