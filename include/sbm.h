@@ -137,9 +137,14 @@ sbm_status sbm_apply(sbm_handle h, const void *u, void *v, int prec, void *strea
  * surrogate faces, Sec. 4.3).  Same argument rules as sbm_apply.  Asynchronous.
  */
 enum { SBM_PART_CELLS = 2, SBM_PART_SBM_FACES = 4, SBM_PART_ALL = 6,
-       SBM_PART_NO_ASSEMBLY = 8 /* CG: skip the final sum over brick-boundary DoFs (those
-                                   entries of v are then left unwritten): times the brick
-                                   kernel alone */ };
+       SBM_PART_NO_ASSEMBLY = 8,  /* CG: skip the final sum over brick-boundary DoFs (those
+                                     entries of v are then left unwritten) */
+       SBM_PART_REUSE_FACES = 16  /* CG, with SBM_PART_SBM_FACES: do not evaluate the
+                                     surrogate faces again; merge the face results of the
+                                     previous call with SBM_PART_SBM_FACES on this handle
+                                     (same precision; otherwise the result is undefined).
+                                     With SBM_PART_ALL | SBM_PART_NO_ASSEMBLY this times the
+                                     brick kernel alone. */ };
 
 /*
  * sbm_layout_stats -- CG work decomposition (zeros for DG): number of bricks (blocks of

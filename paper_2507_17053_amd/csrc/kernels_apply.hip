@@ -1045,7 +1045,7 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
                          c->d_row_bmask,      c->d_row_hbase};
       T *halo = (T *)c->d_halo;
       T *fbuf = (T *)c->d_fbuf;
-      if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
+      if (nf > 0 && (parts & SBM_PART_SBM_FACES) && !(parts & SBM_PART_REUSE_FACES)) {
         constexpr int EF = epb<T, D, N1, 2, 0>();
         hipLaunchKernelGGL((sbm_face_cg_kernel<T, D, N1, EF>), dim3((nf + EF - 1) / EF), dim3(EF * NP), 0, s, nf,
                            c->d_face_code, c->d_face_runs, c->d_face_xi, u, fbuf, tab, sc);

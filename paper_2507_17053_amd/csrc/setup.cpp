@@ -1014,7 +1014,8 @@ sbm_status sbm_apply(sbm_handle h, const void *u, void *v, int prec, void *strea
 
 sbm_status sbm_apply_parts(sbm_handle h, const void *u, void *v, int prec, int parts, void *stream) {
   if (!h || h->host_only || (h->n_dofs > 0 && (!u || !v)) || (u == v && h->n_dofs > 0) ||
-      (prec != SBM_F64 && prec != SBM_F32) || (parts & ~(SBM_PART_ALL | SBM_PART_NO_ASSEMBLY))) {
+      (prec != SBM_F64 && prec != SBM_F32) ||
+      (parts & ~(SBM_PART_ALL | SBM_PART_NO_ASSEMBLY | SBM_PART_REUSE_FACES))) {
     set_error("sbm_apply_parts: invalid argument");
     return SBM_EINVAL;
   }

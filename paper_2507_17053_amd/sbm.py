@@ -87,7 +87,7 @@ _lib.sbm_footprint_estimate.restype = ctypes.c_size_t
 for _n in ("sbm_export_cells", "sbm_export_sbm_faces", "sbm_export_face_xi", "sbm_export_cell_dofs"):
     getattr(_lib, _n).argtypes = [_P, _P]
 
-PART_CELLS, PART_SBM_FACES, PART_ALL, PART_NO_ASSEMBLY = 2, 4, 6, 8
+PART_CELLS, PART_SBM_FACES, PART_ALL, PART_NO_ASSEMBLY, PART_REUSE_FACES = 2, 4, 6, 8, 16
 _lib.sbm_layout_stats.argtypes = [_P, _I64P, _I64P, _I64P]
 EXPORTED = ["sbm_setup", "sbm_info", "sbm_destroy", "sbm_last_error", "sbm_apply", "sbm_apply_parts",
             "sbm_apply_batch", "sbm_layout_stats",

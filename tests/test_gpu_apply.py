@@ -124,3 +124,24 @@ def test_single_cell_domain():
     u = inputs.uniform_vector(ref.n_dofs, seed=0)
     v = _gpu_apply(op, u, torch.float64)
     assert _rel(v, O.assemble(ref) @ u) <= 1e-12
+
+
+def test_apply_parts_split_and_face_reuse():
+    """Cells + surrogate faces = full apply; SBM_PART_REUSE_FACES merges the face results of
+    the previous face evaluation instead of evaluating again."""
+    op = sbm.Operator(3, 10, -1.0, 1.0, inputs.sphere((0, 0, 0), 0.75), 3)
+    u = torch.from_numpy(inputs.uniform_vector(op.n_dofs, seed=0)).cuda()
+    u2 = torch.from_numpy(inputs.uniform_vector(op.n_dofs, seed=5)).cuda()
+    out = {k: torch.full_like(u, float("nan")) for k in ("all", "c", "f", "f2", "reuse", "mix")}
+    op.apply(u, out["all"])
+    op.apply_parts(u, out["c"], sbm.PART_CELLS)
+    op.apply_parts(u2, out["f2"], sbm.PART_SBM_FACES)
+    op.apply_parts(u, out["mix"], sbm.PART_ALL | sbm.PART_REUSE_FACES)   # cells of u + faces of u2
+    op.apply_parts(u, out["f"], sbm.PART_SBM_FACES)
+    op.apply_parts(u, out["reuse"], sbm.PART_ALL | sbm.PART_REUSE_FACES)  # faces of u again
+    torch.cuda.synchronize()
+    nrm = torch.linalg.norm(out["all"]).item()
+    assert torch.linalg.norm(out["c"] + out["f"] - out["all"]).item() <= 1e-13 * nrm
+    assert torch.linalg.norm(out["reuse"] - out["all"]).item() <= 1e-14 * nrm
+    assert torch.linalg.norm(out["mix"] - (out["c"] + out["f2"])).item() <= 1e-13 * nrm
+    assert torch.linalg.norm(out["f2"] - out["f"]).item() > 1e-6 * nrm
