@@ -95,7 +95,7 @@ struct sbm_ctx {
   // CG bricks: BX x BY x BZ blocks of background cells, one workgroup each
   int brick[3] = {1, 1, 1};
   int64_t n_bricks = 0;
-  int64_t n_bricks_faces = 0;  // bricks [0, n_bricks_faces) carry surrogate faces
+  int64_t n_bricks_faces = 0;  // number of bricks that carry surrogate faces
   std::vector<int32_t> brick_cell_off, brick_cells, brick_cell_loc;
   std::vector<int32_t> brick_runs;  // run bases of the cells in brick order (n_cells x (p+1)^(d-1))
   std::vector<int32_t> face_runs;   // run bases of each surrogate face's cell, faces in brick order

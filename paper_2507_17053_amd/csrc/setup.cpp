@@ -464,25 +464,38 @@ static void build_bricks(sbm_ctx *c, const std::vector<int32_t> &id, int64_t lx,
     bkey[r] = (bz * nby + cc[1] / BY) * nbx + cc[0] / BX;
     ++count[bkey[r]];
   }
-  // Bricks with surrogate faces are numbered first (lexicographic), then those without:
-  // the dispatcher starts workgroups in order, and the face-carrying bricks (partial, cell by
-  // cell, plus their faces) are the slow ones, so they start early and the launch ends on
-  // short work.
+  // Brick numbering.  The kernel gives each of the 8 XCDs one contiguous range of bricks (see
+  // xcd_block); the face-carrying bricks (partial, cell by cell, plus their faces) are the
+  // slow ones.  So every XCD range gets an equal share of the face-carrying bricks, numbered
+  // first within the range (the dispatcher starts workgroups in order: the slow ones start
+  // early), then its share of the others; each share is a contiguous run of the lexicographic
+  // order (neighbouring bricks share an L2).
   std::vector<int32_t> fcount(count.size(), 0);
   for (int64_t f = 0; f < c->n_sbm; ++f) ++fcount[bkey[c->faces[3 * f]]];
+  std::vector<int64_t> with_f, without_f;
+  for (size_t k = 0; k < count.size(); ++k)
+    if (count[k] > 0) (fcount[k] > 0 ? with_f : without_f).push_back((int64_t)k);
+  const int64_t nbt = (int64_t)(with_f.size() + without_f.size());
+  const int64_t nwf = (int64_t)with_f.size();
   std::vector<int32_t> bid(count.size(), -1);
   std::vector<int64_t> key_of;
-  int32_t nb = 0;
-  for (int pass = 0; pass < 2; ++pass)
-    for (size_t k = 0; k < count.size(); ++k)
-      if (count[k] > 0 && ((fcount[k] > 0) == (pass == 0))) {
-        bid[k] = nb++;
-        key_of.push_back((int64_t)k);
-      }
+  key_of.reserve(nbt);
+  {
+    const int64_t per = nbt / 8, rem = nbt % 8;
+    int64_t fi = 0, gi = 0;
+    for (int x = 0; x < 8; ++x) {
+      const int64_t size = per + (x < rem ? 1 : 0);
+      const int64_t fend = std::min<int64_t>(nwf * (x + 1) / 8, fi + size);
+      int64_t k = 0;
+      for (; fi < fend; ++fi, ++k) key_of.push_back(with_f[fi]);
+      for (; k < size && gi < (int64_t)without_f.size(); ++gi, ++k) key_of.push_back(without_f[gi]);
+      for (; k < size; ++fi, ++k) key_of.push_back(with_f[fi]);  // only if the others ran out
+    }
+  }
+  const int32_t nb = (int32_t)key_of.size();
+  for (int32_t b = 0; b < nb; ++b) bid[key_of[b]] = b;
   c->n_bricks = nb;
-  c->n_bricks_faces = 0;
-  for (size_t k = 0; k < count.size(); ++k)
-    if (count[k] > 0 && fcount[k] > 0) ++c->n_bricks_faces;
+  c->n_bricks_faces = nwf;
   auto cell_loc = [&](int64_t r, int64_t key) {
     const int32_t *cc = &c->cells[r * d];
     const int64_t bx = key % nbx, by = (key / nbx) % nby, bz = key / (nbx * nby);
