@@ -145,3 +145,40 @@ def test_apply_parts_split_and_face_reuse():
     assert torch.linalg.norm(out["reuse"] - out["all"]).item() <= 1e-14 * nrm
     assert torch.linalg.norm(out["mix"] - (out["c"] + out["f2"])).item() <= 1e-13 * nrm
     assert torch.linalg.norm(out["f2"] - out["f"]).item() > 1e-6 * nrm
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_apply_in_captured_graph_matches_eager(dtype):
+    """The apply (fork/join over the handle's second stream) captured in a HIP graph: every
+    replay, with eager work and synchronisation between replays, equals the eager result."""
+    op = sbm.Operator(3, 16, -1.0, 1.0, inputs.sphere((0, 0, 0), 0.75), 4)
+    n_bricks, _, _ = op.layout_stats()
+    assert n_bricks > 1
+    u = torch.from_numpy(inputs.uniform_vector(op.n_dofs, seed=0)).cuda().to(dtype)
+    ref = torch.empty_like(u)
+    op.apply(u, ref)
+    ref2 = torch.empty_like(u)
+    op.apply(ref, ref2)
+    torch.cuda.synchronize()
+    v, w = torch.empty_like(u), torch.empty_like(u)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        op.apply(u, v, stream=s)  # warm-up on the capture stream
+        s.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            op.apply(u, v, stream=s)
+            op.apply(v, w, stream=s)
+    torch.cuda.synchronize()
+    scratch = torch.empty_like(u)
+    for rep in range(4):
+        v.fill_(float("nan"))
+        w.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        tol = 1e-14 if dtype == torch.float64 else 1e-6
+        assert (torch.linalg.norm(v - ref) / torch.linalg.norm(ref)).item() <= tol, rep
+        assert (torch.linalg.norm(w - ref2) / torch.linalg.norm(ref2)).item() <= tol, rep
+        op.apply(w, scratch)  # eager work between replays
+        torch.cuda.synchronize()
