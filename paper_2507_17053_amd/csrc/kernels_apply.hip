@@ -460,7 +460,7 @@ struct LaneGroup {
 template <typename T, int D, int N1>
 __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     BrickArgs br, const T *__restrict__ fbuf, const T *__restrict__ u, T *__restrict__ v, T *__restrict__ halo,
-    KTab<T, N1> tab, T scale, int parts) {
+    int nhalo, KTab<T, N1> tab, T scale, int parts) {
   using C = BrickCfg<T, D, N1>;
   constexpr int P = C::P, NP = C::NP, NB = C::NB, EPB = C::EPB;
   constexpr int BX = C::BX, BY = C::BY, BZ = C::BZ, LX = C::LX, LY = C::LY, LZ = C::LZ;
@@ -664,7 +664,9 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
   __syncthreads();
   // write-out: lanes walk the lattice with x fastest, so stores are row-contiguous.
   // Points strictly inside the brick box belong to this brick alone: final value.  Points
-  // on the box boundary go to their halo slot; halo_reduce_kernel adds the slots up.
+  // on the box boundary go to plane k = [x == 0] + 2 [y == 0] + 4 [z == 0] of the halo (the
+  // brick's side of the point; bricks sharing the point differ in k), at the point's halo
+  // index (consecutive along the row's boundary DoFs); halo_reduce_kernel sums the planes.
   // Unrolled over the thread's points so that all LDS reads issue back to back; the stores
   // are predicated.
   constexpr int NIT = (NL + C::NT - 1) / C::NT;
@@ -673,28 +675,31 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     const int pt = tid + k * C::NT;
     const int ptc = pt < NL ? pt : 0;
     const int x = ptc % LX, row = ptc / LX;
-    const uint32_t bm = s_bmask[row];
+    const uint32_t bm = s_bmask[row], gm = s_gmask[row];
     const uint32_t below = (1u << x) - 1u;
     const int y = row % LY, z = row / LY;
     const bool brow = y == 0 || y == LY - 1 || (D == 3 && (z == 0 || z == LZ - 1));
     const bool inner = !brow && x > 0 && x < LX - 1;
-    const uint32_t hm = brow ? bm : (bm & (1u | (1u << (LX - 1))));
-    T *dst = inner ? v + s_base[row] + __popc(s_gmask[row] & below) : halo + s_hbase[row] + __popc(hm & below);
+    const uint32_t hgm = brow ? gm : (gm & (1u | (1u << (LX - 1))));
+    const int plane = (x == 0 ? 1 : 0) | (y == 0 ? 2 : 0) | ((D == 3 && z == 0) ? 4 : 0);
+    T *dst = inner ? v + s_base[row] + __popc(gm & below)
+                   : halo + (int64_t)plane * nhalo + s_hbase[row] + __popc(hgm & below);
     const T val = acc[ptc];
     if (pt < NL && ((bm >> x) & 1u)) *dst = val;
   }
 }
 
-// v[dof] = sum of the dof's halo slots, in increasing slot order (deterministic).
-template <typename T>
+// v[dof] = sum over the planes k present in the DoF's mask, in increasing k (deterministic).
+template <typename T, int D>
 __global__ __launch_bounds__(256) void halo_reduce_kernel(int n, const int32_t *__restrict__ dof,
-                                                          const int32_t *__restrict__ off,
-                                                          const int32_t *__restrict__ slot,
+                                                          const uint8_t *__restrict__ mask,
                                                           const T *__restrict__ halo, T *__restrict__ v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const uint32_t m = mask[i];
   T s = 0;
-  for (int j = off[i]; j < off[i + 1]; ++j) s += halo[slot[j]];
+#pragma unroll
+  for (int k = 0; k < (1 << D); ++k) s += ((m >> k) & 1u) ? halo[(int64_t)k * n + i] : T(0);
   v[dof[i]] = s;
 }
 
@@ -1050,12 +1055,12 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
         hipLaunchKernelGGL((sbm_face_cg_kernel<T, D, N1, EF>), dim3((nf + EF - 1) / EF), dim3(EF * NP), 0, s, nf,
                            c->d_face_code, c->d_face_runs, c->d_face_xi, u, fbuf, tab, sc);
       }
+      const int nh = (int)c->n_halo_dofs;
       hipLaunchKernelGGL((brick_kernel<T, D, N1>), dim3((unsigned)c->n_bricks), dim3(NT), 0, s, br,
-                         (const T *)fbuf, u, v, halo, tab, scale, parts);
-      if (c->n_halo_dofs > 0 && !(parts & SBM_PART_NO_ASSEMBLY)) {
-        const int nh = (int)c->n_halo_dofs;
-        hipLaunchKernelGGL(halo_reduce_kernel<T>, dim3((nh + 255) / 256), dim3(256), 0, s, nh, c->d_halo_dof,
-                           c->d_halo_off, c->d_halo_slot, (const T *)halo, v);
+                         (const T *)fbuf, u, v, halo, nh, tab, scale, parts);
+      if (nh > 0 && !(parts & SBM_PART_NO_ASSEMBLY)) {
+        hipLaunchKernelGGL((halo_reduce_kernel<T, D>), dim3((nh + 255) / 256), dim3(256), 0, s, nh, c->d_halo_dof,
+                           (const uint8_t *)c->d_halo_mask, (const T *)halo, v);
       }
     }
   } else {

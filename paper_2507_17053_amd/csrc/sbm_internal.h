@@ -102,11 +102,15 @@ struct sbm_ctx {
   std::vector<int32_t> brick_face_off, brick_faces, brick_face_loc;
   std::vector<int32_t> row_base, row_hbase;
   std::vector<uint32_t> row_gmask, row_bmask;
-  // halo assembly: DoFs on brick boundaries collect one slot per touching brick
+  // halo assembly: a DoF on brick boundaries collects one value per touching brick, in plane
+  // k (2^d planes of n_halo_dofs values) given by the brick's side of the point
   int64_t n_halo_slots = 0, n_halo_dofs = 0;
-  std::vector<int32_t> halo_dof, halo_off, halo_slot;
-  int32_t *d_row_hbase = nullptr, *d_halo_dof = nullptr, *d_halo_off = nullptr, *d_halo_slot = nullptr;
-  void *d_halo = nullptr;  // n_halo_slots doubles (also used as floats); per-handle scratch
+  std::vector<int32_t> halo_dof;   // halo index -> DoF
+  std::vector<uint8_t> halo_mask;  // halo index -> planes written
+  bool halo_ok = true;             // consistency of the halo numbering (checked at setup)
+  int32_t *d_row_hbase = nullptr, *d_halo_dof = nullptr;
+  uint8_t *d_halo_mask = nullptr;
+  void *d_halo = nullptr;  // 2^d x n_halo_dofs doubles (also used as floats); per-handle scratch
   void *d_fbuf = nullptr;  // CG: n_sbm x 2 x (p+1)^(d-1) doubles, surrogate-face results; per-handle scratch
   int32_t *d_brick_cell_off = nullptr, *d_brick_runs = nullptr, *d_brick_cell_loc = nullptr;
   int32_t *d_face_runs = nullptr;

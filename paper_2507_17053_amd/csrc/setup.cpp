@@ -433,8 +433,7 @@ static void free_device(sbm_ctx *c) {
   free_ptr(c->d_row_bmask);
   free_ptr(c->d_row_hbase);
   free_ptr(c->d_halo_dof);
-  free_ptr(c->d_halo_off);
-  free_ptr(c->d_halo_slot);
+  free_ptr(c->d_halo_mask);
   free_ptr(c->d_halo);
   free_ptr(c->d_fbuf);
 }
@@ -587,48 +586,63 @@ static void build_bricks(sbm_ctx *c, const std::vector<int32_t> &id, int64_t lx,
         c->row_bmask[(size_t)b * nrows + row] = bm;
       }
   }
-  // Halo slots: every touched point on a brick's boundary gets one slot, numbered brick
-  // by brick in row order (z, y) and x within the row; the kernel recomputes the slot from
-  // row_hbase and the row's boundary mask.  The reduction lists, per DoF, its slots in
-  // increasing slot order (a fixed summation order).
-  c->row_hbase.assign((size_t)nb * nrows, 0);
-  std::vector<std::pair<int32_t, int32_t>> pairs;  // (dof, slot)
-  int64_t slot = 0;
+  // Halo: the DoFs on brick-box boundaries (bricks are aligned, so such a point lies on the
+  // boundary of every brick that contains it).  They are numbered in DoF order (halo index);
+  // along a brick row the boundary DoFs have consecutive halo indices.  A brick writes its
+  // value for such a point into plane k = [x == 0] + 2 [y == 0] + 4 [z == 0] (its brick-
+  // lattice coordinates: the side of the point the brick lies on), at the point's halo index;
+  // bricks sharing a point have distinct k.  The reduction sums, per halo DoF, the planes
+  // present in its mask in increasing k (a fixed order).  row_hbase: halo index of the row's
+  // first boundary DoF.
+  const uint32_t edge = 1u | (1u << (LX - 1));
+  auto boundary_mask = [&](int y, int z, uint32_t gm) {
+    const bool brow = (y == 0 || y == LY - 1 || (d == 3 && (z == 0 || z == LZ - 1)));
+    return brow ? gm : (gm & edge);
+  };
+  std::vector<int32_t> hidx(c->n_dofs, -1);
   for (int32_t b = 0; b < nb; ++b)
     for (int z = 0; z < LZ; ++z)
       for (int y = 0; y < LY; ++y) {
-        const int row = y + LY * z;
-        const size_t ri = (size_t)b * nrows + row;
-        c->row_hbase[ri] = (int32_t)slot;
-        const bool brow = (y == 0 || y == LY - 1 || (d == 3 && (z == 0 || z == LZ - 1)));
-        const uint32_t bm = c->row_bmask[ri], gm = c->row_gmask[ri];
-        const uint32_t edge = 1u | (1u << (LX - 1));
-        const uint32_t hm = brow ? bm : (bm & edge);
+        const size_t ri = (size_t)b * nrows + y + LY * z;
+        const uint32_t hm = boundary_mask(y, z, c->row_bmask[ri]);
+        for (int x = 0; x < LX; ++x)
+          if ((hm >> x) & 1u)
+            hidx[c->row_base[ri] + __builtin_popcount(c->row_gmask[ri] & ((1u << x) - 1u))] = 0;
+      }
+  c->halo_dof.clear();
+  for (int64_t g = 0; g < c->n_dofs; ++g)
+    if (hidx[g] == 0) {
+      hidx[g] = (int32_t)c->halo_dof.size();
+      c->halo_dof.push_back((int32_t)g);
+    }
+  c->n_halo_dofs = (int64_t)c->halo_dof.size();
+  c->halo_mask.assign(c->n_halo_dofs, 0);
+  c->row_hbase.assign((size_t)nb * nrows, 0);
+  int64_t slots = 0;
+  c->halo_ok = true;
+  for (int32_t b = 0; b < nb; ++b)
+    for (int z = 0; z < LZ; ++z)
+      for (int y = 0; y < LY; ++y) {
+        const size_t ri = (size_t)b * nrows + y + LY * z;
+        const uint32_t gm = c->row_gmask[ri];
+        const uint32_t hgm = boundary_mask(y, z, gm), hm = boundary_mask(y, z, c->row_bmask[ri]);
+        if (hgm) {
+          const int x0 = __builtin_ctz(hgm);
+          c->row_hbase[ri] = hidx[c->row_base[ri] + __builtin_popcount(gm & ((1u << x0) - 1u))];
+        }
         for (int x = 0; x < LX; ++x) {
-          if (!((hm >> x) & 1u)) continue;
-          const uint32_t below = gm & ((1u << x) - 1u);
-          const int32_t dof = c->row_base[ri] + __builtin_popcount(below);
-          pairs.emplace_back(dof, (int32_t)slot);
-          ++slot;
+          if (!((hgm >> x) & 1u)) continue;
+          const int32_t h = hidx[c->row_base[ri] + __builtin_popcount(gm & ((1u << x) - 1u))];
+          // every boundary DoF of the row is a halo DoF, numbered consecutively along the row
+          if (h < 0 || h != c->row_hbase[ri] + __builtin_popcount(hgm & ((1u << x) - 1u))) c->halo_ok = false;
+          if ((hm >> x) & 1u) {
+            const int k = (x == 0 ? 1 : 0) | (y == 0 ? 2 : 0) | ((d == 3 && z == 0) ? 4 : 0);
+            if (h >= 0) c->halo_mask[h] |= (uint8_t)(1u << k);
+            ++slots;
+          }
         }
       }
-  c->n_halo_slots = slot;
-  std::stable_sort(pairs.begin(), pairs.end(),
-                   [](const std::pair<int32_t, int32_t> &a, const std::pair<int32_t, int32_t> &b) {
-                     return a.first < b.first;
-                   });
-  c->halo_dof.clear();
-  c->halo_off.assign(1, 0);
-  c->halo_slot.resize(pairs.size());
-  for (size_t i = 0; i < pairs.size(); ++i) {
-    if (i == 0 || pairs[i].first != pairs[i - 1].first) {
-      if (i > 0) c->halo_off.push_back((int32_t)i);
-      c->halo_dof.push_back(pairs[i].first);
-    }
-    c->halo_slot[i] = pairs[i].second;
-  }
-  if (!pairs.empty()) c->halo_off.push_back((int32_t)pairs.size());
-  c->n_halo_dofs = (int64_t)c->halo_dof.size();
+  c->n_halo_slots = slots;
 }
 
 namespace sbm {
@@ -912,6 +926,10 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
     set_error("sbm_setup: out of host memory");
     st = SBM_ENOMEM;
   }
+  if (st == SBM_OK && !c->halo_ok) {
+    set_error("sbm_setup: internal error: brick-boundary DoFs are not numbered consecutively along a row");
+    st = SBM_EUNSUPPORTED;
+  }
   if (st != SBM_OK) {
     delete c;
     return st;
@@ -950,11 +968,11 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
     if (e == hipSuccess) e = upload(&c->d_row_bmask, c->row_bmask, bytes);
     if (e == hipSuccess) e = upload(&c->d_row_hbase, c->row_hbase, bytes);
     if (e == hipSuccess) e = upload(&c->d_halo_dof, c->halo_dof, bytes);
-    if (e == hipSuccess) e = upload(&c->d_halo_off, c->halo_off, bytes);
-    if (e == hipSuccess) e = upload(&c->d_halo_slot, c->halo_slot, bytes);
-    if (e == hipSuccess && c->n_halo_slots > 0) {
-      e = hipMalloc(&c->d_halo, (size_t)c->n_halo_slots * sizeof(double));
-      bytes += (size_t)c->n_halo_slots * sizeof(double);
+    if (e == hipSuccess) e = upload(&c->d_halo_mask, c->halo_mask, bytes);
+    if (e == hipSuccess && c->n_halo_dofs > 0) {
+      const size_t hb = ((size_t)1 << c->dim) * (size_t)c->n_halo_dofs * sizeof(double);
+      e = hipMalloc(&c->d_halo, hb);
+      bytes += hb;
     }
     if (e == hipSuccess && c->n_sbm > 0) {
       const size_t fb = (size_t)c->n_sbm * 2 * c->nq_face * sizeof(double);
