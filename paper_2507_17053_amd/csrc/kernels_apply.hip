@@ -432,7 +432,12 @@ struct BrickCfg {
   static constexpr int EPB0 = NT / NP;
   static constexpr int EPB = EPB0 < 1 ? 1 : EPB0;   // cells per batch
   static constexpr int NG = (NT + NP - 1) / NP;      // thread groups (the last may be partial)
-  static constexpr int SMEM = (2 * NL > NL + 2 * NG * NB) ? 2 * NL : NL + 2 * NG * NB;
+  // LDS in doubles: the lattice accumulator (FP64 in both precisions: LDS atomic adds in FP32
+  // were measured ~20x slower than in FP64 on gfx950), then either the two sweep arrays of
+  // the full path (in FP64 the first one is the accumulator itself) or the per-cell tiles.
+  static constexpr int TAIL_SWEEP = NL;  // FP64: LB; FP32: LA and LB
+  static constexpr int TAIL_CELLS = (2 * NG * NB * (int)sizeof(T) + 7) / 8;
+  static constexpr int SMEM_D = NL + (TAIL_SWEEP > TAIL_CELLS ? TAIL_SWEEP : TAIL_CELLS);
 };
 
 // Lattice-line segments of a full brick.  A line of B cells has B p + 1 nodes; the segment of
@@ -466,8 +471,9 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
   constexpr int BX = C::BX, BY = C::BY, BZ = C::BZ, LX = C::LX, LY = C::LY, LZ = C::LZ;
   constexpr int NL = C::NL, NROWS = C::NROWS;
   static_assert(LX <= 32, "row masks hold 32 points");
-  __shared__ T smem[C::SMEM];
-  T *acc = smem;  // the brick lattice (both paths)
+  __shared__ double smem_d[C::SMEM_D];
+  double *acc = smem_d;                       // the brick lattice (both paths), FP64
+  T *const tail = (T *)(smem_d + NL);         // per-cell tiles, or the FP32 sweep arrays
   const int brick = xcd_block();
   const int tid = threadIdx.x;
   constexpr int nthr = C::NT;  // the launch uses exactly NT threads
@@ -493,7 +499,10 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     // the Kronecker sum of the 1D operators assembled along each direction; sweep the
     // brick lattice line by line (a = M u, b = K u along the last axis, then c = M a,
     // e = K a + M b, then h (K c + M e)), in place in LDS. ----
-    T *LA = smem, *LB = smem + NL;
+    // sweep arrays: FP64 a/c in the accumulator itself (the last sweep writes in place),
+    // FP32 both in the tail (the last sweep writes the accumulator)
+    T *const LA = (sizeof(T) == sizeof(double)) ? (T *)smem_d : tail;
+    T *const LB = (sizeof(T) == sizeof(double)) ? tail : tail + NL;
     // last axis (z in 3D, y in 2D): a = M u, b = K u, gathered from u (every point of a full
     // brick is a DoF: id = row base + x)
     {
@@ -597,14 +606,14 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
         yo[0] += from_prev_lane<G>(yo[P], j);
         if (live) {
 #pragma unroll
-          for (int i = 0; i < P; ++i) LA[o + i] = yo[i];
-          if (j == BX - 1) LA[o + P] = yo[P];
+          for (int i = 0; i < P; ++i) acc[o + i] = (double)yo[i];
+          if (j == BX - 1) acc[o + P] = (double)yo[P];
         }
       }
     }
     __syncthreads();
   } else {
-    for (int i = tid; i < NL; i += nthr) acc[i] = T(0);
+    for (int i = tid; i < NL; i += nthr) acc[i] = 0.0;
     __syncthreads();
   }
 
@@ -612,7 +621,7 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     // ---- partial brick: cell by cell (EPB cells per batch; a trailing group of fewer than
     // NP threads only takes part in the barriers) ----
     constexpr int NG = C::NG;
-    T *A = smem + NL + le * NB, *B = smem + NL + NG * NB + le * NB;
+    T *A = tail + le * NB, *B = tail + NG * NB + le * NB;
     const bool grp = le < EPB;
     // software pipeline: the pencils of batch b+1 are in flight while batch b computes
     T x[N1];
@@ -631,7 +640,7 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
       kron_cell<T, D, N1>(tab, t, x, A, B, scale, out);
       if (act) {
 #pragma unroll
-        for (int i = 0; i < N1; ++i) atomicAdd(&acc[loc + run_off + i], out[i]);
+        for (int i = 0; i < N1; ++i) atomicAdd(&acc[loc + run_off + i], (double)out[i]);
       }
 #pragma unroll
       for (int i = 0; i < N1; ++i) x[i] = xn[i];
@@ -657,7 +666,8 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
         const int Sc = (D == 3) ? ((a == 2) ? SL1 : SL2) : 0;
         const int node = loc + jb * Sb + jc * Sc;
 #pragma unroll
-        for (int ia = 0; ia < N1; ++ia) atomicAdd(&acc[node + ia * Sa], face_row<T, D, N1>(tab, fa, ia, Rv, Rg));
+        for (int ia = 0; ia < N1; ++ia)
+          atomicAdd(&acc[node + ia * Sa], (double)face_row<T, D, N1>(tab, fa, ia, Rv, Rg));
       }
     }
   }
@@ -684,7 +694,7 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     const int plane = (x == 0 ? 1 : 0) | (y == 0 ? 2 : 0) | ((D == 3 && z == 0) ? 4 : 0);
     T *dst = inner ? v + s_base[row] + __popc(gm & below)
                    : halo + (int64_t)plane * nhalo + s_hbase[row] + __popc(hgm & below);
-    const T val = acc[ptc];
+    const T val = (T)acc[ptc];
     if (pt < NL && ((bm >> x) & 1u)) *dst = val;
   }
 }
