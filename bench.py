@@ -129,25 +129,30 @@ def cpu_baseline(w, budget_s=12.0):
 
 
 SOLVE_CASES = [
-    # (name, workload, overrides, max_it)
-    ("disk2d_q2", "disk2d_q2", {}, 8000),  # converges with restart 64
-    ("torus3d_dg_q3", "torus3d_dg", {"p": 3}, 3000),
-    ("sphere3d_q4", "sphere3d_q4", {}, 1500),
+    # (name, workload, overrides, shift_scale, (FP64 mode, mixed mode), max_it)
+    ("disk2d_q2", "disk2d_q2", {}, 1.0, ("gmres", "gmres_ir"), 8000),
+    ("sphere3d_q1_n64", "sphere3d_q4", {"p": 1}, 1.0, ("gmres", "gmres_ir"), 4000),
+    # the symmetric limit of the 3D Q4 workload (shift 0): CG applies, full size
+    ("sphere3d_q4_unshifted", "sphere3d_q4", {}, 0.0, ("cg", "cg_ir"), 4000),
+    # the shifted 3D Q4 workload: restarted GMRES stagnates (indefinite operator); reported
+    ("sphere3d_q4", "sphere3d_q4", {}, 1.0, ("gmres", "gmres_ir"), 300),
 ]
 
 
 def solve_section(torch, sbm, inputs):
-    """FP64 GMRES vs FP32-inner GMRES with FP64 refinement, same restart length, to 1e-10."""
+    """FP64 Krylov vs FP64 refinement around the same Krylov method in FP32, to 1e-10: GMRES(64)
+    for the shifted (nonsymmetric) operators, CG for the symmetric limit."""
     out = []
-    for name, wname, over, max_it in SOLVE_CASES:
+    for name, wname, over, shift, modes, max_it in SOLVE_CASES:
         w = inputs.workload(wname, **over)
-        op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"])
+        op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"],
+                          shift_scale=shift)
         u_fn, f_fn = inputs.manufactured(w["d"])
         cq, bp = op.rhs_points()
         b = torch.empty(op.n_dofs, dtype=torch.float64, device="cuda")
         op.rhs(f_fn(cq.reshape(-1, w["d"])), u_fn(bp.reshape(-1, w["d"])), b)
-        rec = {"case": name, "n_dofs": op.n_dofs}
-        for mode in ("gmres", "gmres_ir"):
+        rec = {"case": name, "n_dofs": op.n_dofs, "shift_scale": shift}
+        for mode in modes:
             x = torch.zeros_like(b)
             info = op.solve(b, x, rel_tol=1e-10, max_it=max_it, mode=mode, restart=64)
             rec[mode] = {"status": sbm.status_name(info["status"]), "seconds": info["seconds"],
@@ -155,7 +160,7 @@ def solve_section(torch, sbm, inputs):
                          "applies_f64": info["applies_f64"], "applies_f32": info["applies_f32"],
                          "rel_residual_f64": info["rel_residual"]}
             print(f"solve {name} {mode}: {rec[mode]}", file=sys.stderr, flush=True)
-        g, r = rec["gmres"], rec["gmres_ir"]
+        g, r = rec[modes[0]], rec[modes[1]]
         if g["status"] == "SBM_OK" and r["status"] == "SBM_OK":
             rec["ir_speedup"] = g["seconds"] / r["seconds"]
         out.append(rec)

@@ -187,8 +187,12 @@ sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double 
 enum {
   SBM_SOLVE_GMRES_F64 = 0,  /* restarted GMRES(m) in FP64 */
   SBM_SOLVE_GMRES_IR = 1,   /* FP64 iterative refinement around FP32 GMRES(m) */
-  SBM_SOLVE_CG_F64 = 2      /* conjugate gradients in FP64: only for symmetric operators
+  SBM_SOLVE_CG_F64 = 2,     /* conjugate gradients in FP64: only for symmetric operators
                                (shift_scale = 0); the shifted operator is nonsymmetric */
+  SBM_SOLVE_CG_IR = 3       /* FP64 iterative refinement around FP32 conjugate gradients:
+                               r = b - A x, |r| and x += |r| c in FP64, each inner FP32 CG
+                               solves A c = r / |r| to max(1e-6, tol |b| / (2 |r|));
+                               symmetric operators only */
 };
 
 typedef struct {

@@ -151,23 +151,93 @@ __global__ void copy_kernel(const T *__restrict__ a, T *__restrict__ b, int64_t 
     b[k] = a[k];
 }
 
-// CG updates with device scalars: x += alpha p, r -= alpha q with alpha = rr / pq
-__global__ void cg_xr_kernel(double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
-                             const double *__restrict__ q, const double *__restrict__ rr,
-                             const double *__restrict__ pq, int64_t n) {
-  const double alpha = *rr / *pq;
-  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
-    x[k] += alpha * p[k];
-    r[k] -= alpha * q[k];
+// ---- conjugate gradients: three fused kernels per iteration besides the apply, scalars in
+// FP64 on the device, reductions as block partials summed in a fixed order ----
+
+// Sum of the nblk block partials in a fixed order; every thread (and every block, since all
+// blocks run the same code on the same data) gets the identical value.
+__device__ __forceinline__ double block_sum(const double *__restrict__ part, int nblk) {
+  __shared__ double red[kThreads];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) s += part[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double tot = red[0];
+  __syncthreads();
+  return tot;
+}
+
+// part[blockIdx.x] = sum of acc over the block (fixed order)
+__device__ __forceinline__ void block_partial(double acc, double *__restrict__ part) {
+  __shared__ double red[kThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    part[blockIdx.x] = s;
   }
 }
 
-// p = r + (rr_new / rr_old) p
-__global__ void cg_p_kernel(double *__restrict__ p, const double *__restrict__ r, const double *__restrict__ rr_new,
-                            const double *__restrict__ rr_old, int64_t n) {
-  const double beta = *rr_new / *rr_old;
+// r = rhs - q, p = r; partials of |r|^2
+template <typename T>
+__global__ __launch_bounds__(kThreads) void cg_init_kernel(const T *__restrict__ rhs, const T *__restrict__ q,
+                                                           T *__restrict__ r, T *__restrict__ p,
+                                                           double *__restrict__ part, int64_t n) {
+  double acc = 0.0;
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
+    const T rk = rhs[k] - q[k];
+    r[k] = rk;
+    p[k] = rk;
+    acc += (double)rk * (double)rk;
+  }
+  block_partial(acc, part);
+}
+
+// partials of p . q
+template <typename T>
+__global__ __launch_bounds__(kThreads) void cg_dot_kernel(const T *__restrict__ p, const T *__restrict__ q,
+                                                          double *__restrict__ part, int64_t n) {
+  double acc = 0.0;
   for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
-    p[k] = r[k] + beta * p[k];
+    acc += (double)p[k] * (double)q[k];
+  block_partial(acc, part);
+}
+
+// alpha = |r|^2 / (p . q); x += alpha p; r -= alpha q; partials of the new |r|^2
+template <typename T>
+__global__ __launch_bounds__(kThreads) void cg_update_kernel(T *__restrict__ x, T *__restrict__ r,
+                                                             const T *__restrict__ p, const T *__restrict__ q,
+                                                             const double *__restrict__ rr,
+                                                             const double *__restrict__ part_pq, int nblk,
+                                                             double *__restrict__ part_rr, int64_t n) {
+  const double alpha = *rr / block_sum(part_pq, nblk);
+  double acc = 0.0;
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
+    x[k] = (T)((double)x[k] + alpha * (double)p[k]);
+    const T rk = (T)((double)r[k] - alpha * (double)q[k]);
+    r[k] = rk;
+    acc += (double)rk * (double)rk;
+  }
+  block_partial(acc, part_rr);
+}
+
+// beta = |r_new|^2 / |r|^2; p = r + beta p; |r_new|^2 stored for the next iteration
+template <typename T>
+__global__ __launch_bounds__(kThreads) void cg_dir_kernel(T *__restrict__ p, const T *__restrict__ r,
+                                                          const double *__restrict__ rr,
+                                                          const double *__restrict__ part_rr, int nblk,
+                                                          double *__restrict__ rr_new, int64_t n) {
+  const double rn = block_sum(part_rr, nblk);
+  const double beta = rn / *rr;
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    p[k] = (T)((double)r[k] + beta * (double)p[k]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *rr_new = rn;
 }
 
 }  // namespace
@@ -333,6 +403,46 @@ static sbm_status gmres_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *V, T *w
   }
 }
 
+// Conjugate gradients in precision T on A_T (prec), for symmetric positive definite
+// operators: solves A c = rhs from the initial c to a recursive residual norm <= tol_abs, at
+// most max_it iterations (r, p, q: work vectors).  The residual norm is read back every 10
+// iterations.  Uses ws->partial (2 kMaxBlocks) and ws->y[0..1] (|r|^2, alternating).
+template <typename T>
+static sbm_status cg_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *r, T *p, T *q, double tol_abs, int max_it,
+                         hipStream_t s, int *its_out, int *applies, double *res_out) {
+  Workspace *ws = c->ws;
+  const int64_t n = c->n_dofs;
+  const int nb = nblocks(n);
+  double *part_pq = ws->partial, *part_rr = ws->partial + kMaxBlocks;
+  double *rr = ws->y;
+  SBM_HIP_CHECK(launch_apply(c, x, q, prec, SBM_PART_ALL, s));
+  ++*applies;
+  hipLaunchKernelGGL(cg_init_kernel<T>, dim3(nb), dim3(kThreads), 0, s, rhs, q, r, p, part_rr, n);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, s, part_rr, nb, 1, rr);
+  int it = 0;
+  double res = 0.0;
+  for (;; ++it) {
+    const int cur = it & 1;
+    if (it % 10 == 0 || it >= max_it) {
+      double v = 0.0;
+      SBM_HIP_CHECK(hipMemcpyAsync(&v, rr + cur, sizeof(double), hipMemcpyDeviceToHost, s));
+      SBM_HIP_CHECK(hipStreamSynchronize(s));
+      res = std::sqrt(v);
+      if (!(res > tol_abs) || !std::isfinite(res) || it >= max_it) break;
+    }
+    SBM_HIP_CHECK(launch_apply(c, p, q, prec, SBM_PART_ALL, s));
+    ++*applies;
+    hipLaunchKernelGGL(cg_dot_kernel<T>, dim3(nb), dim3(kThreads), 0, s, p, q, part_pq, n);
+    hipLaunchKernelGGL(cg_update_kernel<T>, dim3(nb), dim3(kThreads), 0, s, x, r, p, q, rr + cur, part_pq, nb,
+                       part_rr, n);
+    hipLaunchKernelGGL(cg_dir_kernel<T>, dim3(nb), dim3(kThreads), 0, s, p, r, rr + cur, part_rr, nb, rr + (1 - cur),
+                       n);
+  }
+  *its_out = it;
+  *res_out = res;
+  return SBM_OK;
+}
+
 }  // namespace sbm
 
 using namespace sbm;
@@ -441,7 +551,8 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
   if (!info) info = &loc;
   std::memset(info, 0, sizeof(*info));
   if (!h || h->host_only || (h->n_dofs > 0 && (!b || !x)) || !(rel_tol > 0) || max_it < 1 ||
-      (mode != SBM_SOLVE_GMRES_F64 && mode != SBM_SOLVE_GMRES_IR && mode != SBM_SOLVE_CG_F64)) {
+      (mode != SBM_SOLVE_GMRES_F64 && mode != SBM_SOLVE_GMRES_IR && mode != SBM_SOLVE_CG_F64 &&
+       mode != SBM_SOLVE_CG_IR)) {
     set_error("sbm_solve: invalid argument");
     info->status = SBM_EINVAL;
     return SBM_EINVAL;
@@ -451,8 +562,10 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
     return SBM_OK;
   }
   hipStream_t s = (hipStream_t)stream;
-  const int m = restart > 0 ? std::min(restart, 64) : 50;
-  hipError_t e = ensure_workspace(h, m, mode == SBM_SOLVE_GMRES_IR);
+  const bool cg = mode == SBM_SOLVE_CG_F64 || mode == SBM_SOLVE_CG_IR;
+  // CG needs no Krylov basis: one spare column of it serves as a work vector
+  const int m = cg ? 1 : (restart > 0 ? std::min(restart, 64) : 50);
+  hipError_t e = ensure_workspace(h, m, mode == SBM_SOLVE_GMRES_IR || mode == SBM_SOLVE_CG_IR);
   if (e != hipSuccess) {
     set_error(std::string("sbm_solve: workspace allocation failed: ") + hipGetErrorString(e));
     info->status = SBM_ENOMEM;
@@ -532,34 +645,47 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
       if (its == 0) break;
     }
     info->inner_its = total_its;
-  } else {
+  } else if (mode == SBM_SOLVE_CG_F64) {
     // CG (symmetric operators only)
-    double *r = ws->r, *p = ws->z, *q = ws->t;
-    double *dev = ws->h;  // [0]=rr, [1]=pq, [2]=rr_new
-    SBM_HIP_CHECK(launch_apply(h, x, q, SBM_F64, SBM_PART_ALL, s));
-    ++info->applies_f64;
-    hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, q, r, n);
-    hipLaunchKernelGGL(copy_kernel<double>, dim3(nb), dim3(kThreads), 0, s, r, p, n);
-    SBM_HIP_CHECK(multidot<double>(r, n, 1, r, n, ws->partial, dev, s));
-    int it = 0;
-    for (; it < max_it; ++it) {
-      double rr = 0.0;
-      if (it % 10 == 0) {
-        SBM_HIP_CHECK(hipMemcpyAsync(&rr, dev, sizeof(double), hipMemcpyDeviceToHost, s));
-        SBM_HIP_CHECK(hipStreamSynchronize(s));
-        res = std::sqrt(rr);
-        if (!(res > tol_abs) || !std::isfinite(res)) break;
-      }
-      SBM_HIP_CHECK(launch_apply(h, p, q, SBM_F64, SBM_PART_ALL, s));
-      ++info->applies_f64;
-      SBM_HIP_CHECK(multidot<double>(p, n, 1, q, n, ws->partial, dev + 1, s));
-      hipLaunchKernelGGL(cg_xr_kernel, dim3(nb), dim3(kThreads), 0, s, x, r, p, q, dev, dev + 1, n);
-      SBM_HIP_CHECK(multidot<double>(r, n, 1, r, n, ws->partial, dev + 2, s));
-      hipLaunchKernelGGL(cg_p_kernel, dim3(nb), dim3(kThreads), 0, s, p, r, dev + 2, dev, n);
-      SBM_HIP_CHECK(hipMemcpyAsync(dev, dev + 2, sizeof(double), hipMemcpyDeviceToDevice, s));
-    }
-    info->inner_its = it;
+    int its = 0, applies = 0;
+    st = cg_run<double>(h, SBM_F64, b, x, ws->r, ws->z, ws->t, tol_abs, max_it, s, &its, &applies, &res);
+    info->inner_its = its;
     info->outer_its = 1;
+    info->applies_f64 = applies;
+  } else {
+    // FP64 refinement around FP32 CG: r = b - A x and |r| in FP64, c ~= A32^-1 (r / |r|) by
+    // FP32 CG, x += |r| c in FP64.  The inner tolerance is what the remaining reduction needs
+    // (half of tol / |r|), but not below 1e-6 (FP32): every restart of CG discards its Krylov
+    // space, so each inner solve should do as much of the work as FP32 allows.
+    int total_its = 0;
+    for (int outer = 0;; ++outer) {
+      SBM_HIP_CHECK(launch_apply(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
+      ++info->applies_f64;
+      hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
+      SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));  // |r|^2 stays in h[0]
+      double rn2 = 0.0;
+      SBM_HIP_CHECK(hipMemcpyAsync(&rn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
+      SBM_HIP_CHECK(hipStreamSynchronize(s));
+      res = std::sqrt(rn2);
+      info->outer_its = outer;
+      if (!(res > tol_abs) || total_its >= max_it || !std::isfinite(res)) break;
+      hipLaunchKernelGGL(to_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->r, ws->h, ws->r32, n);
+      hipLaunchKernelGGL(fill_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, n);
+      int its = 0, applies = 0;
+      double inner_res = 0.0;
+      const double inner_tol = std::max(1e-6, 0.5 * tol_abs / res);
+      const sbm_status ist = cg_run<float>(h, SBM_F32, ws->r32, ws->c32, ws->w32, ws->z32, ws->V32, inner_tol,
+                                           max_it - total_its, s, &its, &applies, &inner_res);
+      if (ist != SBM_OK) {
+        info->status = ist;
+        return ist;
+      }
+      total_its += its;
+      info->applies_f32 += applies;
+      hipLaunchKernelGGL(add_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, ws->h, x, n);
+      if (its == 0) break;
+    }
+    info->inner_its = total_its;
   }
   // final true residual in FP64
   SBM_HIP_CHECK(launch_apply(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
