@@ -101,6 +101,49 @@ def time_launches(torch, fn, k, graph_batch=20):
     return e0.elapsed_time(e1) / 1e3 / k, wall / k, k
 
 
+OTHER_CONFIGS = [
+    # (label, workload, overrides)
+    ("torus3d_dg_q3", "torus3d_dg", {}),
+    ("torus3d_dg_q5", "torus3d_dg", {"p": 5}),
+    ("spheres3d_q6", "spheres3d_q6", {}),
+    # working set (vectors alone 229 MB in FP64) above the 256 MB last-level cache together
+    ("sphere3d_q4_n128", "sphere3d_q4", {"n": 128}),
+]
+
+
+def configs_section(torch, sbm, inputs, steps, graph_batch):
+    """FP64 and FP32 apply of the other workloads: DoF/s, effective bandwidth on the
+    algorithmic bytes, and the FP32 result's relative deviation from the FP64 one."""
+    out = []
+    for label, name, over in OTHER_CONFIGS:
+        w = inputs.workload(name, **over)
+        t0 = time.perf_counter()
+        op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"])
+        t_setup = time.perf_counter() - t0
+        u64 = torch.from_numpy(inputs.uniform_vector(op.n_dofs, seed=0)).to("cuda")
+        u32 = u64.float()
+        v64, v32 = torch.empty_like(u64), torch.empty_like(u32)
+        rec = {"config": label, "d": op.d, "p": op.p, "n": w["n"], "disc": op.disc, "n_dofs": op.n_dofs,
+               "n_cells": op.n_cells, "n_sbm_faces": op.n_sbm_faces, "setup_s": t_setup}
+        for prec, (u, v, s) in {"f64": (u64, v64, 8), "f32": (u32, v32, 4)}.items():
+            for _ in range(5):
+                op.apply(u, v)
+            t, _, n = time_launches(torch, lambda: op.apply(u, v), steps, graph_batch)
+            gbs = algorithmic_bytes(op, s, "apply") / t / 1e9
+            rec[prec] = {"dofs_per_s": op.n_dofs / t, "ms_per_apply": t * 1e3, "applies": n,
+                         "effective_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+        op.apply(u64, v64)
+        op.apply(u32, v32)
+        torch.cuda.synchronize()
+        rec["f32_rel_dev_from_f64"] = float((v32.double() - v64).norm() / v64.norm())
+        out.append(rec)
+        print(f"# config {label}: f64 {rec['f64']['ms_per_apply']:.4f} ms, f32 {rec['f32']['ms_per_apply']:.4f} ms",
+              file=sys.stderr, flush=True)
+        del op, u64, u32, v64, v32
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The brute-force C oracle (OpenMP) on this host, on the same workload: as many full
     applies as fit in about budget_s seconds (at least one)."""
@@ -210,6 +253,7 @@ def main():
     ap.add_argument("--workload", default="sphere3d_q4")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' applies")
     ap.add_argument("--solve", action="store_true", help="also time the FP64 and FP32+IR solves")
     ap.add_argument("--profile-run", action="store_true", help="few eager applies + copies (counter runs)")
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving stream (0: skip)")
@@ -297,6 +341,8 @@ def main():
                  "brick_kernel_frac": res["f32"]["b_brick"] / res["f32"]["t_brick"] / 1e9 / HBM_PEAK_GBS},
         "setup_s": t_setup,
     }
+    if not args.no_configs:
+        out["other_configs"] = configs_section(torch, sbm, inputs, min(args.steps, 200), gb)
     if args.solve:
         out["solve"] = solve_section(torch, sbm, inputs)
     if args.serve > 0:
