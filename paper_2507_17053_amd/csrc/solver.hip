@@ -12,6 +12,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "sbm_internal.h"
@@ -240,6 +242,61 @@ __global__ __launch_bounds__(kThreads) void cg_dir_kernel(T *__restrict__ p, con
   if (blockIdx.x == 0 && threadIdx.x == 0) *rr_new = rn;
 }
 
+// Device side of Arnoldi step j of restarted GMRES (one thread): column j of the Hessenberg
+// matrix (H, (m+1) x m, row-major with row stride m) from the two projection passes h1, h2
+// and the norm of the orthogonalised vector, the rotations of steps < j applied to it, the new
+// Givens rotation (cs, sn), the rotated right-hand side g, the residual estimate |g_(j+1)| in
+// res[j] (-1 on breakdown), and the factor 1 / h_(j+1,j) (0 on breakdown) that normalises
+// the next basis vector.
+__global__ void arnoldi_step_kernel(int j, int m, const double *__restrict__ h1, const double *__restrict__ h2,
+                                    const double *__restrict__ nrm2, double *__restrict__ H,
+                                    double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
+                                    double *__restrict__ res, double *__restrict__ fac) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = h1[i] + h2[i];
+  const double hn = sqrt(*nrm2);
+  *fac = hn > 0.0 ? 1.0 / hn : 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double a = H[(int64_t)i * m + j], b = H[(int64_t)(i + 1) * m + j];
+    H[(int64_t)i * m + j] = cs[i] * a + sn[i] * b;
+    H[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = H[(int64_t)j * m + j], b = hn;
+  const double rr = hypot(a, b);
+  cs[j] = rr > 0.0 ? a / rr : 1.0;
+  sn[j] = rr > 0.0 ? b / rr : 0.0;
+  H[(int64_t)j * m + j] = rr;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  res[j] = rr > 0.0 ? fabs(g[j + 1]) : -1.0;
+}
+
+// g = (sqrt(*nrm2), 0, ..., 0), m + 1 entries
+__global__ void gmres_init_kernel(const double *__restrict__ nrm2, double *__restrict__ g, int m) {
+  for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = i == 0 ? sqrt(*nrm2) : 0.0;
+}
+
+// y = R^-1 g for the leading j x j upper triangle R of H (one thread)
+__global__ void backsub_kernel(int j, int m, const double *__restrict__ H, const double *__restrict__ g,
+                               double *__restrict__ y) {
+  if (threadIdx.x != 0) return;
+  for (int i = j - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int k = i + 1; k < j; ++k) s -= H[(int64_t)i * m + k] * y[k];
+    const double d = H[(int64_t)i * m + i];
+    y[i] = d != 0.0 ? s / d : 0.0;
+  }
+}
+
+// y = x * (*fac)
+template <typename T>
+__global__ void scale_by_kernel(const T *__restrict__ x, const double *__restrict__ fac, T *__restrict__ y,
+                                int64_t n) {
+  const double f = *fac;
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
+    y[k] = (T)((double)x[k] * f);
+}
+
 }  // namespace
 
 struct Workspace {
@@ -254,16 +311,23 @@ struct Workspace {
   float *w32 = nullptr, *c32 = nullptr, *z32 = nullptr, *r32 = nullptr, *dinv32 = nullptr;
   // reductions
   double *partial = nullptr;  // kMaxBlocks x (m+2)
-  double *h = nullptr;        // m+2 device scalars (also scratch)
-  double *y = nullptr;        // m+1 coefficients for the update
+  double *h = nullptr;        // 3 (m+2) device scalars: two projection passes and a norm (also scratch)
+  double *y = nullptr;        // m+2 coefficients for the update (slot m+1: scratch of the refinement)
+  double *gm = nullptr;       // GMRES state: H ((m+1) x m), cs, sn (m), g (m+1), res (m), factor
   bool have_diag = false;
+  // Arnoldi steps captured once and replayed: key (precision, preconditioned, restart length,
+  // first step, end step) -> executable graph; they hold this workspace's pointers
+  std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> chunks;
+  hipStream_t cap = nullptr;  // capture stream (default priority)
 };
 
 void free_workspace(sbm_ctx *c) {
   Workspace *ws = c->ws;
   if (!ws) return;
   void *ptrs[] = {ws->V,   ws->w,   ws->r,    ws->t,       ws->z, ws->dinv, ws->V32, ws->w32,
-                  ws->c32, ws->z32, ws->r32, ws->dinv32, ws->partial, ws->h, ws->y};
+                  ws->c32, ws->z32, ws->r32, ws->dinv32, ws->partial, ws->h, ws->y, ws->gm};
+  for (auto &kv : ws->chunks) (void)hipGraphExecDestroy(kv.second);
+  if (ws->cap) (void)hipStreamDestroy(ws->cap);
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete ws;
@@ -285,8 +349,9 @@ static hipError_t ensure_workspace(sbm_ctx *c, int m, bool need32) {
   if (e == hipSuccess) e = hipMalloc(&ws->t, sizeof(double) * n);
   if (e == hipSuccess) e = hipMalloc(&ws->z, sizeof(double) * n);
   if (e == hipSuccess) e = hipMalloc(&ws->partial, sizeof(double) * kMaxBlocks * (m + 2));
-  if (e == hipSuccess) e = hipMalloc(&ws->h, sizeof(double) * (m + 2));
+  if (e == hipSuccess) e = hipMalloc(&ws->h, sizeof(double) * 3 * (m + 2));
   if (e == hipSuccess) e = hipMalloc(&ws->y, sizeof(double) * (m + 2));
+  if (e == hipSuccess) e = hipMalloc(&ws->gm, sizeof(double) * ((size_t)(m + 1) * m + 4 * m + 2));
   if (e == hipSuccess && need32) {
     e = hipMalloc(&ws->V32, sizeof(float) * n * (m + 1));
     if (e == hipSuccess) e = hipMalloc(&ws->w32, sizeof(float) * n);
@@ -314,17 +379,89 @@ static hipError_t multidot(const T *V, int64_t ld, int ncol, const T *w, int64_t
   return hipGetLastError();
 }
 
+// Arnoldi steps j <= k < j1 of restarted GMRES(m) on the basis V (column k + 1 is formed from
+// column k): w = A M^-1 v_k, two classical Gram-Schmidt passes (CGS2), the norm, the device
+// rotation update (arnoldi_step_kernel) and v_(k+1) = w / h_(k+1,k).  Launches only (no host
+// synchronisation, no memory set), so the sequence can be captured.
+template <typename T>
+static sbm_status arnoldi_steps(sbm_ctx *c, int prec, T *V, T *w, T *z, const T *dinv, int m, int j, int j1,
+                                hipStream_t s) {
+  Workspace *ws = c->ws;
+  const int64_t n = c->n_dofs;
+  const int nb = nblocks(n);
+  double *h1 = ws->h, *h2 = ws->h + (m + 2), *hn = ws->h + 2 * (m + 2);
+  double *H = ws->gm, *cs = H + (size_t)(m + 1) * m, *sn = cs + m, *g = sn + m, *dres = g + (m + 1);
+  double *fac = dres + m;
+  for (int k = j; k < j1; ++k) {
+    T *vk = V + (int64_t)k * n, *vn = V + (int64_t)(k + 1) * n;
+    const T *src = vk;
+    if (dinv) {
+      hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, dinv, vk, z, n);
+      src = z;
+    }
+    SBM_HIP_CHECK(launch_apply(c, src, w, prec, SBM_PART_ALL, s));
+    SBM_HIP_CHECK(multidot<T>(V, n, k + 1, w, n, ws->partial, h1, s));
+    hipLaunchKernelGGL(multiaxpy_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, n, k + 1, h1, w, n);
+    SBM_HIP_CHECK(multidot<T>(V, n, k + 1, w, n, ws->partial, h2, s));
+    hipLaunchKernelGGL(multiaxpy_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, n, k + 1, h2, w, n);
+    SBM_HIP_CHECK(multidot<T>(w, n, 1, w, n, ws->partial, hn, s));
+    hipLaunchKernelGGL(arnoldi_step_kernel, dim3(1), dim3(64), 0, s, k, m, h1, h2, hn, H, cs, sn, g, dres, fac);
+    hipLaunchKernelGGL(scale_by_kernel<T>, dim3(nb), dim3(kThreads), 0, s, w, fac, vn, n);
+  }
+  SBM_HIP_CHECK(hipGetLastError());
+  return SBM_OK;
+}
+
+// The executable graph of arnoldi_steps(j, j1) for this workspace, captured on first use (on
+// a private stream, so the caller's stream may be the null stream) and kept with it.
+template <typename T>
+static sbm_status arnoldi_graph(sbm_ctx *c, int prec, T *V, T *w, T *z, const T *dinv, int m, int j, int j1,
+                                hipGraphExec_t *out) {
+  Workspace *ws = c->ws;
+  const auto key = std::make_tuple(prec, dinv ? 1 : 0, m, j, j1);
+  const auto it = ws->chunks.find(key);
+  if (it != ws->chunks.end()) {
+    *out = it->second;
+    return SBM_OK;
+  }
+  if (!ws->cap) SBM_HIP_CHECK(hipStreamCreateWithFlags(&ws->cap, hipStreamNonBlocking));
+  SBM_HIP_CHECK(hipStreamBeginCapture(ws->cap, hipStreamCaptureModeThreadLocal));
+  const sbm_status st = arnoldi_steps<T>(c, prec, V, w, z, dinv, m, j, j1, ws->cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(ws->cap, &graph);
+  if (st != SBM_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != SBM_OK) return st;
+    SBM_HIP_CHECK(e);
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  SBM_HIP_CHECK(ei);
+  ws->chunks[key] = ex;
+  *out = ex;
+  return SBM_OK;
+}
+
 // One restarted-GMRES run in precision T on A_T (prec) with optional right Jacobi
 // preconditioning.  Solves A c = rhs to ||rhs - A c|| <= tol_abs starting from c (device),
 // at most max_it iterations.  Returns the final true residual norm in *res (FP64, device
 // computed) and the iteration count in *its.
+//
+// The Arnoldi steps, the Givens rotations and the back substitution run on the device; the
+// host reads the residual estimates back every few steps (the steps launched past the first
+// one that met the tolerance are discarded: only the leading columns enter the update, so the
+// result and the iteration count are those of a check after every step).
 template <typename T>
 static sbm_status gmres_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *V, T *w, T *z, const T *dinv, int m,
                             double tol_abs, int max_it, hipStream_t s, int *its, int *applies, double *res) {
   Workspace *ws = c->ws;
   const int64_t n = c->n_dofs;
   const int nb = nblocks(n);
-  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), hcol(m + 2);
+  const int check = n > (1 << 20) ? 4 : 8;  // steps between residual read-backs
+  double *hn = ws->h + 2 * (m + 2);
+  double *H = ws->gm, *g = H + (size_t)(m + 1) * m + 2 * m, *dres = g + (m + 1);
+  std::vector<double> rh(m);
   *its = 0;
   double beta = 0.0;
   while (true) {
@@ -332,72 +469,44 @@ static sbm_status gmres_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *V, T *w
     SBM_HIP_CHECK(launch_apply(c, x, w, prec, SBM_PART_ALL, s));
     ++*applies;
     hipLaunchKernelGGL(residual_kernel<T>, dim3(nb), dim3(kThreads), 0, s, rhs, w, V, n);
-    SBM_HIP_CHECK(multidot<T>(V, n, 1, V, n, ws->partial, ws->h, s));
-    SBM_HIP_CHECK(hipMemcpyAsync(&beta, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
+    SBM_HIP_CHECK(multidot<T>(V, n, 1, V, n, ws->partial, hn, s));
+    SBM_HIP_CHECK(hipMemcpyAsync(&beta, hn, sizeof(double), hipMemcpyDeviceToHost, s));
     SBM_HIP_CHECK(hipStreamSynchronize(s));
     beta = std::sqrt(beta);
     *res = beta;
     if (!(beta > tol_abs) || *its >= max_it) return std::isfinite(beta) ? SBM_OK : SBM_ENOCONV;
-    hipLaunchKernelGGL(scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, ws->h, V, n);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
+    hipLaunchKernelGGL(scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, hn, V, n);
+    hipLaunchKernelGGL(gmres_init_kernel, dim3(1), dim3(64), 0, s, hn, g, m);
     int j = 0;
-    for (; j < m && *its < max_it; ++j) {
-      T *vj = V + (int64_t)j * n, *vn = V + (int64_t)(j + 1) * n;
-      const T *src = vj;
-      if (dinv) {
-        hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, dinv, vj, z, n);
-        src = z;
+    bool stop = false;
+    while (j < m && *its < max_it && !stop) {
+      const int j1 = std::min({m, j + check, j + (max_it - *its)});
+      if (j1 - j == check) {
+        hipGraphExec_t ex = nullptr;
+        const sbm_status st = arnoldi_graph<T>(c, prec, V, w, z, dinv, m, j, j1, &ex);
+        if (st != SBM_OK) return st;
+        SBM_HIP_CHECK(hipGraphLaunch(ex, s));
+      } else {
+        const sbm_status st = arnoldi_steps<T>(c, prec, V, w, z, dinv, m, j, j1, s);
+        if (st != SBM_OK) return st;
       }
-      SBM_HIP_CHECK(launch_apply(c, src, w, prec, SBM_PART_ALL, s));
-      ++*applies;
-      // CGS2: two projection passes; h accumulates both coefficient vectors
-      std::fill(hcol.begin(), hcol.end(), 0.0);
-      for (int pass = 0; pass < 2; ++pass) {
-        SBM_HIP_CHECK(multidot<T>(V, n, j + 1, w, n, ws->partial, ws->h, s));
-        hipLaunchKernelGGL(multiaxpy_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, n, j + 1, ws->h, w, n);
-        std::vector<double> hp(j + 1);
-        SBM_HIP_CHECK(hipMemcpyAsync(hp.data(), ws->h, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-        SBM_HIP_CHECK(hipStreamSynchronize(s));
-        for (int i = 0; i <= j; ++i) hcol[i] += hp[i];
-      }
-      SBM_HIP_CHECK(multidot<T>(w, n, 1, w, n, ws->partial, ws->h + (m + 1), s));
-      double nrm2 = 0.0;
-      SBM_HIP_CHECK(hipMemcpyAsync(&nrm2, ws->h + (m + 1), sizeof(double), hipMemcpyDeviceToHost, s));
+      *applies += j1 - j;
+      SBM_HIP_CHECK(hipMemcpyAsync(rh.data(), dres + j, sizeof(double) * (j1 - j), hipMemcpyDeviceToHost, s));
       SBM_HIP_CHECK(hipStreamSynchronize(s));
-      hcol[j + 1] = std::sqrt(nrm2);
-      if (hcol[j + 1] > 0.0)
-        hipLaunchKernelGGL(scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, w, ws->h + (m + 1), vn, n);
-      // Givens rotations
-      for (int i = 0; i < j; ++i) {
-        const double a = hcol[i], b = hcol[i + 1];
-        hcol[i] = cs[i] * a + sn[i] * b;
-        hcol[i + 1] = -sn[i] * a + cs[i] * b;
-      }
-      const double a = hcol[j], b = hcol[j + 1];
-      const double rr = std::hypot(a, b);
-      cs[j] = rr > 0 ? a / rr : 1.0;
-      sn[j] = rr > 0 ? b / rr : 0.0;
-      hcol[j] = rr;
-      hcol[j + 1] = 0.0;
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++*its;
-      if (std::fabs(g[j + 1]) <= tol_abs || !(rr > 0.0)) {
-        ++j;
-        break;
+      int k = j;
+      while (k < j1 && rh[k - j] > tol_abs) ++k;  // stops at convergence, breakdown (-1) or NaN
+      if (k < j1) {
+        *its += k + 1 - j;
+        j = k + 1;
+        stop = true;
+      } else {
+        *its += j1 - j;
+        j = j1;
       }
     }
-    // back substitution and update x += M^-1 V y
-    std::vector<double> y(j, 0.0);
-    for (int i = j - 1; i >= 0; --i) {
-      double sacc = g[i];
-      for (int k = i + 1; k < j; ++k) sacc -= H[(size_t)i * m + k] * y[k];
-      y[i] = H[(size_t)i * m + i] != 0.0 ? sacc / H[(size_t)i * m + i] : 0.0;
-    }
+    // back substitution and update x += M^-1 V y, from the leading j columns
     if (j > 0) {
-      SBM_HIP_CHECK(hipMemcpyAsync(ws->y, y.data(), sizeof(double) * j, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(backsub_kernel, dim3(1), dim3(64), 0, s, j, m, H, g, ws->y);
       hipLaunchKernelGGL(update_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, n, j, ws->y, dinv, x, n);
     }
   }
