@@ -3,17 +3,17 @@
 // The SBM operator of Eq. (1) is nonsymmetric (the extension E acts on the trial side
 // only) and, with full polynomial extrapolation, indefinite, so the default solver is
 // restarted GMRES(m) with classical Gram-Schmidt and one re-orthogonalisation pass
-// (CGS2: two fused multi-dot / multi-axpy sweeps over the basis).  The mixed-precision
-// mode runs GMRES on the FP32 operator inside FP64 iterative refinement: the outer
-// residual r = b - A x, its norm and the update x += c are FP64 on the device.
-// Reductions are two-pass (block partial sums, then one block in a fixed order), so a
-// solve is deterministic given a deterministic apply.
+// (CGS2).  A step is the operator apply and three Gram-Schmidt kernels, each one pass over
+// the row-tiled basis (products; update fused with the next products; update fused with the
+// norm and the Givens rotation update), so the host reads back only a residual estimate every
+// few steps.  The mixed-precision mode runs GMRES on the FP32 operator inside FP64 iterative
+// refinement: the outer residual r = b - A x, its norm and the update x += c are FP64 on the
+// device.  Reductions are block partial sums added in a fixed order, so a solve is
+// deterministic given a deterministic apply.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
-#include <map>
-#include <tuple>
 #include <vector>
 
 #include "sbm_internal.h"
@@ -23,6 +23,13 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxBlocks = 1024;
+// The GMRES basis is stored in row tiles: the m1 columns of rows [128 t, 128 t + 128) are one
+// contiguous block (column i at offset 128 i), so a sweep over a range of rows and all columns
+// streams contiguous memory.
+constexpr int kTile = 128;
+__host__ __device__ __forceinline__ int64_t tile_ix(int64_t k, int i, int m1) {
+  return ((k / kTile) * m1 + i) * kTile + (k % kTile);
+}
 
 inline int nblocks(int64_t n) {
   int64_t b = (n + kThreads * 8 - 1) / (kThreads * 8);
@@ -70,33 +77,15 @@ __global__ void reduce_partials_kernel(const double *__restrict__ partial, int n
   out[i] = s;
 }
 
-// w -= sum_i coef[i] V_i
+// x += sum_i y[i] Z_i  (Z_i = V_i of the tiled basis with m1 columns, optionally scaled by
+// dinv), y on the device
 template <typename T>
-__global__ __launch_bounds__(kThreads) void multiaxpy_kernel(const T *__restrict__ V, int64_t ld, int ncol,
-                                                             const double *__restrict__ coef, T *__restrict__ w,
-                                                             int64_t n) {
-  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
-    double s = (double)w[k];
-    for (int i = 0; i < ncol; ++i) s -= coef[i] * (double)V[i * ld + k];
-    w[k] = (T)s;
-  }
-}
-
-// y = x * (1 / *nrm)  (nrm on the device)
-template <typename T>
-__global__ void scale_kernel(const T *__restrict__ x, const double *__restrict__ nrm, T *__restrict__ y, int64_t n) {
-  const double inv = 1.0 / sqrt(*nrm);
-  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
-    y[k] = (T)((double)x[k] * inv);
-}
-
-// x += sum_i y[i] Z_i  (Z_i = V_i, optionally scaled by dinv), y on the device
-template <typename T>
-__global__ void update_kernel(const T *__restrict__ V, int64_t ld, int ncol, const double *__restrict__ y,
+__global__ void update_kernel(const T *__restrict__ V, int m1, int ncol, const double *__restrict__ y,
                               const T *__restrict__ dinv, T *__restrict__ x, int64_t n) {
   for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
     double s = 0.0;
-    for (int i = 0; i < ncol; ++i) s += y[i] * (double)V[i * ld + k];
+    const int64_t base = tile_ix(k, 0, m1);
+    for (int i = 0; i < ncol; ++i) s += y[i] * (double)V[base + (int64_t)i * kTile];
     if (dinv) s *= (double)dinv[k];
     x[k] = (T)((double)x[k] + s);
   }
@@ -242,33 +231,173 @@ __global__ __launch_bounds__(kThreads) void cg_dir_kernel(T *__restrict__ p, con
   if (blockIdx.x == 0 && threadIdx.x == 0) *rr_new = rn;
 }
 
-// Device side of Arnoldi step j of restarted GMRES (one thread): column j of the Hessenberg
-// matrix (H, (m+1) x m, row-major with row stride m) from the two projection passes h1, h2
-// and the norm of the orthogonalised vector, the rotations of steps < j applied to it, the new
-// Givens rotation (cs, sn), the rotated right-hand side g, the residual estimate |g_(j+1)| in
-// res[j] (-1 on breakdown), and the factor 1 / h_(j+1,j) (0 on breakdown) that normalises
-// the next basis vector.
-__global__ void arnoldi_step_kernel(int j, int m, const double *__restrict__ h1, const double *__restrict__ h2,
-                                    const double *__restrict__ nrm2, double *__restrict__ H,
-                                    double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
-                                    double *__restrict__ res, double *__restrict__ fac) {
-  if (threadIdx.x != 0) return;
-  for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = h1[i] + h2[i];
-  const double hn = sqrt(*nrm2);
-  *fac = hn > 0.0 ? 1.0 / hn : 0.0;
+// Arnoldi step j of restarted GMRES, done by one thread: column j of the Hessenberg matrix
+// (H, (m+1) x m, row-major with row stride m) from the two projection passes h1, h2 and the
+// squared norm nrm2 of the orthogonalised vector, the rotations of steps < j applied to it, the
+// new Givens rotation (cs, sn), the rotated right-hand side g, the residual estimate
+// |g_(j+1)| in res[j] (-1 on breakdown), and the factor 1 / h_(j+1,j) (0 on breakdown) that
+// normalises the next basis vector.
+struct ArnoldiArgs {
+  int j, m;
+  const double *h1, *h2;
+  double *H, *cs, *sn, *g, *res, *fac;
+};
+
+__device__ void arnoldi_step(const ArnoldiArgs &a, double nrm2) {
+  const int j = a.j, m = a.m;
+  double *H = a.H;
+  for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = a.h1[i] + a.h2[i];
+  const double hn = sqrt(nrm2);
+  *a.fac = hn > 0.0 ? 1.0 / hn : 0.0;
   for (int i = 0; i < j; ++i) {
-    const double a = H[(int64_t)i * m + j], b = H[(int64_t)(i + 1) * m + j];
-    H[(int64_t)i * m + j] = cs[i] * a + sn[i] * b;
-    H[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+    const double x = H[(int64_t)i * m + j], y = H[(int64_t)(i + 1) * m + j];
+    H[(int64_t)i * m + j] = a.cs[i] * x + a.sn[i] * y;
+    H[(int64_t)(i + 1) * m + j] = -a.sn[i] * x + a.cs[i] * y;
   }
-  const double a = H[(int64_t)j * m + j], b = hn;
-  const double rr = hypot(a, b);
-  cs[j] = rr > 0.0 ? a / rr : 1.0;
-  sn[j] = rr > 0.0 ? b / rr : 0.0;
+  const double x = H[(int64_t)j * m + j], y = hn;
+  const double rr = hypot(x, y);
+  a.cs[j] = rr > 0.0 ? x / rr : 1.0;
+  a.sn[j] = rr > 0.0 ? y / rr : 0.0;
   H[(int64_t)j * m + j] = rr;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  res[j] = rr > 0.0 ? fabs(g[j + 1]) : -1.0;
+  a.g[j + 1] = -a.sn[j] * a.g[j];
+  a.g[j] = a.cs[j] * a.g[j];
+  a.res[j] = rr > 0.0 ? fabs(a.g[j + 1]) : -1.0;
+}
+
+// Sum of p[0 .. nblk) (nblk <= kMaxBlocks) by the 64 lanes of one wave in a fixed order:
+// lane l adds p[l + 64 j] over j (all loads issued at once, from clamped indices), then a
+// shuffle tree; the result is valid in lane 0.
+__device__ __forceinline__ double wave_sum(const double *__restrict__ p, int nblk, int lane) {
+  constexpr int NJ = kMaxBlocks / 64;
+  double v[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) v[j] = p[lane + 64 * j < nblk ? lane + 64 * j : 0];
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) s += lane + 64 * j < nblk ? v[j] : 0.0;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  return s;
+}
+
+// One Gram-Schmidt kernel of a GMRES step, in a single launch:
+//   MODE 0: out = V^T w                                  (ncol columns of V)
+//   MODE 1: w -= V coef, then out = V^T w
+//   MODE 2: w -= V coef, then out[0] = w . w and the Arnoldi step (arnoldi_step)
+// V is the tiled basis (tile_ix, m1 columns).
+// Layout: lane l of a wave takes rows l, l + 64, ..., l + 64 (R - 1) of each 64 R-row block
+// (coalesced column reads, R CPW loads in flight per lane); wave q of the 4 owns columns
+// q, q + 4, ... (at most CPW each).  The update sums the four waves' partial products in wave
+// order through LDS; the values of V read for it are reused from registers for the products
+// that follow, so V is read once per launch.  Every block writes its partial sums (column i of
+// block b at partial[i kMaxBlocks + b]); the last block to finish (ticket on *counter, which it
+// resets to 0 for the next launch) adds them in a fixed order, so the result is independent of
+// the block schedule.
+template <typename T, int CPW, int MODE>
+__global__ __launch_bounds__(kThreads) void gs_kernel(const T *__restrict__ V, int m1, int ncol,
+                                                      const double *__restrict__ coef, T *__restrict__ w, int64_t n,
+                                                      double *__restrict__ partial, unsigned *__restrict__ counter,
+                                                      double *__restrict__ out, ArnoldiArgs aa) {
+  constexpr int NW = kThreads / 64, R = 32 / CPW;
+  __shared__ double red[MODE == 0 ? 1 : NW][64 * R];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double acc[CPW], cf[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int i = wave + NW * c;
+    acc[c] = 0.0;
+    cf[c] = (MODE != 0 && i < ncol) ? coef[i] : 0.0;
+  }
+  for (int64_t r0 = (int64_t)blockIdx.x * 64 * R; r0 < n; r0 += (int64_t)gridDim.x * 64 * R) {
+    // unconditional loads from a clamped index (entry 0 outside the range), masked after the
+    // conversion: no branch separates a load from the next, so all of them are in flight at once
+    T tv[R][CPW], tw[R];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const int64_t k = r0 + rr * 64 + lane;
+      const bool ok = k < n;
+      const int64_t base = tile_ix(ok ? k : 0, 0, m1);
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int i = wave + NW * c;
+        tv[rr][c] = V[(ok && i < ncol) ? base + (int64_t)i * kTile : 0];
+      }
+      tw[rr] = w[ok ? k : 0];
+    }
+    double v[R][CPW], wv[R];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const bool ok = r0 + rr * 64 + lane < n;
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) v[rr][c] = (ok && wave + NW * c < ncol) ? (double)tv[rr][c] : 0.0;
+      wv[rr] = ok ? (double)tw[rr] : 0.0;
+    }
+    if constexpr (MODE != 0) {
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        double sp = 0.0;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) sp += cf[c] * v[rr][c];
+        red[wave][rr * 64 + lane] = sp;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const int64_t k = r0 + rr * 64 + lane;
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) sum += red[q][rr * 64 + lane];
+        const T t = (T)(wv[rr] - sum);
+        if (wave == 0 && k < n) w[k] = t;
+        wv[rr] = k < n ? (double)t : 0.0;
+      }
+      __syncthreads();  // red is rewritten by the next row block
+    }
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      if constexpr (MODE == 2) {
+        acc[0] += wv[rr] * wv[rr];
+      } else {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) acc[c] += v[rr][c] * wv[rr];
+      }
+    }
+  }
+  // block partials: column i = wave + NW c (MODE 2: wave 0's sum as column 0)
+  const int nout = MODE == 2 ? 1 : ncol;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int i = wave + NW * c;
+    double sacc = acc[c];
+    for (int off = 32; off > 0; off >>= 1) sacc += __shfl_down(sacc, off, 64);
+    const bool mine = MODE == 2 ? (c == 0 && wave == 0) : i < ncol;
+    if (lane == 0 && mine) partial[(int64_t)i * kMaxBlocks + blockIdx.x] = sacc;
+  }
+  __syncthreads();  // the block's partials are written (each wave waited for its stores)
+  if (threadIdx.x == 0) {
+    __threadfence();  // release: the partials before the ticket
+    last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();  // acquire: the other blocks' partials
+  const int nblk = gridDim.x;
+  if constexpr (MODE == 2) {
+    if (wave == 0) {
+      const double sum = wave_sum(partial, nblk, lane);
+      if (lane == 0) {
+        *out = sum;
+        arnoldi_step(aa, sum);
+        *counter = 0u;
+      }
+    }
+  } else {
+    for (int i = wave; i < nout; i += NW) {
+      const double sum = wave_sum(partial + (int64_t)i * kMaxBlocks, nblk, lane);
+      if (lane == 0) out[i] = sum;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+  }
 }
 
 // g = (sqrt(*nrm2), 0, ..., 0), m + 1 entries
@@ -288,13 +417,17 @@ __global__ void backsub_kernel(int j, int m, const double *__restrict__ H, const
   }
 }
 
-// y = x * (*fac)
+// Basis vector col = x * f, stored in column col of the tiled basis V (m1 columns) and in the
+// contiguous vector vc (the next operator input); f = *fac, or 1 / sqrt(*fac) if inv_sqrt.
 template <typename T>
-__global__ void scale_by_kernel(const T *__restrict__ x, const double *__restrict__ fac, T *__restrict__ y,
-                                int64_t n) {
-  const double f = *fac;
-  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads)
-    y[k] = (T)((double)x[k] * f);
+__global__ void basis_store_kernel(const T *__restrict__ x, const double *__restrict__ fac, int inv_sqrt,
+                                   T *__restrict__ V, int col, int m1, T *__restrict__ vc, int64_t n) {
+  const double f = inv_sqrt ? 1.0 / sqrt(*fac) : *fac;
+  for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
+    const T y = (T)((double)x[k] * f);
+    V[tile_ix(k, col, m1)] = y;
+    vc[k] = y;
+  }
 }
 
 }  // namespace
@@ -303,31 +436,31 @@ struct Workspace {
   int64_t n = 0;
   int m = 0;
   // FP64
-  double *V = nullptr;   // (m+1) x n
+  double *V = nullptr;   // (m+1) columns of the GMRES basis in row tiles (tile_ix), rows padded to kTile
+  double *vc = nullptr;  // newest basis vector, contiguous
   double *w = nullptr, *r = nullptr, *t = nullptr, *z = nullptr;
   double *dinv = nullptr;
   // FP32
-  float *V32 = nullptr;  // (m+1) x n
+  float *V32 = nullptr;  // as V
+  float *vc32 = nullptr;
   float *w32 = nullptr, *c32 = nullptr, *z32 = nullptr, *r32 = nullptr, *dinv32 = nullptr;
   // reductions
   double *partial = nullptr;  // kMaxBlocks x (m+2)
   double *h = nullptr;        // 3 (m+2) device scalars: two projection passes and a norm (also scratch)
   double *y = nullptr;        // m+2 coefficients for the update (slot m+1: scratch of the refinement)
   double *gm = nullptr;       // GMRES state: H ((m+1) x m), cs, sn (m), g (m+1), res (m), factor
+  unsigned *ticket = nullptr; // block counter of the single-pass reductions (0 between launches)
   bool have_diag = false;
-  // Arnoldi steps captured once and replayed: key (precision, preconditioned, restart length,
-  // first step, end step) -> executable graph; they hold this workspace's pointers
-  std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> chunks;
-  hipStream_t cap = nullptr;  // capture stream (default priority)
+  // grid of each Gram-Schmidt kernel: as many blocks as fit on the device at once (no partial
+  // last round), index [FP32][log2(CPW) - 1][MODE]
+  int gs_grid[2][4][3] = {};
 };
 
 void free_workspace(sbm_ctx *c) {
   Workspace *ws = c->ws;
   if (!ws) return;
-  void *ptrs[] = {ws->V,   ws->w,   ws->r,    ws->t,       ws->z, ws->dinv, ws->V32, ws->w32,
-                  ws->c32, ws->z32, ws->r32, ws->dinv32, ws->partial, ws->h, ws->y, ws->gm};
-  for (auto &kv : ws->chunks) (void)hipGraphExecDestroy(kv.second);
-  if (ws->cap) (void)hipStreamDestroy(ws->cap);
+  void *ptrs[] = {ws->V,   ws->vc,  ws->vc32, ws->w,   ws->r,    ws->t,       ws->z, ws->dinv, ws->V32, ws->w32,
+                  ws->c32, ws->z32, ws->r32, ws->dinv32, ws->partial, ws->h, ws->y, ws->gm, ws->ticket};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete ws;
@@ -343,7 +476,9 @@ static hipError_t ensure_workspace(sbm_ctx *c, int m, bool need32) {
   ws->n = c->n_dofs;
   ws->m = m;
   const size_t n = (size_t)std::max<int64_t>(1, c->n_dofs);
-  hipError_t e = hipMalloc(&ws->V, sizeof(double) * n * (m + 1));
+  const size_t npad = (n + kTile - 1) / kTile * kTile;
+  hipError_t e = hipMalloc(&ws->V, sizeof(double) * npad * (m + 1));
+  if (e == hipSuccess) e = hipMalloc(&ws->vc, sizeof(double) * n);
   if (e == hipSuccess) e = hipMalloc(&ws->w, sizeof(double) * n);
   if (e == hipSuccess) e = hipMalloc(&ws->r, sizeof(double) * n);
   if (e == hipSuccess) e = hipMalloc(&ws->t, sizeof(double) * n);
@@ -352,8 +487,11 @@ static hipError_t ensure_workspace(sbm_ctx *c, int m, bool need32) {
   if (e == hipSuccess) e = hipMalloc(&ws->h, sizeof(double) * 3 * (m + 2));
   if (e == hipSuccess) e = hipMalloc(&ws->y, sizeof(double) * (m + 2));
   if (e == hipSuccess) e = hipMalloc(&ws->gm, sizeof(double) * ((size_t)(m + 1) * m + 4 * m + 2));
+  if (e == hipSuccess) e = hipMalloc(&ws->ticket, sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemset(ws->ticket, 0, sizeof(unsigned));
   if (e == hipSuccess && need32) {
-    e = hipMalloc(&ws->V32, sizeof(float) * n * (m + 1));
+    e = hipMalloc(&ws->V32, sizeof(float) * npad * (m + 1));
+    if (e == hipSuccess) e = hipMalloc(&ws->vc32, sizeof(float) * n);
     if (e == hipSuccess) e = hipMalloc(&ws->w32, sizeof(float) * n);
     if (e == hipSuccess) e = hipMalloc(&ws->c32, sizeof(float) * n);
     if (e == hipSuccess) e = hipMalloc(&ws->z32, sizeof(float) * n);
@@ -379,67 +517,79 @@ static hipError_t multidot(const T *V, int64_t ld, int ncol, const T *w, int64_t
   return hipGetLastError();
 }
 
+template <typename T, int CPW, int MODE>
+static int gs_grid_cap() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess)
+    return kMaxBlocks;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gs_kernel<T, CPW, MODE>, kThreads, 0) != hipSuccess)
+    return kMaxBlocks;
+  return std::max(1, std::min(kMaxBlocks, per_cu * cus));
+}
+
+template <typename T>
+static void gs_grid_caps(int (*g)[3]) {
+  g[0][0] = gs_grid_cap<T, 2, 0>(), g[0][1] = gs_grid_cap<T, 2, 1>(), g[0][2] = gs_grid_cap<T, 2, 2>();
+  g[1][0] = gs_grid_cap<T, 4, 0>(), g[1][1] = gs_grid_cap<T, 4, 1>(), g[1][2] = gs_grid_cap<T, 4, 2>();
+  g[2][0] = gs_grid_cap<T, 8, 0>(), g[2][1] = gs_grid_cap<T, 8, 1>(), g[2][2] = gs_grid_cap<T, 8, 2>();
+  g[3][0] = gs_grid_cap<T, 16, 0>(), g[3][1] = gs_grid_cap<T, 16, 1>(), g[3][2] = gs_grid_cap<T, 16, 2>();
+}
+
+template <typename T, int CPW, int MODE>
+static void gs_launch1(const Workspace *ws, const T *V, int m1, int ncol, const double *coef, T *w, int64_t n,
+                       double *partial, unsigned *ticket, double *out, const ArnoldiArgs &aa, hipStream_t s) {
+  constexpr int L = CPW == 2 ? 0 : (CPW == 4 ? 1 : (CPW == 8 ? 2 : 3));
+  const int64_t rows = 64 * (32 / CPW);  // rows per block and step
+  const int cap = ws->gs_grid[sizeof(T) == 4 ? 1 : 0][L][MODE];
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((n + rows - 1) / rows, cap));
+  hipLaunchKernelGGL((gs_kernel<T, CPW, MODE>), dim3(nb), dim3(kThreads), 0, s, V, m1, ncol, coef, w, n, partial,
+                     ticket, out, aa);
+}
+
+template <typename T, int MODE>
+static void gs_launch(const Workspace *ws, const T *V, int m1, int ncol, const double *coef, T *w, int64_t n,
+                      double *partial, unsigned *ticket, double *out, const ArnoldiArgs &aa, hipStream_t s) {
+  if (ncol <= 8)
+    gs_launch1<T, 2, MODE>(ws, V, m1, ncol, coef, w, n, partial, ticket, out, aa, s);
+  else if (ncol <= 16)
+    gs_launch1<T, 4, MODE>(ws, V, m1, ncol, coef, w, n, partial, ticket, out, aa, s);
+  else if (ncol <= 32)
+    gs_launch1<T, 8, MODE>(ws, V, m1, ncol, coef, w, n, partial, ticket, out, aa, s);
+  else
+    gs_launch1<T, 16, MODE>(ws, V, m1, ncol, coef, w, n, partial, ticket, out, aa, s);
+}
+
 // Arnoldi steps j <= k < j1 of restarted GMRES(m) on the basis V (column k + 1 is formed from
 // column k): w = A M^-1 v_k, two classical Gram-Schmidt passes (CGS2), the norm, the device
-// rotation update (arnoldi_step_kernel) and v_(k+1) = w / h_(k+1,k).  Launches only (no host
-// synchronisation, no memory set), so the sequence can be captured.
+// rotation update (arnoldi_step) and v_(k+1) = w / h_(k+1,k).  Launches only (no host
+// synchronisation).
 template <typename T>
-static sbm_status arnoldi_steps(sbm_ctx *c, int prec, T *V, T *w, T *z, const T *dinv, int m, int j, int j1,
-                                hipStream_t s) {
+static sbm_status arnoldi_steps(sbm_ctx *c, int prec, T *V, T *vc, T *w, T *z, const T *dinv, int m, int j,
+                                int j1, hipStream_t s) {
   Workspace *ws = c->ws;
   const int64_t n = c->n_dofs;
   const int nb = nblocks(n);
+  const int m1 = ws->m + 1;
   double *h1 = ws->h, *h2 = ws->h + (m + 2), *hn = ws->h + 2 * (m + 2);
   double *H = ws->gm, *cs = H + (size_t)(m + 1) * m, *sn = cs + m, *g = sn + m, *dres = g + (m + 1);
   double *fac = dres + m;
   for (int k = j; k < j1; ++k) {
-    T *vk = V + (int64_t)k * n, *vn = V + (int64_t)(k + 1) * n;
-    const T *src = vk;
+    // vc holds v_k contiguously
+    const T *src = vc;
     if (dinv) {
-      hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, dinv, vk, z, n);
+      hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, dinv, vc, z, n);
       src = z;
     }
     SBM_HIP_CHECK(launch_apply(c, src, w, prec, SBM_PART_ALL, s));
-    SBM_HIP_CHECK(multidot<T>(V, n, k + 1, w, n, ws->partial, h1, s));
-    hipLaunchKernelGGL(multiaxpy_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, n, k + 1, h1, w, n);
-    SBM_HIP_CHECK(multidot<T>(V, n, k + 1, w, n, ws->partial, h2, s));
-    hipLaunchKernelGGL(multiaxpy_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, n, k + 1, h2, w, n);
-    SBM_HIP_CHECK(multidot<T>(w, n, 1, w, n, ws->partial, hn, s));
-    hipLaunchKernelGGL(arnoldi_step_kernel, dim3(1), dim3(64), 0, s, k, m, h1, h2, hn, H, cs, sn, g, dres, fac);
-    hipLaunchKernelGGL(scale_by_kernel<T>, dim3(nb), dim3(kThreads), 0, s, w, fac, vn, n);
+    // CGS2: h1 = V^T w; w -= V h1, h2 = V^T w; w -= V h2, |w|^2 and the rotation update
+    const ArnoldiArgs aa{k, m, h1, h2, H, cs, sn, g, dres, fac};
+    gs_launch<T, 0>(ws, V, m1, k + 1, nullptr, w, n, ws->partial, ws->ticket, h1, aa, s);
+    gs_launch<T, 1>(ws, V, m1, k + 1, h1, w, n, ws->partial, ws->ticket, h2, aa, s);
+    gs_launch<T, 2>(ws, V, m1, k + 1, h2, w, n, ws->partial, ws->ticket, hn, aa, s);
+    hipLaunchKernelGGL(basis_store_kernel<T>, dim3(nb), dim3(kThreads), 0, s, w, fac, 0, V, k + 1, m1, vc, n);
   }
   SBM_HIP_CHECK(hipGetLastError());
-  return SBM_OK;
-}
-
-// The executable graph of arnoldi_steps(j, j1) for this workspace, captured on first use (on
-// a private stream, so the caller's stream may be the null stream) and kept with it.
-template <typename T>
-static sbm_status arnoldi_graph(sbm_ctx *c, int prec, T *V, T *w, T *z, const T *dinv, int m, int j, int j1,
-                                hipGraphExec_t *out) {
-  Workspace *ws = c->ws;
-  const auto key = std::make_tuple(prec, dinv ? 1 : 0, m, j, j1);
-  const auto it = ws->chunks.find(key);
-  if (it != ws->chunks.end()) {
-    *out = it->second;
-    return SBM_OK;
-  }
-  if (!ws->cap) SBM_HIP_CHECK(hipStreamCreateWithFlags(&ws->cap, hipStreamNonBlocking));
-  SBM_HIP_CHECK(hipStreamBeginCapture(ws->cap, hipStreamCaptureModeThreadLocal));
-  const sbm_status st = arnoldi_steps<T>(c, prec, V, w, z, dinv, m, j, j1, ws->cap);
-  hipGraph_t graph = nullptr;
-  const hipError_t e = hipStreamEndCapture(ws->cap, &graph);
-  if (st != SBM_OK || e != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    if (st != SBM_OK) return st;
-    SBM_HIP_CHECK(e);
-  }
-  hipGraphExec_t ex = nullptr;
-  const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  SBM_HIP_CHECK(ei);
-  ws->chunks[key] = ex;
-  *out = ex;
   return SBM_OK;
 }
 
@@ -453,8 +603,9 @@ static sbm_status arnoldi_graph(sbm_ctx *c, int prec, T *V, T *w, T *z, const T 
 // one that met the tolerance are discarded: only the leading columns enter the update, so the
 // result and the iteration count are those of a check after every step).
 template <typename T>
-static sbm_status gmres_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *V, T *w, T *z, const T *dinv, int m,
-                            double tol_abs, int max_it, hipStream_t s, int *its, int *applies, double *res) {
+static sbm_status gmres_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *V, T *vc, T *w, T *z, const T *dinv,
+                            int m, double tol_abs, int max_it, hipStream_t s, int *its, int *applies,
+                            double *res) {
   Workspace *ws = c->ws;
   const int64_t n = c->n_dofs;
   const int nb = nblocks(n);
@@ -462,34 +613,29 @@ static sbm_status gmres_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *V, T *w
   double *hn = ws->h + 2 * (m + 2);
   double *H = ws->gm, *g = H + (size_t)(m + 1) * m + 2 * m, *dres = g + (m + 1);
   std::vector<double> rh(m);
+  int(*grid)[3] = ws->gs_grid[sizeof(T) == 4 ? 1 : 0];
+  if (grid[0][0] == 0) gs_grid_caps<T>(grid);
   *its = 0;
   double beta = 0.0;
   while (true) {
     // r = rhs - A x  -> V_0
     SBM_HIP_CHECK(launch_apply(c, x, w, prec, SBM_PART_ALL, s));
     ++*applies;
-    hipLaunchKernelGGL(residual_kernel<T>, dim3(nb), dim3(kThreads), 0, s, rhs, w, V, n);
-    SBM_HIP_CHECK(multidot<T>(V, n, 1, V, n, ws->partial, hn, s));
+    hipLaunchKernelGGL(residual_kernel<T>, dim3(nb), dim3(kThreads), 0, s, rhs, w, vc, n);
+    SBM_HIP_CHECK(multidot<T>(vc, n, 1, vc, n, ws->partial, hn, s));
     SBM_HIP_CHECK(hipMemcpyAsync(&beta, hn, sizeof(double), hipMemcpyDeviceToHost, s));
     SBM_HIP_CHECK(hipStreamSynchronize(s));
     beta = std::sqrt(beta);
     *res = beta;
     if (!(beta > tol_abs) || *its >= max_it) return std::isfinite(beta) ? SBM_OK : SBM_ENOCONV;
-    hipLaunchKernelGGL(scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, hn, V, n);
+    hipLaunchKernelGGL(basis_store_kernel<T>, dim3(nb), dim3(kThreads), 0, s, vc, hn, 1, V, 0, ws->m + 1, vc, n);
     hipLaunchKernelGGL(gmres_init_kernel, dim3(1), dim3(64), 0, s, hn, g, m);
     int j = 0;
     bool stop = false;
     while (j < m && *its < max_it && !stop) {
       const int j1 = std::min({m, j + check, j + (max_it - *its)});
-      if (j1 - j == check) {
-        hipGraphExec_t ex = nullptr;
-        const sbm_status st = arnoldi_graph<T>(c, prec, V, w, z, dinv, m, j, j1, &ex);
-        if (st != SBM_OK) return st;
-        SBM_HIP_CHECK(hipGraphLaunch(ex, s));
-      } else {
-        const sbm_status st = arnoldi_steps<T>(c, prec, V, w, z, dinv, m, j, j1, s);
-        if (st != SBM_OK) return st;
-      }
+      const sbm_status st = arnoldi_steps<T>(c, prec, V, vc, w, z, dinv, m, j, j1, s);
+      if (st != SBM_OK) return st;
       *applies += j1 - j;
       SBM_HIP_CHECK(hipMemcpyAsync(rh.data(), dres + j, sizeof(double) * (j1 - j), hipMemcpyDeviceToHost, s));
       SBM_HIP_CHECK(hipStreamSynchronize(s));
@@ -507,7 +653,7 @@ static sbm_status gmres_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *V, T *w
     // back substitution and update x += M^-1 V y, from the leading j columns
     if (j > 0) {
       hipLaunchKernelGGL(backsub_kernel, dim3(1), dim3(64), 0, s, j, m, H, g, ws->y);
-      hipLaunchKernelGGL(update_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, n, j, ws->y, dinv, x, n);
+      hipLaunchKernelGGL(update_kernel<T>, dim3(nb), dim3(kThreads), 0, s, V, ws->m + 1, j, ws->y, dinv, x, n);
     }
   }
 }
@@ -720,8 +866,8 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
   double res = 0.0;
   if (mode == SBM_SOLVE_GMRES_F64) {
     int its = 0, applies = 0;
-    st = gmres_run<double>(h, SBM_F64, b, x, ws->V, ws->w, ws->z, dinv, m, tol_abs, max_it, s, &its, &applies,
-                           &res);
+    st = gmres_run<double>(h, SBM_F64, b, x, ws->V, ws->vc, ws->w, ws->z, dinv, m, tol_abs, max_it, s, &its,
+                           &applies, &res);
     info->inner_its = its;
     info->outer_its = (its + m - 1) / m;
     info->applies_f64 = applies;
@@ -746,7 +892,7 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
       int its = 0, applies = 0;
       double inner_res = 0.0;
       // inner solve of A32 c = r / |r| to 1e-4 (unit right-hand side), at most 4 restart cycles
-      (void)gmres_run<float>(h, SBM_F32, ws->r32, ws->c32, ws->V32, ws->w32, ws->z32, dinv32, m, 1e-4,
+      (void)gmres_run<float>(h, SBM_F32, ws->r32, ws->c32, ws->V32, ws->vc32, ws->w32, ws->z32, dinv32, m, 1e-4,
                              std::min(4 * m, max_it - total_its), s, &its, &applies, &inner_res);
       total_its += its;
       info->applies_f32 += applies;
