@@ -213,22 +213,29 @@ def solve_section(torch, sbm, inputs):
 
 def serve_section(n_req, max_it, rate, slots, budget_gb):
     """Request stream (p in 2..6, 16^3..64^3 cells, ellipsoid or 8-ball union, CG or SIPG,
-    FP32 GMRES inside FP64 refinement to 1e-10 with an iteration cap), Poisson arrivals."""
+    FP32 GMRES inside FP64 refinement to 1e-10 with an iteration cap).  First closed loop (all
+    requests queued at t = 0) for the capacity mu in solves/s, then open loop with Poisson
+    arrivals at 0.7 mu (rate > 0 overrides the open-loop rate)."""
     from paper_2507_17053_amd import inputs
     from paper_2507_17053_amd.serving import Server
 
-    reqs = inputs.serving_requests(n_req, seed=2, rate=rate)
-    srv = Server(budget_bytes=int(budget_gb * (1 << 30)), slots=slots, mode="gmres_ir", rel_tol=1e-10,
-                 max_it=max_it, restart=32)
-    s = srv.run(reqs, time_scale=1.0)
-    res = list(s["results"].values())
-    return {"requests": s["requests"], "served": s["served"], "converged_to_1e-10": s["converged"],
-            "errors": s["errors"], "solves_per_s": s["solves_per_s"], "latency_p50_s": s["latency_p50_s"],
-            "latency_p99_s": s["latency_p99_s"], "arrival_rate_per_s": rate, "slots": slots,
-            "hbm_budget_GB": budget_gb, "krylov_cap": max_it,
-            "median_rel_residual": float(sorted(r["info"].get("rel_residual", float("nan")) for r in res)[len(res) // 2])
-            if res else None,
-            "total_dofs": int(sum(r["info"].get("n_dofs", 0) for r in res))}
+    def one(reqs, time_scale):
+        srv = Server(budget_bytes=int(budget_gb * (1 << 30)), slots=slots, mode="gmres_ir", rel_tol=1e-10,
+                     max_it=max_it, restart=32)
+        s = srv.run(reqs, time_scale=time_scale)
+        res = list(s["results"].values())
+        rr = sorted(r["info"].get("rel_residual", float("nan")) for r in res)
+        return {"requests": s["requests"], "served": s["served"], "converged_to_1e-10": s["converged"],
+                "errors": s["errors"], "solves_per_s": s["solves_per_s"], "latency_p50_s": s["latency_p50_s"],
+                "latency_p99_s": s["latency_p99_s"], "median_rel_residual": rr[len(rr) // 2] if rr else None,
+                "total_dofs": int(sum(r["info"].get("n_dofs", 0) for r in res))}
+
+    closed = one(inputs.serving_requests(n_req, seed=2, rate=1.0), 0.0)
+    mu = closed["solves_per_s"]
+    lam = rate if rate > 0 else 0.7 * mu
+    opened = one(inputs.serving_requests(n_req, seed=2, rate=lam), 1.0)
+    return {"closed_loop": closed, "open_loop": dict(opened, arrival_rate_per_s=lam), "slots": slots,
+            "hbm_budget_GB": budget_gb, "krylov_cap": max_it}
 
 
 def profile_run(torch, sbm, inputs, n=5):
@@ -258,7 +265,8 @@ def main():
     ap.add_argument("--profile-run", action="store_true", help="few eager applies + copies (counter runs)")
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-max-it", type=int, default=100)
-    ap.add_argument("--serve-rate", type=float, default=8.0)
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="open-loop arrival rate (default: 0.7 of the closed-loop capacity)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
