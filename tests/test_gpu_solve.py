@@ -119,3 +119,70 @@ def test_not_converged_is_reported():
     info = op.solve(b, x, rel_tol=1e-10, max_it=1, mode="gmres")
     assert info["status"] == sbm.SBM_ENOCONV
     assert 0 < info["rel_residual"] < 1.0
+
+
+def _gmres_reference(A, b, m, rel_tol, max_it):
+    """Restarted GMRES(m) with two classical Gram-Schmidt passes and Givens rotations, a
+    convergence check after every step and the true residual at every restart (numpy, FP64):
+    the iteration semantics sbm_solve follows."""
+    n = len(b)
+    x = np.zeros(n)
+    tol = rel_tol * np.linalg.norm(b)
+    its = 0
+    while True:
+        r = b - A @ x
+        beta = np.linalg.norm(r)
+        if not beta > tol or its >= max_it:
+            return x, its, beta
+        V = np.zeros((m + 1, n))
+        V[0] = r / beta
+        H = np.zeros((m + 1, m))
+        cs, sn, g = np.zeros(m), np.zeros(m), np.zeros(m + 1)
+        g[0] = beta
+        j = 0
+        while j < m and its < max_it:
+            w = A @ V[j]
+            h = np.zeros(j + 2)
+            for _ in range(2):
+                c = V[: j + 1] @ w
+                w = w - V[: j + 1].T @ c
+                h[: j + 1] += c
+            h[j + 1] = np.linalg.norm(w)
+            if h[j + 1] > 0:
+                V[j + 1] = w / h[j + 1]
+            for i in range(j):
+                a, bb = h[i], h[i + 1]
+                h[i], h[i + 1] = cs[i] * a + sn[i] * bb, -sn[i] * a + cs[i] * bb
+            rr = np.hypot(h[j], h[j + 1])
+            cs[j], sn[j] = (h[j] / rr, h[j + 1] / rr) if rr > 0 else (1.0, 0.0)
+            h[j] = rr
+            H[: j + 1, j] = h[: j + 1]
+            g[j + 1], g[j] = -sn[j] * g[j], cs[j] * g[j]
+            its += 1
+            j += 1
+            if abs(g[j]) <= tol or not rr > 0:
+                break
+        y = np.zeros(j)
+        for i in range(j - 1, -1, -1):
+            y[i] = (g[i] - H[i, i + 1: j] @ y[i + 1: j]) / H[i, i] if H[i, i] != 0 else 0.0
+        x = x + V[:j].T @ y
+
+
+@pytest.mark.parametrize("m,max_it", [(10, 8000), (24, 8000), (10, 37)], ids=["m10", "m24", "m10-cut37"])
+def test_gmres_iterations_match_a_per_step_reference(m, max_it):
+    """The device GMRES reads its residual estimates back every few steps; its iteration count
+    and final residual must be those of GMRES checking after every step (restart boundaries
+    and a max_it that is not a multiple of the read-back interval included)."""
+    ref, op = _problem(2, 16, DISK, 1, "cg")
+    b, bref = _rhs(ref, op)
+    A = O.assemble(ref).tocsr()
+    _, its_ref, beta_ref = _gmres_reference(A, b.cpu().numpy(), m, 1e-10, max_it)
+    x = torch.zeros_like(b)
+    info = op.solve(b, x, rel_tol=1e-10, max_it=max_it, mode="gmres", restart=m)
+    assert abs(info["inner_its"] - its_ref) <= 1, (info, its_ref)
+    if max_it < 100:
+        assert info["inner_its"] == max_it and info["status"] == sbm.SBM_ENOCONV, info
+        rel_ref = beta_ref / np.linalg.norm(b.cpu().numpy())
+        assert abs(info["rel_residual"] - rel_ref) <= 1e-6 * rel_ref, (info["rel_residual"], rel_ref)
+    else:
+        assert info["status"] == sbm.SBM_OK, info
