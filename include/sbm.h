@@ -156,9 +156,10 @@ sbm_status sbm_layout_stats(sbm_handle h, int64_t *n_bricks, int64_t *n_boundary
 sbm_status sbm_apply_parts(sbm_handle h, const void *u, void *v, int prec, int parts, void *stream);
 
 /*
- * sbm_apply_batch -- n independent applies v_i = A_i u_i, launched together on one
- * stream (one launch per kernel kind and degree for all operators of the batch).
- * Same argument rules as sbm_apply for every i.  Asynchronous.
+ * sbm_apply_batch -- n independent applies v_i = A_i u_i, enqueued in order on one stream
+ * (the kernels of each operator as sbm_apply launches them).  Same argument rules as
+ * sbm_apply for every i; stops at the first failing entry and returns its status.
+ * Asynchronous.
  */
 sbm_status sbm_apply_batch(int n, const sbm_handle *hs, const void *const *u, void *const *v,
                            int prec, void *stream);
@@ -208,10 +209,12 @@ typedef struct {
 /*
  * sbm_solve -- solve A x = b to ||b - A x|| <= rel_tol ||b|| from the initial guess in x.
  * b, x: device FP64 vectors of n_dofs entries (x is read as the initial guess and
- * overwritten).  restart: Krylov dimension m of GMRES (<= 0 selects 50).  max_it bounds
- * the total Krylov iterations.  jacobi != 0 right-preconditions with the inverse of the
- * operator's diagonal.  Synchronous (returns after the work on stream has finished).
- * Errors: EINVAL, ENOCONV (info->rel_residual holds what was reached), EHIP.
+ * overwritten).  restart: Krylov dimension m of GMRES (<= 0 selects 50, at most 64).
+ * max_it bounds the total Krylov iterations.  jacobi != 0 right-preconditions with the
+ * inverse of the operator's diagonal.  The Krylov workspace (GMRES: m + 1 basis vectors per
+ * precision used) is allocated on the first solve and kept with the handle; solves on one
+ * handle must not overlap.  Synchronous (returns after the work on stream has finished).
+ * Errors: EINVAL, ENOMEM, ENOCONV (info->rel_residual holds what was reached), EHIP.
  */
 sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, int max_it,
                      int mode, int restart, int jacobi, void *stream, sbm_solve_info *info);
