@@ -269,7 +269,7 @@ def main():
                     help="open-loop arrival rate (default: 0.7 of the closed-loop capacity)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU: the library has no multi-GPU path; use --gpus 1"}))
         sys.exit(2)
 
     import torch
