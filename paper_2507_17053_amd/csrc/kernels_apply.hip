@@ -45,6 +45,26 @@ constexpr int epb() {
   return e;
 }
 
+// Entities per workgroup when there are few entities: one wavefront (at least one entity),
+// so that small operators still spread over every CU.
+template <typename T, int D, int N1, int NBUF>
+constexpr int epb_one_wave() {
+  constexpr int NP = Shape<D, N1>::NP, E = 64 / NP, F = epb<T, D, N1, NBUF, 0>();
+  return E < 1 ? 1 : (E > F ? F : E);
+}
+
+// Workgroups that fill the device twice (two per compute unit).
+inline int two_per_cu() {
+  static const int n = [] {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                hipSuccess)
+      return 512;
+    return 2 * cus;
+  }();
+  return n;
+}
+
 // Brick of background cells per CG workgroup, chosen per degree so that the LDS lattice
 // ((BX p + 1)(BY p + 1)(BZ p + 1) values) stays near 20 KB in FP64.
 template <int D, int P>
@@ -1075,15 +1095,25 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
       }
     }
   } else {
+    // entities per workgroup: as many as fit, unless that leaves fewer than two workgroups
+    // per compute unit; then one wavefront's worth
     if (nc > 0 && (parts & SBM_PART_CELLS)) {
-      constexpr int E = epb<T, D, N1, 4, 0>();
-      hipLaunchKernelGGL((dg_cell_kernel<T, D, N1, E>), dim3((nc + E - 1) / E), dim3(E * NP), 0, s, nc,
-                         c->d_nbr, u, v, tab, sc, scale);
+      constexpr int E = epb<T, D, N1, 4, 0>(), E1 = epb_one_wave<T, D, N1, 4>();
+      if ((nc + E - 1) / E >= two_per_cu())
+        hipLaunchKernelGGL((dg_cell_kernel<T, D, N1, E>), dim3((nc + E - 1) / E), dim3(E * NP), 0, s, nc,
+                           c->d_nbr, u, v, tab, sc, scale);
+      else
+        hipLaunchKernelGGL((dg_cell_kernel<T, D, N1, E1>), dim3((nc + E1 - 1) / E1), dim3(E1 * NP), 0, s, nc,
+                           c->d_nbr, u, v, tab, sc, scale);
     }
     if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
-      constexpr int E = epb<T, D, N1, 2, 0>();
-      hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s, nf,
-                         c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
+      constexpr int E = epb<T, D, N1, 2, 0>(), E1 = epb_one_wave<T, D, N1, 2>();
+      if ((nf + E - 1) / E >= two_per_cu())
+        hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s, nf,
+                           c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
+      else
+        hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E1>), dim3((nf + E1 - 1) / E1), dim3(E1 * NP), 0, s, nf,
+                           c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
     }
   }
   return hipGetLastError();

@@ -71,7 +71,8 @@ def test_apply_matches_assembled_oracle(d, n, ls, p, disc, dtype):
     ("dg", "torus3d_dg", {"p": 5}),
     ("cg", "spheres3d_q6", {}),
     ("cg", "sphere3d_q4", {"n": 128}),
-], ids=["sphere64-q4-cg", "torus32-q3-dg", "torus32-q5-dg", "spheres48-q6-cg", "sphere128-q4-cg"])
+    ("dg", "torus3d_dg", {"p": 3, "n": 80}),
+], ids=["sphere64-q4-cg", "torus32-q3-dg", "torus32-q5-dg", "spheres48-q6-cg", "sphere128-q4-cg", "torus80-q3-dg"])
 def test_apply_full_size_matches_c_oracle(disc, wname, over, dtype):
     """Full workload sizes, every output entry compared with the brute-force C oracle."""
     native.build(force=False)
