@@ -69,13 +69,15 @@ inline int two_per_cu() {
 // ((BX p + 1)(BY p + 1)(BZ p + 1) values) stays near 20 KB in FP64.
 template <int D, int P>
 struct BrickDims {
-  // 3D: p=1 8x8x8, p=2 8x4x4, p=3 4x4x4, p=4,5 4x2x2, p=6,7 2x2x2, p=8 2x2x1 (at p=4, 4x2x2
-  // measured faster than 4x4x2, whose LDS allowed 3 workgroups per CU, and than 2x2x2)
+  // 3D: p=1 8x8x8, p=2 8x4x4, p=3 4x4x4, p=4,5 4x2x2, p=6 2x2x1, p=7 2x2x2, p=8 2x2x1 (at
+  // p=4, 4x2x2 measured faster than 4x4x2, whose LDS allowed 3 workgroups per CU, and than
+  // 2x2x2; at p=6, 2x2x1 faster than 2x2x2 on a 48^3 mesh, which has too few 2x2x2 bricks to
+  // fill the device)
   // 2D: 8x8 up to p=2, 4x4 up to p=7, 3x3 for p=8 (a lattice row must fit 32 points)
   static constexpr int BX = (D == 2) ? (P <= 2 ? 8 : (P <= 7 ? 4 : 3))
                                      : (P <= 2 ? 8 : (P <= 5 ? 4 : 2));
   static constexpr int BY = (D == 2) ? BX : (P == 1 ? 8 : (P <= 3 ? 4 : 2));
-  static constexpr int BZ = (D == 2) ? 1 : (P == 1 ? 8 : (P <= 3 ? 4 : (P <= 7 ? 2 : 1)));
+  static constexpr int BZ = (D == 2) ? 1 : (P == 1 ? 8 : (P <= 3 ? 4 : (P <= 5 || P == 7 ? 2 : 1)));
 };
 
 // XCD-aware block order: the dispatcher hands block b to XCD (b mod 8), so give every XCD
