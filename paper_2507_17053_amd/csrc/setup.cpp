@@ -7,6 +7,7 @@
 #include <cstring>
 #include <limits>
 #include <new>
+#include <thread>
 
 #include "sbm_internal.h"
 
@@ -822,35 +823,55 @@ static sbm_status host_setup(sbm_ctx *c, const sbm_mesh *mesh, const sbm_levelse
   c->n_int = n_int;
 
   // ---- face points: xi~ (face Gauss points), closest points, shifted xi ----
+  // (the projections are independent per face: faces are split over host threads, every
+  // face's results go to its own slots, so the outcome does not depend on the split)
   const int64_t nf = c->n_sbm;
   c->face_xi.assign(nf * np * d, 0.0);
   c->face_xtrue.assign(nf * np * d, 0.0);
-  for (int64_t f = 0; f < nf; ++f) {
-    const int32_t r = c->faces[3 * f], a = c->faces[3 * f + 1], s = c->faces[3 * f + 2];
-    const int32_t *cc = &c->cells[(int64_t)r * d];
-    for (int q = 0; q < np; ++q) {
-      double xt[3], xs[3], xx[3], cp[3];
-      int qq = q;
-      for (int k = 0; k < d; ++k) {
-        if (k == a) {
-          xt[k] = (double)s;
-        } else {
-          xt[k] = R.g[qq % n1];
-          qq /= n1;
+  auto project = [&](int64_t f0, int64_t f1) -> bool {
+    bool ok = true;
+    for (int64_t f = f0; f < f1; ++f) {
+      const int32_t r = c->faces[3 * f], a = c->faces[3 * f + 1], s = c->faces[3 * f + 2];
+      const int32_t *cc = &c->cells[(int64_t)r * d];
+      for (int q = 0; q < np; ++q) {
+        double xt[3], xs[3], xx[3], cp[3];
+        int qq = q;
+        for (int k = 0; k < d; ++k) {
+          if (k == a) {
+            xt[k] = (double)s;
+          } else {
+            xt[k] = R.g[qq % n1];
+            qq /= n1;
+          }
+          xx[k] = c->lo[k] + c->h * ((double)cc[k] + xt[k]);
         }
-        xx[k] = c->lo[k] + c->h * ((double)cc[k] + xt[k]);
-      }
-      L.closest(xx, cp);
-      for (int k = 0; k < d; ++k) {
-        xs[k] = xt[k] + c->shift_scale * (cp[k] - xx[k]) / c->h;
-        c->face_xi[(f * np + q) * d + k] = xs[k];
-        c->face_xtrue[(f * np + q) * d + k] = cp[k];
-        if (!std::isfinite(xs[k])) {
-          set_error("sbm_setup: closest-point projection failed (degenerate level set?)");
-          return SBM_EINVAL;
+        L.closest(xx, cp);
+        for (int k = 0; k < d; ++k) {
+          xs[k] = xt[k] + c->shift_scale * (cp[k] - xx[k]) / c->h;
+          c->face_xi[(f * np + q) * d + k] = xs[k];
+          c->face_xtrue[(f * np + q) * d + k] = cp[k];
+          ok = ok && std::isfinite(xs[k]);
         }
       }
     }
+    return ok;
+  };
+  const int64_t nthr = std::max<int64_t>(
+      1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 16, (nf * np) / 4096}));
+  bool proj_ok = true;
+  if (nthr <= 1) {
+    proj_ok = project(0, nf);
+  } else {
+    std::vector<std::thread> pool;
+    std::vector<char> oks((size_t)nthr, 1);
+    for (int64_t t = 0; t < nthr; ++t)
+      pool.emplace_back([&, t] { oks[t] = project(nf * t / nthr, nf * (t + 1) / nthr) ? 1 : 0; });
+    for (auto &th : pool) th.join();
+    for (char o : oks) proj_ok = proj_ok && o;
+  }
+  if (!proj_ok) {
+    set_error("sbm_setup: closest-point projection failed (degenerate level set?)");
+    return SBM_EINVAL;
   }
 
   // ---- DoF numbering ----
