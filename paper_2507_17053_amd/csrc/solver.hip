@@ -14,6 +14,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <thread>
 #include <vector>
 
 #include "sbm_internal.h"
@@ -711,59 +713,98 @@ sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double 
   }
   const int d = h->dim, n1 = h->n1, nb = h->nb, np = h->nq_face, P = h->p;
   const Rules1D &R = h->rules;
-  std::vector<double> bh(h->n_dofs, 0.0);
-  // psi_i(g_q) on the reference cell and the cell weights W_q h^d
-  std::vector<double> psi((size_t)nb * nb), wq(nb);
-  for (int q = 0; q < nb; ++q) {
-    int qk[3] = {q % n1, (q / n1) % n1, q / (n1 * n1)};
-    double w = 1.0;
-    for (int m = 0; m < d; ++m) w *= R.w[qk[m]] * h->h;
-    wq[q] = w;
-    for (int i = 0; i < nb; ++i) {
-      int ik[3] = {i % n1, (i / n1) % n1, i / (n1 * n1)};
-      double v = 1.0;
-      for (int m = 0; m < d; ++m) v *= R.N[qk[m] * n1 + ik[m]];
-      psi[(size_t)q * nb + i] = v;
+  const int64_t nc = h->n_cells, nf = h->n_sbm;
+  // Every integral is a tensor-product quadrature, so the transposed interpolation to the
+  // basis is done axis by axis (N^T along each axis in turn).  Cells and faces are split over
+  // host threads; each entity's local vector has its own slot, and the slots are added into b
+  // in entity order afterwards (the result does not depend on the split).
+  //   cell r:  loc_i = sum_q psi_i(g_q) W_q h^d f(x_q)
+  //   face:    loc_i = c(i_a) T(i_t), T = sum_q psi_t(g_q) omega_q g(x_q) (tangential axes),
+  //            c(i_a) = sigma [i_a = s p] - sgn / h l'_{i_a}(s)   (sigma g v - g dv/dn~)
+  std::vector<double> cl((size_t)nc * nb), fl((size_t)nf * nb);
+  // out = contraction of in (tensor with n1 points per axis, `dims` axes, first fastest)
+  // with N^T along `axis`: out[.., i, ..] = sum_q N[q][i] in[.., q, ..]
+  auto contract = [&](const double *in, double *out, int dims, int axis) {
+    int st = 1;
+    for (int m = 0; m < axis; ++m) st *= n1;
+    int tot = 1;
+    for (int m = 0; m < dims; ++m) tot *= n1;
+    for (int idx = 0; idx < tot; ++idx) {
+      const int i = (idx / st) % n1, base = idx - i * st;
+      double acc = 0.0;
+      for (int q = 0; q < n1; ++q) acc += R.N[q * n1 + i] * in[base + q * st];
+      out[idx] = acc;
     }
-  }
+  };
+  auto cells = [&](int64_t r0, int64_t r1) {
+    std::vector<double> A(nb), B(nb);
+    for (int64_t r = r0; r < r1; ++r) {
+      for (int q = 0; q < nb; ++q) {
+        const int qk[3] = {q % n1, (q / n1) % n1, q / (n1 * n1)};
+        double w = 1.0;
+        for (int m = 0; m < d; ++m) w *= R.w[qk[m]] * h->h;
+        A[q] = f_qp[r * nb + q] * w;
+      }
+      double *src = A.data(), *dst = B.data();
+      for (int m = 0; m < d; ++m) {
+        contract(src, dst, d, m);
+        std::swap(src, dst);
+      }
+      std::copy(src, src + nb, cl.begin() + r * nb);
+    }
+  };
+  auto faces = [&](int64_t f0, int64_t f1) {
+    std::vector<double> A(np), B(np), cn(n1);
+    for (int64_t f = f0; f < f1; ++f) {
+      const int32_t a = h->faces[3 * f + 1], s = h->faces[3 * f + 2];
+      const double sgn = s ? 1.0 : -1.0;
+      const double *Ds = s ? R.D1.data() : R.D0.data();
+      for (int q = 0; q < np; ++q) {
+        const int qt[2] = {q % n1, q / n1};
+        double om = 1.0;
+        for (int t = 0; t < d - 1; ++t) om *= R.w[qt[t]] * h->h;
+        A[q] = om * g_bp[f * np + q];
+      }
+      double *src = A.data(), *dst = B.data();
+      for (int m = 0; m < d - 1; ++m) {
+        contract(src, dst, d - 1, m);
+        std::swap(src, dst);
+      }
+      for (int ia = 0; ia < n1; ++ia) cn[ia] = (ia == s * P ? h->sigma_gamma : 0.0) - sgn / h->h * Ds[ia];
+      for (int i = 0; i < nb; ++i) {
+        const int ik[3] = {i % n1, (i / n1) % n1, i / (n1 * n1)};
+        int jt = 0, sc = 1;
+        for (int m = 0; m < d; ++m)
+          if (m != a) {
+            jt += ik[m] * sc;
+            sc *= n1;
+          }
+        fl[(size_t)f * nb + i] = cn[ik[a]] * src[jt];
+      }
+    }
+  };
+  auto run = [](int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &fn) {
+    const int64_t nt = std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 16, n / grain}));
+    if (nt <= 1) {
+      fn(0, n);
+      return;
+    }
+    std::vector<std::thread> pool;
+    for (int64_t t = 0; t < nt; ++t) pool.emplace_back([&, t] { fn(n * t / nt, n * (t + 1) / nt); });
+    for (auto &th : pool) th.join();
+  };
+  run(nc, 1024, cells);
+  run(nf, 1024, faces);
   auto dof_of = [&](int64_t r, int i) -> int64_t {
     return (h->disc == SBM_CG) ? (int64_t)h->runs[r * np + i / n1] + i % n1 : r * nb + i;
   };
-  std::vector<double> loc(nb);
-  for (int64_t r = 0; r < h->n_cells; ++r) {
-    std::fill(loc.begin(), loc.end(), 0.0);
-    for (int q = 0; q < nb; ++q) {
-      const double fw = f_qp[r * nb + q] * wq[q];
-      for (int i = 0; i < nb; ++i) loc[i] += psi[(size_t)q * nb + i] * fw;
-    }
-    for (int i = 0; i < nb; ++i) bh[dof_of(r, i)] += loc[i];
-  }
-  // surrogate faces: int sigma g psi_i - int (dpsi_i/dn~) g, g at the true-boundary points
-  for (int64_t f = 0; f < h->n_sbm; ++f) {
-    const int32_t r = h->faces[3 * f], a = h->faces[3 * f + 1], s = h->faces[3 * f + 2];
-    const double sgn = s ? 1.0 : -1.0;
-    const double *Ds = s ? R.D1.data() : R.D0.data();
-    std::fill(loc.begin(), loc.end(), 0.0);
-    for (int q = 0; q < np; ++q) {
-      int qt[2] = {q % n1, q / n1};
-      double om = 1.0;
-      for (int t = 0; t < d - 1; ++t) om *= R.w[qt[t]] * h->h;
-      const double g = g_bp[f * np + q];
-      for (int i = 0; i < nb; ++i) {
-        int ik[3] = {i % n1, (i / n1) % n1, i / (n1 * n1)};
-        double tang = 1.0;
-        int t = 0;
-        for (int m = 0; m < d; ++m) {
-          if (m == a) continue;
-          tang *= R.N[qt[t] * n1 + ik[m]];
-          ++t;
-        }
-        const double val = (ik[a] == s * P) ? tang : 0.0;
-        const double dn = sgn / h->h * Ds[ik[a]] * tang;
-        loc[i] += om * (h->sigma_gamma * g * val - g * dn);
-      }
-    }
-    for (int i = 0; i < nb; ++i) bh[dof_of(r, i)] += loc[i];
+  std::vector<double> bh(h->n_dofs, 0.0);
+  for (int64_t r = 0; r < nc; ++r)
+    for (int i = 0; i < nb; ++i) bh[dof_of(r, i)] += cl[(size_t)r * nb + i];
+  for (int64_t f = 0; f < nf; ++f) {
+    const int32_t r = h->faces[3 * f];
+    for (int i = 0; i < nb; ++i) bh[dof_of(r, i)] += fl[(size_t)f * nb + i];
   }
   SBM_HIP_CHECK(hipMemcpyAsync(b, bh.data(), bh.size() * sizeof(double), hipMemcpyHostToDevice,
                                (hipStream_t)stream));

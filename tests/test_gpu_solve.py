@@ -46,7 +46,10 @@ def test_diagonal_matches_assembled(d, n, ls, p, disc, dtype):
     assert err <= (1e-12 if dtype == torch.float64 else 1e-6), err
 
 
-@pytest.mark.parametrize("d,n,ls,p,disc", [(2, 16, DISK, 2, "cg"), (3, 6, inputs.sphere((0, 0, 0), 0.75), 3, "dg")])
+@pytest.mark.parametrize("d,n,ls,p,disc", [
+    (2, 16, DISK, 2, "cg"), (3, 6, inputs.sphere((0, 0, 0), 0.75), 3, "dg"),
+    (3, 8, inputs.sphere((0, 0, 0), 0.75), 4, "cg"), (2, 10, inputs.ellipsoid((0, 0), (0.8, 0.6)), 5, "dg"),
+])
 def test_rhs_matches_oracle(d, n, ls, p, disc):
     ref, op = _problem(d, n, ls, p, disc)
     b, bref = _rhs(ref, op)
