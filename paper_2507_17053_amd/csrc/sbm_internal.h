@@ -117,7 +117,8 @@ struct sbm_ctx {
   int32_t *d_brick_face_off = nullptr, *d_brick_face_loc = nullptr;
   int32_t *d_row_base = nullptr;
   uint32_t *d_row_gmask = nullptr, *d_row_bmask = nullptr;
-  // device copies
+  // device copies (all inside one allocation, d_arena)
+  void *d_arena = nullptr;
   int32_t *d_runs = nullptr;       // CG
   int32_t *d_nbr = nullptr;        // DG
   int32_t *d_face_cell = nullptr;  // n_sbm

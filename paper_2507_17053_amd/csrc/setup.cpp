@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <functional>
 #include <new>
 #include <thread>
 
@@ -401,42 +402,58 @@ using namespace sbm;
 // ---------------------------------------------------------------------------------------
 // Setup
 // ---------------------------------------------------------------------------------------
-template <typename V>
-static hipError_t upload(V **dst, const std::vector<V> &src, size_t &bytes) {
-  *dst = nullptr;
-  if (src.empty()) return hipSuccess;
-  hipError_t e = hipMalloc((void **)dst, src.size() * sizeof(V));
-  if (e != hipSuccess) return e;
-  bytes += src.size() * sizeof(V);
-  return hipMemcpy(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice);
-}
-
-template <typename V>
-static void free_ptr(V *&p) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-}
+// All device arrays of a handle live in one allocation (the arena): one hipMalloc at setup
+// and one hipFree at destroy (hipFree synchronises the device, which would otherwise stall
+// every other stream once per array).  Each array starts on a 256-byte boundary.
+struct ArenaPlan {
+  struct Item {
+    std::function<void(char *)> set;
+    const void *src;  // host data to copy, or nullptr for scratch
+    size_t bytes;
+  };
+  std::vector<Item> items;
+  template <typename P, typename V>
+  void add(P *&ptr, const std::vector<V> &src) {
+    ptr = nullptr;
+    if (!src.empty())
+      items.push_back({[&ptr](char *a) { ptr = reinterpret_cast<P *>(a); }, src.data(), src.size() * sizeof(V)});
+  }
+  void scratch(void *&ptr, size_t bytes) {
+    ptr = nullptr;
+    if (bytes) items.push_back({[&ptr](char *a) { ptr = a; }, nullptr, bytes});
+  }
+  static size_t aligned(size_t b) { return (b + 255) / 256 * 256; }
+  hipError_t commit(void **arena, size_t *total) {
+    *total = 0;
+    for (const Item &it : items) *total += aligned(it.bytes);
+    *arena = nullptr;
+    if (*total == 0) return hipSuccess;
+    hipError_t e = hipMalloc(arena, *total);
+    if (e != hipSuccess) return e;
+    size_t off = 0;
+    for (const Item &it : items) {
+      char *p = static_cast<char *>(*arena) + off;
+      it.set(p);
+      if (it.src) {
+        e = hipMemcpy(p, it.src, it.bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+      }
+      off += aligned(it.bytes);
+    }
+    return hipSuccess;
+  }
+};
 
 static void free_device(sbm_ctx *c) {
-  free_ptr(c->d_runs);
-  free_ptr(c->d_nbr);
-  free_ptr(c->d_face_cell);
-  free_ptr(c->d_face_code);
-  free_ptr(c->d_face_xi);
-  free_ptr(c->d_brick_cell_off);
-  free_ptr(c->d_brick_runs);
-  free_ptr(c->d_face_runs);
-  free_ptr(c->d_brick_cell_loc);
-  free_ptr(c->d_brick_face_off);
-  free_ptr(c->d_brick_face_loc);
-  free_ptr(c->d_row_base);
-  free_ptr(c->d_row_gmask);
-  free_ptr(c->d_row_bmask);
-  free_ptr(c->d_row_hbase);
-  free_ptr(c->d_halo_dof);
-  free_ptr(c->d_halo_mask);
-  free_ptr(c->d_halo);
-  free_ptr(c->d_fbuf);
+  if (c->d_arena) (void)hipFree(c->d_arena);
+  c->d_arena = nullptr;
+  c->d_runs = c->d_nbr = c->d_face_cell = c->d_face_code = nullptr;
+  c->d_face_xi = nullptr;
+  c->d_brick_cell_off = c->d_brick_runs = c->d_face_runs = c->d_brick_cell_loc = nullptr;
+  c->d_brick_face_off = c->d_brick_face_loc = c->d_row_base = c->d_row_hbase = c->d_halo_dof = nullptr;
+  c->d_row_gmask = c->d_row_bmask = nullptr;
+  c->d_halo_mask = nullptr;
+  c->d_halo = c->d_fbuf = nullptr;
 }
 
 // CG bricks: group the active cells into blocks of BX x BY x BZ background cells (one
@@ -974,37 +991,31 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
     fcode[i] = 2 * c->faces[3 * f + 1] + c->faces[3 * f + 2];
     std::copy(c->face_xi.begin() + f * xq, c->face_xi.begin() + (f + 1) * xq, fxi.begin() + i * xq);
   }
-  hipError_t e = hipSuccess;
-  size_t bytes = 0;
+  ArenaPlan plan;
   if (c->disc == SBM_CG) {
-    e = upload(&c->d_runs, c->runs, bytes);
-    if (e == hipSuccess) e = upload(&c->d_brick_cell_off, c->brick_cell_off, bytes);
-    if (e == hipSuccess) e = upload(&c->d_brick_runs, c->brick_runs, bytes);
-    if (e == hipSuccess) e = upload(&c->d_face_runs, c->face_runs, bytes);
-    if (e == hipSuccess) e = upload(&c->d_brick_cell_loc, c->brick_cell_loc, bytes);
-    if (e == hipSuccess) e = upload(&c->d_brick_face_off, c->brick_face_off, bytes);
-    if (e == hipSuccess) e = upload(&c->d_brick_face_loc, c->brick_face_loc, bytes);
-    if (e == hipSuccess) e = upload(&c->d_row_base, c->row_base, bytes);
-    if (e == hipSuccess) e = upload(&c->d_row_gmask, c->row_gmask, bytes);
-    if (e == hipSuccess) e = upload(&c->d_row_bmask, c->row_bmask, bytes);
-    if (e == hipSuccess) e = upload(&c->d_row_hbase, c->row_hbase, bytes);
-    if (e == hipSuccess) e = upload(&c->d_halo_dof, c->halo_dof, bytes);
-    if (e == hipSuccess) e = upload(&c->d_halo_mask, c->halo_mask, bytes);
-    if (e == hipSuccess && c->n_halo_dofs > 0) {
-      const size_t hb = ((size_t)1 << c->dim) * (size_t)c->n_halo_dofs * sizeof(double);
-      e = hipMalloc(&c->d_halo, hb);
-      bytes += hb;
-    }
-    if (e == hipSuccess && c->n_sbm > 0) {
-      const size_t fb = (size_t)c->n_sbm * 2 * c->nq_face * sizeof(double);
-      e = hipMalloc(&c->d_fbuf, fb);
-      bytes += fb;
-    }
+    plan.add(c->d_runs, c->runs);
+    plan.add(c->d_brick_cell_off, c->brick_cell_off);
+    plan.add(c->d_brick_runs, c->brick_runs);
+    plan.add(c->d_face_runs, c->face_runs);
+    plan.add(c->d_brick_cell_loc, c->brick_cell_loc);
+    plan.add(c->d_brick_face_off, c->brick_face_off);
+    plan.add(c->d_brick_face_loc, c->brick_face_loc);
+    plan.add(c->d_row_base, c->row_base);
+    plan.add(c->d_row_gmask, c->row_gmask);
+    plan.add(c->d_row_bmask, c->row_bmask);
+    plan.add(c->d_row_hbase, c->row_hbase);
+    plan.add(c->d_halo_dof, c->halo_dof);
+    plan.add(c->d_halo_mask, c->halo_mask);
+    plan.scratch(c->d_halo, ((size_t)1 << c->dim) * (size_t)c->n_halo_dofs * sizeof(double));
+    plan.scratch(c->d_fbuf, (size_t)c->n_sbm * 2 * c->nq_face * sizeof(double));
+  } else {
+    plan.add(c->d_nbr, c->nbr);
   }
-  if (e == hipSuccess && c->disc == SBM_DG) e = upload(&c->d_nbr, c->nbr, bytes);
-  if (e == hipSuccess) e = upload(&c->d_face_cell, fcell, bytes);
-  if (e == hipSuccess) e = upload(&c->d_face_code, fcode, bytes);
-  if (e == hipSuccess) e = upload(&c->d_face_xi, fxi, bytes);
+  plan.add(c->d_face_cell, fcell);
+  plan.add(c->d_face_code, fcode);
+  plan.add(c->d_face_xi, fxi);
+  size_t bytes = 0;
+  const hipError_t e = plan.commit(&c->d_arena, &bytes);
   if (e != hipSuccess) {
     set_error(std::string("sbm_setup: device upload failed: ") + hipGetErrorString(e));
     free_device(c);

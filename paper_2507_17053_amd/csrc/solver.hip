@@ -16,6 +16,7 @@
 #include <cstring>
 #include <functional>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "sbm_internal.h"
@@ -452,6 +453,7 @@ struct Workspace {
   double *y = nullptr;        // m+2 coefficients for the update (slot m+1: scratch of the refinement)
   double *gm = nullptr;       // GMRES state: H ((m+1) x m), cs, sn (m), g (m+1), res (m), factor
   unsigned *ticket = nullptr; // block counter of the single-pass reductions (0 between launches)
+  void *arena = nullptr;      // the allocation holding all of the above
   bool have_diag = false;
   // grid of each Gram-Schmidt kernel: as many blocks as fit on the device at once (no partial
   // last round), index [FP32][log2(CPW) - 1][MODE]
@@ -461,9 +463,9 @@ struct Workspace {
 void free_workspace(sbm_ctx *c) {
   Workspace *ws = c->ws;
   if (!ws) return;
-  void *ptrs[] = {ws->V,   ws->vc,  ws->vc32, ws->w,   ws->r,    ws->t,       ws->z, ws->dinv, ws->V32, ws->w32,
-                  ws->c32, ws->z32, ws->r32, ws->dinv32, ws->partial, ws->h, ws->y, ws->gm, ws->ticket};
-  for (void *p : ptrs)
+  // one allocation for the vectors and scalars (hipFree synchronises the device); the Jacobi
+  // diagonals are allocated on their first use
+  for (void *p : {ws->arena, (void *)ws->dinv, (void *)ws->dinv32})
     if (p) (void)hipFree(p);
   delete ws;
   c->ws = nullptr;
@@ -479,27 +481,38 @@ static hipError_t ensure_workspace(sbm_ctx *c, int m, bool need32) {
   ws->m = m;
   const size_t n = (size_t)std::max<int64_t>(1, c->n_dofs);
   const size_t npad = (n + kTile - 1) / kTile * kTile;
-  hipError_t e = hipMalloc(&ws->V, sizeof(double) * npad * (m + 1));
-  if (e == hipSuccess) e = hipMalloc(&ws->vc, sizeof(double) * n);
-  if (e == hipSuccess) e = hipMalloc(&ws->w, sizeof(double) * n);
-  if (e == hipSuccess) e = hipMalloc(&ws->r, sizeof(double) * n);
-  if (e == hipSuccess) e = hipMalloc(&ws->t, sizeof(double) * n);
-  if (e == hipSuccess) e = hipMalloc(&ws->z, sizeof(double) * n);
-  if (e == hipSuccess) e = hipMalloc(&ws->partial, sizeof(double) * kMaxBlocks * (m + 2));
-  if (e == hipSuccess) e = hipMalloc(&ws->h, sizeof(double) * 3 * (m + 2));
-  if (e == hipSuccess) e = hipMalloc(&ws->y, sizeof(double) * (m + 2));
-  if (e == hipSuccess) e = hipMalloc(&ws->gm, sizeof(double) * ((size_t)(m + 1) * m + 4 * m + 2));
-  if (e == hipSuccess) e = hipMalloc(&ws->ticket, sizeof(unsigned));
-  if (e == hipSuccess) e = hipMemset(ws->ticket, 0, sizeof(unsigned));
-  if (e == hipSuccess && need32) {
-    e = hipMalloc(&ws->V32, sizeof(float) * npad * (m + 1));
-    if (e == hipSuccess) e = hipMalloc(&ws->vc32, sizeof(float) * n);
-    if (e == hipSuccess) e = hipMalloc(&ws->w32, sizeof(float) * n);
-    if (e == hipSuccess) e = hipMalloc(&ws->c32, sizeof(float) * n);
-    if (e == hipSuccess) e = hipMalloc(&ws->z32, sizeof(float) * n);
-    if (e == hipSuccess) e = hipMalloc(&ws->r32, sizeof(float) * n);
+  // carve the arena: every piece starts on a 256-byte boundary
+  size_t off = 0;
+  std::vector<std::function<void(char *)>> parts;
+  auto piece = [&](auto *&ptr, size_t bytes) {
+    using P = std::remove_reference_t<decltype(*ptr)>;
+    const size_t at = off;
+    parts.push_back([&ptr, at](char *base) { ptr = reinterpret_cast<P *>(base + at); });
+    off += (bytes + 255) / 256 * 256;
+  };
+  piece(ws->V, sizeof(double) * npad * (m + 1));
+  piece(ws->vc, sizeof(double) * n);
+  piece(ws->w, sizeof(double) * n);
+  piece(ws->r, sizeof(double) * n);
+  piece(ws->t, sizeof(double) * n);
+  piece(ws->z, sizeof(double) * n);
+  piece(ws->partial, sizeof(double) * kMaxBlocks * (m + 2));
+  piece(ws->h, sizeof(double) * 3 * (m + 2));
+  piece(ws->y, sizeof(double) * (m + 2));
+  piece(ws->gm, sizeof(double) * ((size_t)(m + 1) * m + 4 * m + 2));
+  piece(ws->ticket, sizeof(unsigned));
+  if (need32) {
+    piece(ws->V32, sizeof(float) * npad * (m + 1));
+    piece(ws->vc32, sizeof(float) * n);
+    piece(ws->w32, sizeof(float) * n);
+    piece(ws->c32, sizeof(float) * n);
+    piece(ws->z32, sizeof(float) * n);
+    piece(ws->r32, sizeof(float) * n);
   }
-  return e;
+  hipError_t e = hipMalloc(&ws->arena, off);
+  if (e != hipSuccess) return e;
+  for (auto &set : parts) set(static_cast<char *>(ws->arena));
+  return hipMemset(ws->ticket, 0, sizeof(unsigned));
 }
 
 // device dot products: out[i] = V_i . w for i < ncol (out on the device)
