@@ -193,7 +193,8 @@ double LevelSet::phi(const double *x) const {
 }
 
 // Ellipsoid: x_k = a_k^2 y_k / (a_k^2 + t) with t the largest root of
-// F(t) = sum (a_k y_k / (a_k^2 + t))^2 - 1, bracketed and bisected.
+// F(t) = sum (a_k y_k / (a_k^2 + t))^2 - 1, found by Newton from the left end of a bracket
+// (bisection if that fails).
 static void closest_ellipsoid(const double *a, const double *c, int d, const double *x, double *out) {
   double y[3], a2[3];
   double amin2 = std::numeric_limits<double>::infinity();
@@ -232,15 +233,43 @@ static void closest_ellipsoid(const double *a, const double *c, int d, const dou
     for (int k = 0; k < d; ++k) out[k] += c[k];
     return;
   }
-  for (int it = 0; it < 400; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    if (F(mid) > 0.0)
-      lo = mid;
-    else
-      hi = mid;
+  // F is convex and decreasing on (-amin2, inf), and F(lo) >= 0 (a term with y_k != 0 is
+  // at least 1 at -a_k^2 + a_k |y_k|): a tangent lies below F, so Newton's method from lo
+  // moves right monotonically and never passes the root.  It stops when F reaches 0 or the
+  // step no longer moves t; bisection on [lo, hi] is the fallback.
+  double t = lo;
+  bool done = false;
+  for (int it = 0; it < 100; ++it) {
+    double f = -1.0, df = 0.0;
+    for (int k = 0; k < d; ++k)
+      if (y[k] != 0.0) {
+        const double den = a2[k] + t, q = a[k] * y[k] / den;
+        f += q * q;
+        df -= 2.0 * q * q / den;
+      }
+    if (!(f > 0.0)) {
+      done = f == 0.0 || it > 0;  // at or (by rounding) just past the root
+      break;
+    }
+    if (!(df < 0.0)) break;
+    const double tn = t - f / df;
+    if (!(tn > t) || !(tn <= hi)) {
+      done = !(tn > t);
+      break;
+    }
+    t = tn;
   }
-  const double t = 0.5 * (lo + hi);
+  if (!done) {
+    for (int it = 0; it < 400; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (F(mid) > 0.0)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    t = 0.5 * (lo + hi);
+  }
   for (int k = 0; k < d; ++k) out[k] = c[k] + a2[k] * y[k] / (a2[k] + t);
 }
 
