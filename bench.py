@@ -172,11 +172,11 @@ def cpu_baseline(w, budget_s=12.0):
 
 
 SOLVE_CASES = [
-    # (name, workload, overrides, shift_scale, (FP64 mode, mixed mode), max_it)
+    # (name, workload, overrides, shift_scale, (FP64 mode, mixed modes...), max_it)
     ("disk2d_q2", "disk2d_q2", {}, 1.0, ("gmres", "gmres_ir"), 8000),
     ("sphere3d_q1_n64", "sphere3d_q4", {"p": 1}, 1.0, ("gmres", "gmres_ir"), 4000),
     # the symmetric limit of the 3D Q4 workload (shift 0): CG applies, full size
-    ("sphere3d_q4_unshifted", "sphere3d_q4", {}, 0.0, ("cg", "cg_ir"), 4000),
+    ("sphere3d_q4_unshifted", "sphere3d_q4", {}, 0.0, ("cg", "cg_ir", "cg_rr"), 4000),
     # the shifted 3D Q4 workload: restarted GMRES stagnates (indefinite operator); reported
     ("sphere3d_q4", "sphere3d_q4", {}, 1.0, ("gmres", "gmres_ir"), 300),
 ]
@@ -203,9 +203,10 @@ def solve_section(torch, sbm, inputs):
                          "applies_f64": info["applies_f64"], "applies_f32": info["applies_f32"],
                          "rel_residual_f64": info["rel_residual"]}
             print(f"solve {name} {mode}: {rec[mode]}", file=sys.stderr, flush=True)
-        g, r = rec[modes[0]], rec[modes[1]]
-        if g["status"] == "SBM_OK" and r["status"] == "SBM_OK":
-            rec["ir_speedup"] = g["seconds"] / r["seconds"]
+        g = rec[modes[0]]
+        for mode in modes[1:]:
+            if g["status"] == "SBM_OK" and rec[mode]["status"] == "SBM_OK":
+                rec[f"{mode}_speedup"] = g["seconds"] / rec[mode]["seconds"]
         out.append(rec)
         op.close()
     return out

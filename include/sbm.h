@@ -190,9 +190,15 @@ enum {
   SBM_SOLVE_GMRES_IR = 1,   /* FP64 iterative refinement around FP32 GMRES(m) */
   SBM_SOLVE_CG_F64 = 2,     /* conjugate gradients in FP64: only for symmetric operators
                                (shift_scale = 0); the shifted operator is nonsymmetric */
-  SBM_SOLVE_CG_IR = 3       /* FP64 iterative refinement around FP32 conjugate gradients:
+  SBM_SOLVE_CG_IR = 3,      /* FP64 iterative refinement around FP32 conjugate gradients:
                                r = b - A x, |r| and x += |r| c in FP64, each inner FP32 CG
                                solves A c = r / |r| to max(1e-6, tol |b| / (2 |r|));
+                               symmetric operators only */
+  SBM_SOLVE_CG_RR = 4       /* conjugate gradients on the FP32 operator with x in FP64 and
+                               FP64 residual replacement: r is recomputed as b - A x with the
+                               FP64 operator whenever the recursive residual has dropped by
+                               1e3 since the last replacement, without restarting (outer_its
+                               counts the replacements); stops on the true residual;
                                symmetric operators only */
 };
 

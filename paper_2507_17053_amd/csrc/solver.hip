@@ -203,9 +203,10 @@ __global__ __launch_bounds__(kThreads) void cg_dot_kernel(const T *__restrict__ 
   block_partial(acc, part);
 }
 
-// alpha = |r|^2 / (p . q); x += alpha p; r -= alpha q; partials of the new |r|^2
-template <typename T>
-__global__ __launch_bounds__(kThreads) void cg_update_kernel(T *__restrict__ x, T *__restrict__ r,
+// alpha = |r|^2 / (p . q); x += alpha p; r -= alpha q; partials of the new |r|^2 (x may be
+// kept in a wider type than the other vectors)
+template <typename T, typename TX = T>
+__global__ __launch_bounds__(kThreads) void cg_update_kernel(TX *__restrict__ x, T *__restrict__ r,
                                                              const T *__restrict__ p, const T *__restrict__ q,
                                                              const double *__restrict__ rr,
                                                              const double *__restrict__ part_pq, int nblk,
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(kThreads) void cg_update_kernel(T *__restrict__ x, 
   const double alpha = *rr / block_sum(part_pq, nblk);
   double acc = 0.0;
   for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
-    x[k] = (T)((double)x[k] + alpha * (double)p[k]);
+    x[k] = (TX)((double)x[k] + alpha * (double)p[k]);
     const T rk = (T)((double)r[k] - alpha * (double)q[k]);
     r[k] = rk;
     acc += (double)rk * (double)rk;
@@ -713,6 +714,67 @@ static sbm_status cg_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *r, T *p, T
   return SBM_OK;
 }
 
+// CG on the FP32 operator with FP64 residual replacement (van der Vorst and Ye, "Residual
+// replacement strategies for Krylov subspace iterative methods", SIAM J. Sci. Comput. 22,
+// 2000), for symmetric positive definite operators: x is accumulated in FP64, r, p, q are FP32.
+// Whenever the recursive residual has dropped by 1e3 since the last replacement (or claims
+// convergence), r is replaced by the true residual b - A x computed with the FP64 operator
+// (the search direction is kept), so the FP32 recursion never drifts far from it.  The
+// iteration stops on the true residual.  Uses ws->r, t (FP64), r32, z32, w32 (FP32),
+// ws->partial and ws->y[0..1].
+static sbm_status cg_rr_run(sbm_ctx *c, const double *b, double *x, double tol_abs, int max_it, hipStream_t s,
+                            int *its_out, int *replacements, int *applies64, int *applies32, double *res_out) {
+  Workspace *ws = c->ws;
+  const int64_t n = c->n_dofs;
+  const int nb = nblocks(n);
+  float *r = ws->r32, *p = ws->z32, *q = ws->w32;
+  double *part_pq = ws->partial, *part_rr = ws->partial + kMaxBlocks;
+  double *rr = ws->y;
+  // r = b - A64 x in FP64, its square norm into rr[slot] (read back), r32 = (float) r
+  auto replace = [&](int slot, double *rn2) -> sbm_status {
+    SBM_HIP_CHECK(launch_apply(c, x, ws->t, SBM_F64, SBM_PART_ALL, s));
+    ++*applies64;
+    hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
+    SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, rr + slot, s));
+    hipLaunchKernelGGL(cast_f64_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->r, r, n);
+    SBM_HIP_CHECK(hipMemcpyAsync(rn2, rr + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+    SBM_HIP_CHECK(hipStreamSynchronize(s));
+    return SBM_OK;
+  };
+  double seg = 0.0;
+  sbm_status st = replace(0, &seg);
+  if (st != SBM_OK) return st;
+  hipLaunchKernelGGL(copy_kernel<float>, dim3(nb), dim3(kThreads), 0, s, r, p, n);
+  double res = std::sqrt(seg);
+  int it = 0;
+  for (;; ++it) {
+    const int cur = it & 1;
+    if (!(res > tol_abs) || !std::isfinite(res)) break;
+    if (it > 0 && (it % 10 == 0 || it >= max_it)) {
+      double v = 0.0;
+      SBM_HIP_CHECK(hipMemcpyAsync(&v, rr + cur, sizeof(double), hipMemcpyDeviceToHost, s));
+      SBM_HIP_CHECK(hipStreamSynchronize(s));
+      if (!(std::sqrt(v) > tol_abs) || !(v > 1e-6 * seg) || it >= max_it) {
+        st = replace(cur, &seg);
+        if (st != SBM_OK) return st;
+        ++*replacements;
+        res = std::sqrt(seg);
+        if (!(res > tol_abs) || it >= max_it) break;
+      }
+    }
+    SBM_HIP_CHECK(launch_apply(c, p, q, SBM_F32, SBM_PART_ALL, s));
+    ++*applies32;
+    hipLaunchKernelGGL(cg_dot_kernel<float>, dim3(nb), dim3(kThreads), 0, s, p, q, part_pq, n);
+    hipLaunchKernelGGL((cg_update_kernel<float, double>), dim3(nb), dim3(kThreads), 0, s, x, r, p, q, rr + cur,
+                       part_pq, nb, part_rr, n);
+    hipLaunchKernelGGL(cg_dir_kernel<float>, dim3(nb), dim3(kThreads), 0, s, p, r, rr + cur, part_rr, nb,
+                       rr + (1 - cur), n);
+  }
+  *its_out = it;
+  *res_out = res;
+  return SBM_OK;
+}
+
 }  // namespace sbm
 
 using namespace sbm;
@@ -861,7 +923,7 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
   std::memset(info, 0, sizeof(*info));
   if (!h || h->host_only || (h->n_dofs > 0 && (!b || !x)) || !(rel_tol > 0) || max_it < 1 ||
       (mode != SBM_SOLVE_GMRES_F64 && mode != SBM_SOLVE_GMRES_IR && mode != SBM_SOLVE_CG_F64 &&
-       mode != SBM_SOLVE_CG_IR)) {
+       mode != SBM_SOLVE_CG_IR && mode != SBM_SOLVE_CG_RR)) {
     set_error("sbm_solve: invalid argument");
     info->status = SBM_EINVAL;
     return SBM_EINVAL;
@@ -871,10 +933,11 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
     return SBM_OK;
   }
   hipStream_t s = (hipStream_t)stream;
-  const bool cg = mode == SBM_SOLVE_CG_F64 || mode == SBM_SOLVE_CG_IR;
+  const bool cg = mode == SBM_SOLVE_CG_F64 || mode == SBM_SOLVE_CG_IR || mode == SBM_SOLVE_CG_RR;
   // CG needs no Krylov basis: one spare column of it serves as a work vector
   const int m = cg ? 1 : (restart > 0 ? std::min(restart, 64) : 50);
-  hipError_t e = ensure_workspace(h, m, mode == SBM_SOLVE_GMRES_IR || mode == SBM_SOLVE_CG_IR);
+  hipError_t e =
+      ensure_workspace(h, m, mode == SBM_SOLVE_GMRES_IR || mode == SBM_SOLVE_CG_IR || mode == SBM_SOLVE_CG_RR);
   if (e != hipSuccess) {
     set_error(std::string("sbm_solve: workspace allocation failed: ") + hipGetErrorString(e));
     info->status = SBM_ENOMEM;
@@ -961,6 +1024,13 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
     info->inner_its = its;
     info->outer_its = 1;
     info->applies_f64 = applies;
+  } else if (mode == SBM_SOLVE_CG_RR) {
+    int its = 0, reps = 0, a64 = 0, a32 = 0;
+    st = cg_rr_run(h, b, x, tol_abs, max_it, s, &its, &reps, &a64, &a32, &res);
+    info->inner_its = its;
+    info->outer_its = reps;
+    info->applies_f64 = a64;
+    info->applies_f32 = a32;
   } else {
     // FP64 refinement around FP32 CG: r = b - A x and |r| in FP64, c ~= A32^-1 (r / |r|) by
     // FP32 CG, x += |r| c in FP64.  The inner tolerance is what the remaining reduction needs

@@ -26,7 +26,7 @@ SBM_OK, SBM_EINVAL, SBM_ENOMEM, SBM_EHIP, SBM_ENOCONV, SBM_EUNSUPPORTED = range(
 SBM_CG, SBM_DG = 0, 1
 SBM_F64, SBM_F32 = 0, 1
 LS_KINDS = {"sphere": 0, "ellipsoid": 1, "torus": 2, "sphere_union": 3, "halfspace": 4}
-SOLVE_MODES = {"gmres": 0, "gmres_ir": 1, "cg": 2, "cg_ir": 3}
+SOLVE_MODES = {"gmres": 0, "gmres_ir": 1, "cg": 2, "cg_ir": 3, "cg_rr": 4}
 _STATUS = {0: "SBM_OK", 1: "SBM_EINVAL", 2: "SBM_ENOMEM", 3: "SBM_EHIP", 4: "SBM_ENOCONV",
            5: "SBM_EUNSUPPORTED"}
 

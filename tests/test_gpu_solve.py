@@ -88,16 +88,17 @@ def test_gmres_reaches_1e10_against_oracle(d, n, ls, p, disc, m, mode):
     assert abs(e_gpu - e_ref) <= 1e-6 * e_ref + 1e-12, (e_gpu, e_ref)
 
 
-@pytest.mark.parametrize("mode", ["cg", "cg_ir"])
+@pytest.mark.parametrize("mode", ["cg", "cg_ir", "cg_rr"])
 def test_cg_on_unshifted_symmetric_limit(mode):
-    """CG in FP64, and FP64 refinement around FP32 CG, on the symmetric limit (shift 0)."""
+    """CG in FP64, FP64 refinement around FP32 CG, and FP32 CG with FP64 residual replacement,
+    on the symmetric limit (shift 0)."""
     ls = inputs.sphere((0, 0, 0), 0.75)
     ref, op = _problem(3, 8, ls, 2, "cg", shift=0.0)
     b, bref = _rhs(ref, op)
     x = torch.zeros_like(b)
     info = op.solve(b, x, rel_tol=1e-10, max_it=4000, mode=mode)
     assert info["status"] == sbm.SBM_OK and info["rel_residual"] <= 1e-10, info
-    if mode == "cg_ir":
+    if mode in ("cg_ir", "cg_rr"):
         assert info["applies_f32"] > info["applies_f64"] and info["outer_its"] >= 1
     A = O.assemble(ref)
     res = np.linalg.norm(bref - A @ x.cpu().numpy()) / np.linalg.norm(bref)
