@@ -1008,9 +1008,11 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
       hipLaunchKernelGGL(fill_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, n);
       int its = 0, applies = 0;
       double inner_res = 0.0;
-      // inner solve of A32 c = r / |r| to 1e-4 (unit right-hand side), at most 4 restart cycles
-      (void)gmres_run<float>(h, SBM_F32, ws->r32, ws->c32, ws->V32, ws->vc32, ws->w32, ws->z32, dinv32, m, 1e-4,
-                             std::min(4 * m, max_it - total_its), s, &its, &applies, &inner_res);
+      // inner solve of A32 c = r / |r| (unit right-hand side) to what the remaining reduction
+      // needs, max(1e-6, tol / (2 |r|)) (FP32 reaches about 1e-6), at most 4 restart cycles
+      const double inner_tol = std::max(1e-6, 0.5 * tol_abs / res);
+      (void)gmres_run<float>(h, SBM_F32, ws->r32, ws->c32, ws->V32, ws->vc32, ws->w32, ws->z32, dinv32, m,
+                             inner_tol, std::min(4 * m, max_it - total_its), s, &its, &applies, &inner_res);
       total_its += its;
       info->applies_f32 += applies;
       hipLaunchKernelGGL(add_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, ws->y + (m + 1), x, n);
