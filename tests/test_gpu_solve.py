@@ -105,11 +105,12 @@ def test_cg_on_unshifted_symmetric_limit(mode):
     assert res <= 2e-10
 
 
-def test_jacobi_preconditioned_gmres():
+@pytest.mark.parametrize("mode", ["gmres", "gmres_ir"])
+def test_jacobi_preconditioned_gmres(mode):
     ref, op = _problem(2, 16, DISK, 1, "cg")
     b, bref = _rhs(ref, op)
     x = torch.zeros_like(b)
-    info = op.solve(b, x, rel_tol=1e-10, max_it=2000, mode="gmres", restart=64, jacobi=True)
+    info = op.solve(b, x, rel_tol=1e-10, max_it=2000, mode=mode, restart=64, jacobi=True)
     assert info["status"] == sbm.SBM_OK, info
     res = np.linalg.norm(bref - O.assemble(ref) @ x.cpu().numpy()) / np.linalg.norm(bref)
     assert res <= 2e-10
