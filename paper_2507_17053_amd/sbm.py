@@ -242,6 +242,11 @@ class Operator:
         _check(_lib.sbm_rhs(self._h, _hptr(f_qp), _hptr(g_bp), _dptr(out), _stream_ptr(stream)), "sbm_rhs")
 
     def solve(self, b, x, rel_tol=1e-10, max_it=10000, mode="gmres", restart=50, jacobi=False, stream=None):
+        """sbm_solve: A x = b to rel_tol from the initial x (FP64 device tensors of n_dofs).
+        mode: "gmres" (FP64 GMRES(restart)), "gmres_ir" (FP64 refinement around FP32 GMRES),
+        "cg" (FP64 CG), "cg_ir" (FP64 refinement around FP32 CG), "cg_rr" (FP32 CG with FP64
+        residual replacement); the CG modes need a symmetric operator (shift_scale = 0).
+        Returns the sbm_solve_info fields as a dict; ENOCONV is reported there, not raised."""
         info = SolveInfo()
         st = _lib.sbm_solve(self._h, _dptr(b), _dptr(x), float(rel_tol), int(max_it), SOLVE_MODES[mode],
                             int(restart), int(bool(jacobi)), _stream_ptr(stream), ctypes.byref(info))
