@@ -165,10 +165,22 @@ def cpu_baseline(w, budget_s=12.0):
         el = time.perf_counter() - t0
         if el >= budget_s or (n >= 1 and el * (n + 1) / n > 2.5 * budget_s):
             break
+    # one apply on a single thread (then back to all threads: the OpenMP setting persists)
+    t1 = time.perf_counter()
+    ap(u, n_threads=1)
+    el1 = time.perf_counter() - t1
+    ap(u, n_threads=threads)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": prob.n_dofs * n / el, "unit": "DoF/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} full FP64 applies of the same workload ({prob.n_dofs} DoFs), brute-force "
                       f"dense local matrices in plain C + OpenMP, {el:.1f} s",
-            "seconds": el}
+            "seconds": el, "single_core_value": prob.n_dofs / el1, "cpu_model": model,
+            "host_cpus": os.cpu_count()}
 
 
 SOLVE_CASES = [
