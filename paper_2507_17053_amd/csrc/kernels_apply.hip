@@ -971,6 +971,17 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
   T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
   const T h = T(sc.h), sigf = T(sc.sigma_f);
 
+  // neighbours of the 2d faces, and the first neighbour's run for this thread: every
+  // neighbour's values are loaded one face ahead, so the loads overlap the previous face
+  int nbs[2 * D];
+#pragma unroll
+  for (int k = 0; k < 2 * D; ++k) nbs[k] = act ? nbr[(int64_t)cell * 2 * D + k] : -1;
+  T nx[N1];
+  if (nbs[0] >= 0) {
+    const T *up = u + (int64_t)nbs[0] * NB + N1 * t;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) nx[i] = up[i];
+  }
   // own block (contiguous), thread t = run
   if (act) {
     const T *up = u + (int64_t)cell * NB + N1 * t;
@@ -988,15 +999,19 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
   }
   // ---- interior faces ----
   const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
+#pragma unroll
   for (int code = 0; code < 2 * D; ++code) {
     const FaceAxes<D, N1> fa(code);
-    const int nb = act ? nbr[(int64_t)cell * 2 * D + code] : -1;
-    const bool has = nb >= 0;
+    const bool has = nbs[code] >= 0;
     __syncthreads();  // previous users of A (neighbour tile) and f1..f4 are done
     if (has) {
-      const T *up = u + (int64_t)nb * NB + N1 * t;
 #pragma unroll
-      for (int i = 0; i < N1; ++i) A[N1 * t + i] = up[i];
+      for (int i = 0; i < N1; ++i) A[N1 * t + i] = nx[i];
+    }
+    if (code + 1 < 2 * D && nbs[code + 1] >= 0) {
+      const T *up = u + (int64_t)nbs[code + 1] * NB + N1 * t;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) nx[i] = up[i];
     }
     __syncthreads();
     const T sgn = fa.s ? T(1) : T(-1);
