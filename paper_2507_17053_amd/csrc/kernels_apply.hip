@@ -455,13 +455,20 @@ struct BrickCfg {
   static constexpr int NT =
       (sizeof(T) == 4 && D == 3 && P == 4) ? 256 : (NT0 < 128 ? 128 : (NT0 > 256 ? 256 : NT0));
   static constexpr int EPB0 = NT / NP;
-  static constexpr int EPB = EPB0 < 1 ? 1 : EPB0;   // cells per batch
+  static constexpr int EPB = EPB0 < 1 ? 1 : EPB0;   // faces per batch (and thread groups with NP threads)
   static constexpr int NG = (NT + NP - 1) / NP;      // thread groups (the last may be partial)
+  // cells per batch of the per-cell path: each has two tiles of NB values; the groups beyond
+  // share one more pair of tiles (they only take part in the barriers).  In FP64 at 3D p=4 the
+  // batch is cut to 4 cells so that the tiles fit in the sweep arrays' space: 6 instead of 5
+  // workgroups per CU.
+  static constexpr int EPC0 = (sizeof(T) == 8 && D == 3 && P == 4) ? 4 : EPB;
+  static constexpr int EPC = EPC0 < EPB ? EPC0 : EPB;
+  static constexpr int NTILE = EPC < NG ? EPC + 1 : NG;  // tile pairs
   // LDS in doubles: the lattice accumulator (FP64 in both precisions: LDS atomic adds in FP32
   // were measured ~20x slower than in FP64 on gfx950), then either the two sweep arrays of
   // the full path (in FP64 the first one is the accumulator itself) or the per-cell tiles.
   static constexpr int TAIL_SWEEP = NL;  // FP64: LB; FP32: LA and LB
-  static constexpr int TAIL_CELLS = (2 * NG * NB * (int)sizeof(T) + 7) / 8;
+  static constexpr int TAIL_CELLS = (2 * NTILE * NB * (int)sizeof(T) + 7) / 8;
   static constexpr int SMEM_D = NL + (TAIL_SWEEP > TAIL_CELLS ? TAIL_SWEEP : TAIL_CELLS);
 };
 
@@ -643,22 +650,23 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
   }
 
   if (!full && (parts & SBM_PART_CELLS)) {
-    // ---- partial brick: cell by cell (EPB cells per batch; a trailing group of fewer than
-    // NP threads only takes part in the barriers) ----
-    constexpr int NG = C::NG;
-    T *A = tail + le * NB, *B = tail + NG * NB + le * NB;
-    const bool grp = le < EPB;
+    // ---- partial brick: cell by cell (EPC cells per batch; the other thread groups only
+    // take part in the barriers) ----
+    constexpr int EPC = C::EPC, NTILE = C::NTILE;
+    const int tl = le < EPC ? le : NTILE - 1;  // groups beyond EPC share the last tile pair
+    T *A = tail + tl * NB, *B = tail + NTILE * NB + tl * NB;
+    const bool grp = le < EPC;
     // software pipeline: the pencils of batch b+1 are in flight while batch b computes
     T x[N1];
     {
       const bool act = grp && c0 + le < c1;
       gather_pencil<T, D, N1>(br.runs + (int64_t)(act ? c0 + le : 0) * NP, u, t, act, x);
     }
-    for (int b = c0; b < c1; b += EPB) {
+    for (int b = c0; b < c1; b += EPC) {
       const int idx = b + le;
       const bool act = grp && idx < c1;
       const int loc = act ? br.cell_loc[idx] : 0;
-      const int idn = idx + EPB;
+      const int idn = idx + EPC;
       const bool actn = grp && idn < c1;
       T xn[N1], out[N1];
       gather_pencil<T, D, N1>(br.runs + (int64_t)(actn ? idn : 0) * NP, u, t, actn, xn);
