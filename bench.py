@@ -367,7 +367,7 @@ def main():
     if args.solve:
         out["solve"] = solve_section(torch, sbm, inputs)
     if args.serve > 0:
-        out["serving"] = serve_section(args.serve, args.serve_max_it, args.serve_rate, slots=8, budget_gb=96.0)
+        out["serving"] = serve_section(args.serve, args.serve_max_it, args.serve_rate, slots=12, budget_gb=96.0)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
