@@ -299,6 +299,16 @@ static void closest_union(const std::vector<double> &cs, const std::vector<doubl
       for (int k = 0; k < d; ++k) out[k] = pt[k];
     }
   };
+  // Every point of sphere i is at least lb[i] = | |x - c_i| - r_i | from x, so a seam or triple
+  // point of spheres whose bounds exceed the best distance so far (with a margin far above
+  // rounding) cannot be selected and is skipped: the result is that of the full enumeration.
+  std::vector<double> lb(S);
+  for (int i = 0; i < S; ++i) {
+    double u[3];
+    for (int k = 0; k < d; ++k) u[k] = x[k] - cs[3 * i + k];
+    lb[i] = std::fabs(norm_d(u, d) - rs[i]);
+  }
+  auto hopeless = [&](double bound) { return bound > best * (1.0 + 1e-12) + 1e-300; };
   double pt[3];
   for (int i = 0; i < S; ++i) {
     double u[3];
@@ -316,6 +326,7 @@ static void closest_union(const std::vector<double> &cs, const std::vector<doubl
   }
   for (int i = 0; i < S; ++i)
     for (int j = i + 1; j < S; ++j) {
+      if (hopeless(std::max(lb[i], lb[j]))) continue;
       double e[3];
       for (int k = 0; k < d; ++k) e[k] = cs[3 * j + k] - cs[3 * i + k];
       const double D = norm_d(e, d);
@@ -357,6 +368,7 @@ static void closest_union(const std::vector<double> &cs, const std::vector<doubl
     for (int i = 0; i < S; ++i)
       for (int j = i + 1; j < S; ++j)
         for (int l = j + 1; l < S; ++l) {
+          if (hopeless(std::max({lb[i], lb[j], lb[l]}))) continue;
           // three-sphere intersection in the frame (ex, ey, ez) anchored at c_i
           const double *c1 = &cs[3 * i], *c2 = &cs[3 * j], *c3 = &cs[3 * l];
           double ex[3], ey[3], ez[3];
