@@ -184,3 +184,34 @@ def test_apply_in_captured_graph_matches_eager(dtype):
         assert (torch.linalg.norm(w - ref2) / torch.linalg.norm(ref2)).item() <= tol, rep
         op.apply(w, scratch)  # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_apply_batch_matches_single_applies(dtype):
+    """sbm_apply_batch over operators of different dimension, degree and discretisation gives
+    each operator's own apply (to rounding: LDS atomics order sums differently per launch)."""
+    cases = [dict(d=2, n=16, ls=inputs.sphere((0.05, -0.03), 0.7), p=2, disc="cg"),
+             dict(d=3, n=6, ls=inputs.sphere((0, 0, 0), 0.75), p=2, disc="dg"),
+             dict(d=3, n=10, ls=inputs.sphere((0, 0, 0), 0.75), p=4, disc="cg")]
+    ops = [sbm.Operator(c["d"], c["n"], -1.0, 1.0, c["ls"], c["p"], disc=c["disc"]) for c in cases]
+    us = [torch.from_numpy(inputs.uniform_vector(o.n_dofs, seed=i)).to("cuda", dtype) for i, o in enumerate(ops)]
+    vs = [torch.full_like(u, 7.0) for u in us]
+    refs = [torch.empty_like(u) for u in us]
+    for o, u, r in zip(ops, us, refs):
+        o.apply(u, r)
+    sbm.apply_batch(ops, us, vs)
+    torch.cuda.synchronize()
+    for v, r in zip(vs, refs):
+        err = (torch.linalg.norm((v - r).double()) / torch.linalg.norm(r.double())).item()
+        assert err <= (1e-14 if dtype == torch.float64 else 1e-6), err
+
+
+def test_footprint_estimate_bounds_setup_allocation():
+    """The host-side estimate used for admission is at least what sbm_setup allocates."""
+    for d, n, ls, p, disc in [(2, 16, inputs.sphere((0.05, -0.03), 0.7), 2, "cg"),
+                              (3, 12, inputs.sphere((0, 0, 0), 0.75), 4, "cg"),
+                              (3, 10, inputs.torus(0.55, 0.3), 3, "dg"),
+                              (3, 16, inputs.sphere_union(1), 6, "cg")]:
+        op = sbm.Operator(d, n, -1.0, 1.0, ls, p, disc=disc)
+        est = sbm.footprint_estimate(d, n, -1.0, 1.0, p, disc, op.n_cells, op.n_sbm_faces)
+        assert est >= op.device_bytes, (d, n, p, disc, est, op.device_bytes)
