@@ -962,8 +962,10 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
 //   [u]_K = u_K - u_N,  {du/dn_K} = (du_K/dn_K + du_N/dn_K)/2,
 //   K's rows += int (sigma_F [u]_K - {du/dn_K}) v - 1/2 [u]_K dv/dn_K   (Alg. 2, per side)
 // ------------------------------------------------------------------------------------
+// Face-by-face form (one group of NP threads per cell walks the 2d faces in turn), for the
+// degrees with more than 128 threads per cell in the parallel form below.
 template <typename T, int D, int N1, int EPB>
-__global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t *__restrict__ nbr,
+__global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int32_t *__restrict__ nbr,
                                                       const T *__restrict__ u, T *__restrict__ v,
                                                       KTab<T, N1> tab, KScal sc, T scale) {
   constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, P = N1 - 1;
@@ -1064,6 +1066,124 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
   }
 }
 
+// Thread layout: 2d groups of NP threads per cell, group g evaluates interior face g (code
+// 2 axis + side) with its own neighbour tile and scratch, all faces at once; group 0 also
+// forms the cell term (the other groups pass its barriers on a shared scratch pair of tiles).
+// Then every row of the cell adds the cell term and the faces' rows in face order (the order
+// of a face-by-face loop).
+template <typename T, int D, int N1>
+constexpr int dg_cells_per_block(bool one_wave) {
+  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, TPC = 2 * D * NP;
+  // LDS per cell: own tile, cell-term tiles, 2d neighbour tiles, cell result (NB each);
+  // per face 6 NP of scratch and results
+  constexpr int per_cell = ((4 + 2 * D) * NB + 2 * D * 6 * NP) * (int)sizeof(T);
+  int e = (one_wave ? 64 : 256) / TPC;
+  if (e < 1) e = 1;
+  while (e > 1 && e * per_cell + 2 * NB * (int)sizeof(T) > 60000) --e;
+  return e;
+}
+
+template <typename T, int D, int N1, int EPB>
+__global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t *__restrict__ nbr,
+                                                      const T *__restrict__ u, T *__restrict__ v,
+                                                      KTab<T, N1> tab, KScal sc, T scale) {
+  constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, P = N1 - 1, NF = 2 * D, TPC = NF * NP;
+  __shared__ T su_all[EPB * NB];           // own tile
+  __shared__ T sab_all[(2 * EPB + 2) * NB];  // cell-term tiles (A, B) per cell + one shared scratch pair
+  __shared__ T sn_all[EPB * NF * NB];      // neighbour tiles, one per face
+  __shared__ T sw_all[EPB * NB];           // cell term
+  __shared__ T f_all[EPB * NF * 6 * NP];   // per face: f1..f4 scratch, Rv, Rg
+  const int le = threadIdx.x / TPC, r = threadIdx.x - le * TPC;  // cell in block, thread in cell
+  const int g = r / NP, t = r - g * NP;                            // face group, node / run
+  const int cell = xcd_block() * EPB + le;
+  const bool act = cell < n_cells;
+  T *su = su_all + le * NB, *sw = sw_all + le * NB;
+  T *A = (g == 0) ? sab_all + 2 * le * NB : sab_all + 2 * EPB * NB;
+  T *B = A + NB;
+  T *An = sn_all + (le * NF + g) * NB;
+  T *fw = f_all + (le * NF + g) * 6 * NP;
+  T *f1 = fw, *f2 = fw + NP, *f3 = fw + 2 * NP, *f4 = fw + 3 * NP, *fRv = fw + 4 * NP, *fRg = fw + 5 * NP;
+  const T h = T(sc.h), sigf = T(sc.sigma_f);
+
+  // loads: group 0 the cell's own block (thread t = run), group g the neighbour across face g
+  const int nb = act ? nbr[(int64_t)cell * NF + g] : -1;
+  const bool has = nb >= 0;
+  if (g == 0 && act) {
+    const T *up = u + (int64_t)cell * NB + N1 * t;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) su[N1 * t + i] = up[i];
+  }
+  if (has) {
+    const T *up = u + (int64_t)nb * NB + N1 * t;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) An[N1 * t + i] = up[i];
+  }
+  __syncthreads();
+  // ---- interior face g: traces, Gauss-point integrands, transposed integration ----
+  {
+    const FaceAxes<D, N1> fa(g);
+    const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
+    const T sgn = fa.s ? T(1) : T(-1);
+    const int node_off = jb * fa.Sb + jc * fa.Sc;
+    T dK = 0, dN = 0;
+#pragma unroll
+    for (int ia = 0; ia < N1; ++ia) {
+      dK += (fa.s ? tab.D1[ia] : tab.D0[ia]) * su[ia * fa.Sa + node_off];
+      dN += (fa.s ? tab.D0[ia] : tab.D1[ia]) * An[ia * fa.Sa + node_off];
+    }
+    const T uK = su[fa.s * P * fa.Sa + node_off];
+    const T uN = An[(1 - fa.s) * P * fa.Sa + node_off];
+    f1[t] = uK - uN;                       // [u]_K at the face nodes
+    f2[t] = T(0.5) * sgn * (dK + dN) / h;  // {du/dn_K} at the face nodes
+    __syncthreads();
+    T jq, aq;
+    face_interpolate<T, D, N1>(tab, t, f1, f2, f3, f4, jq, aq);
+    T om;
+    if constexpr (D == 3)
+      om = h * h * tab.w[t % N1] * tab.w[t / N1];
+    else
+      om = h * tab.w[t];
+    __syncthreads();
+    f3[t] = om * (sigf * jq - aq);
+    f4[t] = T(-0.5) * om * jq * sgn / h;
+    __syncthreads();
+    T Rv, Rg;
+    face_integrate<T, D, N1>(tab, t, f1, f2, f3, f4, Rv, Rg);
+    fRv[t] = has ? Rv : T(0);
+    fRg[t] = has ? Rg : T(0);
+  }
+  // ---- cell term (group 0; the other groups on the shared scratch tiles) ----
+  {
+    T x[N1], out[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) x[k] = su[t + NP * k];
+    kron_cell<T, D, N1>(tab, t, x, A, B, scale, out);
+    if (g == 0) {
+#pragma unroll
+      for (int i = 0; i < N1; ++i) sw[N1 * t + i] = out[i];
+    }
+  }
+  __syncthreads();
+  // ---- rows: cell term, then each face's rows in face order ----
+  if (act) {
+    for (int i = r; i < NB; i += TPC) {
+      const int ik[3] = {i % N1, (i / N1) % N1, i / (N1 * N1)};
+      T val = sw[i];
+#pragma unroll
+      for (int code = 0; code < NF; ++code) {
+        const int a = code >> 1, s = code & 1;
+        // node index on face `code`: lower tangential coordinate + N1 * upper one
+        const int lo = (a == 0) ? 1 : 0, hi = (a == 2) ? 1 : 2;
+        const int node = (D == 3) ? ik[lo] + N1 * ik[hi] : ik[lo];
+        const int ia = ik[a];
+        const T *fc = f_all + (le * NF + code) * 6 * NP;
+        val += ((ia == s * P) ? fc[4 * NP + node] : T(0)) + (s ? tab.D1[ia] : tab.D0[ia]) * fc[5 * NP + node];
+      }
+      v[(int64_t)cell * NB + i] = val;
+    }
+  }
+}
+
 template <typename T, int N1>
 KTab<T, N1> make_ktab(const Rules1D &r) {
   KTab<T, N1> k;
@@ -1125,13 +1245,28 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
     // entities per workgroup: as many as fit, unless that leaves fewer than two workgroups
     // per compute unit; then one wavefront's worth
     if (nc > 0 && (parts & SBM_PART_CELLS)) {
-      constexpr int E = epb<T, D, N1, 4, 0>(), E1 = epb_one_wave<T, D, N1, 4>();
-      if ((nc + E - 1) / E >= two_per_cu())
-        hipLaunchKernelGGL((dg_cell_kernel<T, D, N1, E>), dim3((nc + E - 1) / E), dim3(E * NP), 0, s, nc,
-                           c->d_nbr, u, v, tab, sc, scale);
-      else
-        hipLaunchKernelGGL((dg_cell_kernel<T, D, N1, E1>), dim3((nc + E1 - 1) / E1), dim3(E1 * NP), 0, s, nc,
-                           c->d_nbr, u, v, tab, sc, scale);
+      // faces in parallel where a cell needs at most 128 threads (3D p <= 3, 2D): measured 7 %
+      // (FP64) to 20 % (FP32) faster at 3D p=3; at 3D p=5 its 216-thread, 31 KB cells leave the
+      // grid in more than one round and the face-by-face form is faster
+      constexpr int TPC = 2 * D * NP, NBC = Shape<D, N1>::NB;
+      constexpr bool PAR = TPC <= 128 && ((4 + 2 * D) * NBC + 2 * D * 6 * NP + 2 * NBC) * (int)sizeof(T) <= 60000;
+      if constexpr (PAR) {
+        constexpr int E = dg_cells_per_block<T, D, N1>(false), E1 = dg_cells_per_block<T, D, N1>(true);
+        if ((nc + E - 1) / E >= two_per_cu())
+          hipLaunchKernelGGL((dg_cell_kernel<T, D, N1, E>), dim3((nc + E - 1) / E), dim3(E * TPC), 0, s, nc,
+                             c->d_nbr, u, v, tab, sc, scale);
+        else
+          hipLaunchKernelGGL((dg_cell_kernel<T, D, N1, E1>), dim3((nc + E1 - 1) / E1), dim3(E1 * TPC), 0, s, nc,
+                             c->d_nbr, u, v, tab, sc, scale);
+      } else {
+        constexpr int E = epb<T, D, N1, 4, 0>(), E1 = epb_one_wave<T, D, N1, 4>();
+        if ((nc + E - 1) / E >= two_per_cu())
+          hipLaunchKernelGGL((dg_cell_seq_kernel<T, D, N1, E>), dim3((nc + E - 1) / E), dim3(E * NP), 0, s, nc,
+                             c->d_nbr, u, v, tab, sc, scale);
+        else
+          hipLaunchKernelGGL((dg_cell_seq_kernel<T, D, N1, E1>), dim3((nc + E1 - 1) / E1), dim3(E1 * NP), 0, s,
+                             nc, c->d_nbr, u, v, tab, sc, scale);
+      }
     }
     if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
       constexpr int E = epb<T, D, N1, 2, 0>(), E1 = epb_one_wave<T, D, N1, 2>();
