@@ -954,6 +954,83 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
   }
 }
 
+// DG surrogate-boundary faces in 3D with (p+1)^3 threads per face: thread (t, i2) takes face
+// point t and slab i2 of the cell.  The cell's values are loaded one per thread; E u at each
+// shifted point is split over the slabs (each thread one slab's (p+1)^2 terms) and the slab
+// sums are added in slab order, as in sbm_face_eval; the face-node phases (normal
+// derivative, Gauss interpolation, integration) run in every slab with identical results;
+// each thread adds one of the face's rows.  For p <= 5 ((p+1)^3 <= 256).
+template <typename T, int N1, int EPB>
+__global__ __launch_bounds__(256) void sbm_face_slab_kernel(int n_faces, const int32_t *__restrict__ face_cell,
+                                                            const int32_t *__restrict__ face_code,
+                                                            const double *__restrict__ face_xi,
+                                                            const T *__restrict__ u, T *__restrict__ v,
+                                                            KTab<T, N1> tab, KScal sc) {
+  constexpr int D = 3, NP = N1 * N1, NB = NP * N1;
+  __shared__ T su_all[EPB * NB];
+  __shared__ T sp_all[EPB * NB];  // slab partial sums of E u
+  __shared__ T f_all[4 * EPB * NP];
+  const int le = threadIdx.x / NB, r = threadIdx.x - le * NB;
+  const int t = r % NP, i2 = r / NP;
+  const int f = xcd_block() * EPB + le;
+  const bool act = f < n_faces;
+  T *su = su_all + le * NB, *sp = sp_all + le * NB;
+  T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
+  double xp[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xp[k] = act ? face_xi[((int64_t)f * NP + t) * D + k] : 0.0;
+  const FaceAxes<D, N1> fa(act ? face_code[f] : 0);
+  const int64_t base = (int64_t)(act ? face_cell[f] : 0) * NB;
+  if (act) su[r] = u[base + r];
+  __syncthreads();
+  const T h = T(sc.h), sig = T(sc.sigma_gamma);
+  const T sh = (fa.s ? T(1) : T(-1)) / h;
+  const int jb = t % N1, jc = t / N1;
+  const int node_off = jb * fa.Sb + jc * fa.Sc;
+  {
+    T g = 0;
+#pragma unroll
+    for (int ia = 0; ia < N1; ++ia) g += (fa.s ? tab.D1[ia] : tab.D0[ia]) * su[ia * fa.Sa + node_off];
+    f1[t] = g;
+    f2[t] = g;
+  }
+  __syncthreads();
+  T dn, dn2;
+  face_interpolate<T, D, N1>(tab, t, f1, f2, f3, f4, dn, dn2);
+  dn *= sh;
+  // slab i2 of E u at point t
+  T part = 0;
+  if (act) {
+    double l[D][N1];
+#pragma unroll
+    for (int k = 0; k < D; ++k) lagrange_at<N1>(tab.z, tab.cinv, xp[k], l[k]);
+    T s1 = 0;
+#pragma unroll
+    for (int i1 = 0; i1 < N1; ++i1) {
+      T s0 = 0;
+#pragma unroll
+      for (int i0 = 0; i0 < N1; ++i0) s0 += T(l[0][i0]) * su[i0 + N1 * i1 + NP * i2];
+      s1 += T(l[1][i1]) * s0;
+    }
+    T l2 = 0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) l2 = (j == i2) ? T(l[2][j]) : l2;
+    part = l2 * s1;
+  }
+  sp[i2 * NP + t] = part;
+  __syncthreads();  // slab sums written; face_interpolate's reads of f3/f4 are done
+  T eu = 0;
+#pragma unroll
+  for (int j = 0; j < N1; ++j) eu += sp[j * NP + t];
+  const T om = act ? h * h * tab.w[t % N1] * tab.w[t / N1] : T(0);
+  f3[t] = om * (sig * eu - dn);  // tested against v
+  f4[t] = -om * eu * sh;         // tested against the reference derivative along a
+  __syncthreads();
+  T Rv, Rg;
+  face_integrate<T, D, N1>(tab, t, f1, f2, f3, f4, Rv, Rg);
+  if (act) atomic_add(v + base + i2 * fa.Sa + node_off, face_row<T, D, N1>(tab, fa, i2, Rv, Rg));
+}
+
 // ------------------------------------------------------------------------------------
 // DG cell kernel: Laplace cell term + SIPG terms of the cell's interior faces, computed
 // from the cell's side only (each interior face is evaluated twice, once per cell), so
@@ -1269,13 +1346,23 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
       }
     }
     if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
-      constexpr int E = epb<T, D, N1, 2, 0>(), E1 = epb_one_wave<T, D, N1, 2>();
-      if ((nf + E - 1) / E >= two_per_cu())
-        hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s, nf,
-                           c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
-      else
-        hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E1>), dim3((nf + E1 - 1) / E1), dim3(E1 * NP), 0, s, nf,
-                           c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
+      if constexpr (D == 3 && Shape<D, N1>::NB <= 256) {
+        constexpr int NB = Shape<D, N1>::NB, E = 256 / NB, E1 = (64 / NB < 1) ? 1 : 64 / NB;
+        if ((nf + E - 1) / E >= two_per_cu())
+          hipLaunchKernelGGL((sbm_face_slab_kernel<T, N1, E>), dim3((nf + E - 1) / E), dim3(E * NB), 0, s, nf,
+                             c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
+        else
+          hipLaunchKernelGGL((sbm_face_slab_kernel<T, N1, E1>), dim3((nf + E1 - 1) / E1), dim3(E1 * NB), 0, s,
+                             nf, c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
+      } else {
+        constexpr int E = epb<T, D, N1, 2, 0>(), E1 = epb_one_wave<T, D, N1, 2>();
+        if ((nf + E - 1) / E >= two_per_cu())
+          hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s, nf,
+                             c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
+        else
+          hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E1>), dim3((nf + E1 - 1) / E1), dim3(E1 * NP), 0, s, nf,
+                             c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
+      }
     }
   }
   return hipGetLastError();
