@@ -215,7 +215,7 @@ typedef struct {
 /*
  * sbm_solve -- solve A x = b to ||b - A x|| <= rel_tol ||b|| from the initial guess in x.
  * b, x: device FP64 vectors of n_dofs entries (x is read as the initial guess and
- * overwritten).  restart: Krylov dimension m of GMRES (<= 0 selects 50, at most 64).
+ * overwritten).  restart: Krylov dimension m of GMRES (<= 0 selects 50, at most 256).
  * max_it bounds the total Krylov iterations.  jacobi != 0 right-preconditions with the
  * inverse of the operator's diagonal.  The Krylov workspace (GMRES: m + 1 basis vectors per
  * precision used) is allocated on the first solve and kept with the handle; solves on one

@@ -26,6 +26,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxBlocks = 1024;
+constexpr int kMaxRestart = 256;  // longest GMRES restart (basis columns)
 // The GMRES basis is stored in row tiles: the m1 columns of rows [128 t, 128 t + 128) are one
 // contiguous block (column i at offset 128 i), so a sweep over a range of rows and all columns
 // streams contiguous memory.
@@ -404,6 +405,135 @@ __global__ __launch_bounds__(kThreads) void gs_kernel(const T *__restrict__ V, i
   }
 }
 
+// The Gram-Schmidt kernels for more than 64 columns: the columns are taken in chunks of 64
+// (wave q of the 4 owns chunk columns q, q + 4, ...), with the same row layout, partial
+// layout and last-block reduction as gs_kernel.  MODE 0: one sweep per chunk.  MODE 1: a
+// sweep for w -= V coef over all chunks (the block's new w values are its own rows, read back
+// after a barrier), then one sweep per chunk for the products: V is read twice.  MODE 2: one
+// sweep (update and norm).
+template <typename T, int MODE>
+__global__ __launch_bounds__(kThreads) void gs_wide_kernel(const T *__restrict__ V, int m1, int ncol,
+                                                           const double *__restrict__ coef, T *__restrict__ w,
+                                                           int64_t n, double *__restrict__ partial,
+                                                           unsigned *__restrict__ counter, double *__restrict__ out,
+                                                           ArnoldiArgs aa) {
+  constexpr int NW = kThreads / 64, CPW = 16, R = 2, CH = NW * CPW;
+  __shared__ double red[NW][64 * R];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nch = (ncol + CH - 1) / CH;
+  const int64_t stride = (int64_t)gridDim.x * 64 * R;
+  // products of the chunk columns with the current w over this block's rows -> partials
+  auto products = [&](int ch) {
+    double acc[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) acc[c] = 0.0;
+    for (int64_t r0 = (int64_t)blockIdx.x * 64 * R; r0 < n; r0 += stride) {
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const int64_t k = r0 + rr * 64 + lane;
+        const bool ok = k < n;
+        const int64_t base = tile_ix(ok ? k : 0, 0, m1);
+        const double wk = ok ? (double)w[k] : 0.0;
+        T tv[CPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          const int i = ch * CH + wave + NW * c;
+          tv[c] = V[(ok && i < ncol) ? base + (int64_t)i * kTile : 0];
+        }
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          const int i = ch * CH + wave + NW * c;
+          acc[c] += (ok && i < ncol) ? (double)tv[c] * wk : 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int i = ch * CH + wave + NW * c;
+      double sacc = acc[c];
+      for (int off = 32; off > 0; off >>= 1) sacc += __shfl_down(sacc, off, 64);
+      if (lane == 0 && i < ncol) partial[(int64_t)i * kMaxBlocks + blockIdx.x] = sacc;
+    }
+  };
+  if constexpr (MODE == 0) {
+    for (int ch = 0; ch < nch; ++ch) products(ch);
+  } else {
+    double nrm = 0.0;
+    for (int64_t r0 = (int64_t)blockIdx.x * 64 * R; r0 < n; r0 += stride) {
+      double sp[R];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) sp[rr] = 0.0;
+      for (int ch = 0; ch < nch; ++ch) {
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+          const int64_t k = r0 + rr * 64 + lane;
+          const bool ok = k < n;
+          const int64_t base = tile_ix(ok ? k : 0, 0, m1);
+          T tv[CPW];
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            const int i = ch * CH + wave + NW * c;
+            tv[c] = V[(ok && i < ncol) ? base + (int64_t)i * kTile : 0];
+          }
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            const int i = ch * CH + wave + NW * c;
+            sp[rr] += (ok && i < ncol) ? coef[i] * (double)tv[c] : 0.0;
+          }
+        }
+      }
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) red[wave][rr * 64 + lane] = sp[rr];
+      __syncthreads();
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const int64_t k = r0 + rr * 64 + lane;
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) sum += red[q][rr * 64 + lane];
+        if (wave == 0 && k < n) {  // wave 0 alone reads and writes w here
+          const T t = (T)((double)w[k] - sum);
+          w[k] = t;
+          nrm += (double)t * (double)t;
+        }
+      }
+      __syncthreads();  // red is rewritten by the next row block; the block's new w rows are written
+    }
+    if constexpr (MODE == 1) {
+      for (int ch = 0; ch < nch; ++ch) products(ch);
+    } else {
+      for (int off = 32; off > 0; off >>= 1) nrm += __shfl_down(nrm, off, 64);
+      if (lane == 0 && wave == 0) partial[blockIdx.x] = nrm;
+    }
+  }
+  __syncthreads();  // the block's partials are written (each wave waited for its stores)
+  if (threadIdx.x == 0) {
+    __threadfence();  // release: the partials before the ticket
+    last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();  // acquire: the other blocks' partials
+  const int nblk = gridDim.x;
+  if constexpr (MODE == 2) {
+    if (wave == 0) {
+      const double sum = wave_sum(partial, nblk, lane);
+      if (lane == 0) {
+        *out = sum;
+        arnoldi_step(aa, sum);
+        *counter = 0u;
+      }
+    }
+  } else {
+    for (int i = wave; i < ncol; i += NW) {
+      const double sum = wave_sum(partial + (int64_t)i * kMaxBlocks, nblk, lane);
+      if (lane == 0) out[i] = sum;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+  }
+}
+
 // g = (sqrt(*nrm2), 0, ..., 0), m + 1 entries
 __global__ void gmres_init_kernel(const double *__restrict__ nrm2, double *__restrict__ g, int m) {
   for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = i == 0 ? sqrt(*nrm2) : 0.0;
@@ -457,8 +587,8 @@ struct Workspace {
   void *arena = nullptr;      // the allocation holding all of the above
   bool have_diag = false;
   // grid of each Gram-Schmidt kernel: as many blocks as fit on the device at once (no partial
-  // last round), index [FP32][log2(CPW) - 1][MODE]
-  int gs_grid[2][4][3] = {};
+  // last round), index [FP32][log2(CPW) - 1, 4 for the kernel of more than 64 columns][MODE]
+  int gs_grid[2][5][3] = {};
 };
 
 void free_workspace(sbm_ctx *c) {
@@ -533,23 +663,30 @@ static hipError_t multidot(const T *V, int64_t ld, int ncol, const T *w, int64_t
   return hipGetLastError();
 }
 
-template <typename T, int CPW, int MODE>
-static int gs_grid_cap() {
+template <typename K>
+static int grid_cap(K kernel) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
                                               hipSuccess)
     return kMaxBlocks;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gs_kernel<T, CPW, MODE>, kThreads, 0) != hipSuccess)
-    return kMaxBlocks;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess) return kMaxBlocks;
   return std::max(1, std::min(kMaxBlocks, per_cu * cus));
+}
+
+template <typename T, int L>
+static void gs_grid_caps1(int *g) {
+  constexpr int CPW = 2 << L;
+  if constexpr (L == 4) {
+    g[0] = grid_cap(gs_wide_kernel<T, 0>), g[1] = grid_cap(gs_wide_kernel<T, 1>), g[2] = grid_cap(gs_wide_kernel<T, 2>);
+  } else {
+    g[0] = grid_cap(gs_kernel<T, CPW, 0>), g[1] = grid_cap(gs_kernel<T, CPW, 1>), g[2] = grid_cap(gs_kernel<T, CPW, 2>);
+  }
 }
 
 template <typename T>
 static void gs_grid_caps(int (*g)[3]) {
-  g[0][0] = gs_grid_cap<T, 2, 0>(), g[0][1] = gs_grid_cap<T, 2, 1>(), g[0][2] = gs_grid_cap<T, 2, 2>();
-  g[1][0] = gs_grid_cap<T, 4, 0>(), g[1][1] = gs_grid_cap<T, 4, 1>(), g[1][2] = gs_grid_cap<T, 4, 2>();
-  g[2][0] = gs_grid_cap<T, 8, 0>(), g[2][1] = gs_grid_cap<T, 8, 1>(), g[2][2] = gs_grid_cap<T, 8, 2>();
-  g[3][0] = gs_grid_cap<T, 16, 0>(), g[3][1] = gs_grid_cap<T, 16, 1>(), g[3][2] = gs_grid_cap<T, 16, 2>();
+  gs_grid_caps1<T, 0>(g[0]), gs_grid_caps1<T, 1>(g[1]), gs_grid_caps1<T, 2>(g[2]), gs_grid_caps1<T, 3>(g[3]);
+  gs_grid_caps1<T, 4>(g[4]);
 }
 
 template <typename T, int CPW, int MODE>
@@ -572,8 +709,15 @@ static void gs_launch(const Workspace *ws, const T *V, int m1, int ncol, const d
     gs_launch1<T, 4, MODE>(ws, V, m1, ncol, coef, w, n, partial, ticket, out, aa, s);
   else if (ncol <= 32)
     gs_launch1<T, 8, MODE>(ws, V, m1, ncol, coef, w, n, partial, ticket, out, aa, s);
-  else
+  else if (ncol <= 64)
     gs_launch1<T, 16, MODE>(ws, V, m1, ncol, coef, w, n, partial, ticket, out, aa, s);
+  else {
+    const int64_t rows = 128;  // rows per block and step of gs_wide_kernel
+    const int cap = ws->gs_grid[sizeof(T) == 4 ? 1 : 0][4][MODE];
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((n + rows - 1) / rows, cap));
+    hipLaunchKernelGGL((gs_wide_kernel<T, MODE>), dim3(nb), dim3(kThreads), 0, s, V, m1, ncol, coef, w, n, partial,
+                       ticket, out, aa);
+  }
 }
 
 // Arnoldi steps j <= k < j1 of restarted GMRES(m) on the basis V (column k + 1 is formed from
@@ -935,7 +1079,7 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
   hipStream_t s = (hipStream_t)stream;
   const bool cg = mode == SBM_SOLVE_CG_F64 || mode == SBM_SOLVE_CG_IR || mode == SBM_SOLVE_CG_RR;
   // CG needs no Krylov basis: one spare column of it serves as a work vector
-  const int m = cg ? 1 : (restart > 0 ? std::min(restart, 64) : 50);
+  const int m = cg ? 1 : (restart > 0 ? std::min(restart, kMaxRestart) : 50);
   hipError_t e =
       ensure_workspace(h, m, mode == SBM_SOLVE_GMRES_IR || mode == SBM_SOLVE_CG_IR || mode == SBM_SOLVE_CG_RR);
   if (e != hipSuccess) {

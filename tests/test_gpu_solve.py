@@ -173,21 +173,84 @@ def _gmres_reference(A, b, m, rel_tol, max_it):
         x = x + V[:j].T @ y
 
 
-@pytest.mark.parametrize("m,max_it", [(10, 8000), (24, 8000), (10, 37)], ids=["m10", "m24", "m10-cut37"])
-def test_gmres_iterations_match_a_per_step_reference(m, max_it):
+PER_STEP = [
+    ((2, 16, DISK, 1, "cg"), 10, 8000), ((2, 16, DISK, 1, "cg"), 24, 8000), ((2, 16, DISK, 1, "cg"), 10, 37),
+    ((2, 32, DISK, 1, "cg"), 100, 8000),   # one cycle of 98 steps: more than 64 basis columns
+    ((2, 32, DISK, 1, "cg"), 100, 80),     # cut inside that cycle
+    ((2, 16, DISK, 3, "cg"), 150, 3000),   # stagnates with 64 or 100 columns, converges with 150
+]
+
+
+@pytest.mark.parametrize("prob,m,max_it", PER_STEP,
+                         ids=["m10", "m24", "m10-cut37", "m100", "m100-cut80", "q3-m150"])
+def test_gmres_iterations_match_a_per_step_reference(prob, m, max_it):
     """The device GMRES reads its residual estimates back every few steps; its iteration count
-    and final residual must be those of GMRES checking after every step (restart boundaries
-    and a max_it that is not a multiple of the read-back interval included)."""
-    ref, op = _problem(2, 16, DISK, 1, "cg")
+    and final residual must be those of GMRES checking after every step (restart boundaries,
+    restarts longer than 64 columns and a max_it that is not a multiple of the read-back
+    interval included)."""
+    ref, op = _problem(*prob)
     b, bref = _rhs(ref, op)
     A = O.assemble(ref).tocsr()
     _, its_ref, beta_ref = _gmres_reference(A, b.cpu().numpy(), m, 1e-10, max_it)
     x = torch.zeros_like(b)
     info = op.solve(b, x, rel_tol=1e-10, max_it=max_it, mode="gmres", restart=m)
-    assert abs(info["inner_its"] - its_ref) <= 1, (info, its_ref)
+    # long runs over several restarts may shift the step that meets the tolerance slightly
+    assert abs(info["inner_its"] - its_ref) <= max(1, its_ref // 100), (info, its_ref)
     if max_it < 100:
         assert info["inner_its"] == max_it and info["status"] == sbm.SBM_ENOCONV, info
         rel_ref = beta_ref / np.linalg.norm(b.cpu().numpy())
         assert abs(info["rel_residual"] - rel_ref) <= 1e-6 * rel_ref, (info["rel_residual"], rel_ref)
     else:
         assert info["status"] == sbm.SBM_OK, info
+        res = np.linalg.norm(bref - A @ x.cpu().numpy()) / np.linalg.norm(bref)
+        assert res <= 2e-10, res
+
+
+@pytest.mark.parametrize("mode", ["gmres", "gmres_ir"])
+def test_long_restart_at_size_matches_torch_gmres(mode):
+    """GMRES(100) on 274,625 DoFs (3D Q2, 32^3 cells: the Gram-Schmidt kernels sweep several row
+    blocks per workgroup and more than 64 columns), 100 steps from x = 0, against the same
+    GMRES written with torch FP64 vector operations around the operator's own FP64 apply
+    (parity-tested separately).  FP64: residuals agree to 1e-6 relative; FP32 inner GMRES with
+    FP64 refinement: the solution reaches the same residual within a factor of 2 (or 1e-5, the
+    reach of the FP32 inner solve)."""
+    ls = inputs.sphere((0, 0, 0), 0.75)
+    op = sbm.Operator(3, 32, -1.0, 1.0, ls, 2, disc="cg", shift_scale=1.0)
+    n = op.n_dofs
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    b = torch.rand(n, generator=gen, dtype=torch.float64).cuda() - 0.5
+
+    def A(v):
+        out = torch.empty_like(v)
+        op.apply(v, out)
+        return out
+
+    m = 100
+    beta = b.norm().item()
+    V = torch.zeros(m + 1, n, dtype=torch.float64, device="cuda")
+    V[0] = b / beta
+    H = torch.zeros(m + 1, m, dtype=torch.float64)
+    for j in range(m):
+        w = A(V[j])
+        for _ in range(2):
+            c = V[: j + 1] @ w
+            w = w - V[: j + 1].T @ c
+            H[: j + 1, j] += c.cpu()
+        H[j + 1, j] = w.norm().item()
+        V[j + 1] = w / H[j + 1, j].item()
+    e1 = torch.zeros(m + 1, dtype=torch.float64)
+    e1[0] = beta
+    y = torch.linalg.lstsq(H, e1.unsqueeze(1)).solution.squeeze(1)
+    x_ref = V[:m].T @ y.cuda()
+    rel_ref = (b - A(x_ref)).norm().item() / beta
+
+    x = torch.zeros_like(b)
+    info = op.solve(b, x, rel_tol=1e-14, max_it=m, mode=mode, restart=m)
+    assert info["status"] == sbm.SBM_ENOCONV, info
+    rel = (b - A(x)).norm().item() / beta
+    assert abs(rel - info["rel_residual"]) <= 1e-8 * rel, (rel, info)
+    if mode == "gmres":
+        assert info["inner_its"] == m, info
+        assert abs(rel - rel_ref) <= 1e-6 * rel_ref, (rel, rel_ref)
+    else:
+        assert rel <= max(2 * rel_ref, 1e-5), (rel, rel_ref)
