@@ -43,6 +43,12 @@ notes as well):
      active cell times (p+1)^d plus the local index.
   R7 Closest points are exact (sphere, torus, ellipsoid, half-space, sphere union);
      see closest_point().
+  R8 The truncated extension E_m (the Taylor expansion of Sec. 2.1 kept to total order
+     m) expands the same cell polynomial about the surrogate point:
+         E_m u(x~) = sum_{|alpha| <= m} D^alpha u_K(x~) d^alpha / alpha!,
+     in reference coordinates (D_x^alpha d^alpha = D_xi^alpha delta^alpha with
+     delta = xi - xi~).  m = 1 is "values and gradients"; m >= d p is the full
+     extension of R1, since u_K has degree at most p in each coordinate.
 
 Parity pins: see tests/test_oracle_*.py.  Functions without an independent pin are
 marked "parity unpinned" in their docstrings (none at present).
@@ -122,6 +128,50 @@ def lagrange_values(nodes: np.ndarray, x) -> np.ndarray:
         for m in range(n):
             if m != j:
                 out[..., j] *= (x - nodes[m]) / (nodes[j] - nodes[m])
+    return out
+
+
+def lagrange_taylor_terms(nodes: np.ndarray, x0, dlt, m: int) -> np.ndarray:
+    """Terms l_j^(k)(x0) dlt^k / k! of the Taylor expansion of each 1D Lagrange polynomial
+    about x0, for k = 0..m (k > p gives zero).  The derivatives come from the monomial
+    coefficients of l_j (numpy's polyfromroots / polyder).  x0, dlt: arrays of one shape;
+    result shape x0.shape + (m + 1, n)."""
+    P = np.polynomial.polynomial
+    x0 = np.asarray(x0, dtype=np.float64)
+    dlt = np.asarray(dlt, dtype=np.float64)
+    n = len(nodes)
+    out = np.zeros(x0.shape + (m + 1, n))
+    fact = 1.0
+    for k in range(m + 1):
+        if k > 0:
+            fact *= k
+        for j in range(n):
+            others = np.delete(nodes, j)
+            c = P.polyfromroots(others) / np.prod(nodes[j] - others)
+            dk = P.polyder(c, k) if k > 0 else c
+            out[..., k, j] = P.polyval(x0, dk) * dlt ** k / fact
+    return out
+
+
+def basis_taylor_values(nodes: np.ndarray, xi0: np.ndarray, xi: np.ndarray, m: int) -> np.ndarray:
+    """E_m psi_i at each point (reading R8): sum over multi-indices alpha with |alpha| <= m
+    of prod_k l_{i_k}^(alpha_k)(xi0_k) (xi_k - xi0_k)^alpha_k / alpha_k!.
+    xi0, xi: (nq, d); result (nq, n1^d), the truncated counterpart of basis_values(xi)."""
+    xi0 = np.atleast_2d(xi0)
+    xi = np.atleast_2d(xi)
+    d = xi.shape[1]
+    p = len(nodes) - 1
+    mi = local_multi_indices(d, p)
+    km = min(m, p)
+    terms = [lagrange_taylor_terms(nodes, xi0[:, k], xi[:, k] - xi0[:, k], km) for k in range(d)]
+    out = np.zeros((xi.shape[0], mi.shape[0]))
+    for alpha in itertools.product(range(km + 1), repeat=d):
+        if sum(alpha) > m:
+            continue
+        t = np.ones((xi.shape[0], mi.shape[0]))
+        for k in range(d):
+            t *= terms[k][:, alpha[k], :][:, mi[:, k]]
+        out += t
     return out
 
 
@@ -459,6 +509,7 @@ class Problem:
     face_x_true: np.ndarray = field(default=None, repr=False)  # (nf, nq, d)
     face_xi: np.ndarray = field(default=None, repr=False)  # (nf, nq, d) shifted reference coords
     face_w: np.ndarray = field(default=None, repr=False)  # (nq,) reference tangential weights
+    taylor_order: int | None = None  # None: full extension (R1); m >= 0: truncated E_m (R8)
 
     @property
     def n1(self):
@@ -501,8 +552,10 @@ def face_reference_points(d: int, p: int, axis: int, side: int):
     return pts, wts
 
 
-def setup(d, n, lo, hi, levelset, p, disc="cg", gamma=10.0, gamma_dg=10.0, shift_scale=1.0):
-    """Build the surrogate domain, face data and DoF numbering for one problem."""
+def setup(d, n, lo, hi, levelset, p, disc="cg", gamma=10.0, gamma_dg=10.0, shift_scale=1.0,
+          taylor_order=None):
+    """Build the surrogate domain, face data and DoF numbering for one problem.
+    taylor_order: None for the full extension E (R1), m >= 0 for the truncated E_m (R8)."""
     n = tuple(int(v) for v in (n if np.ndim(n) else [n] * d))[:d]
     lo = np.asarray(lo if np.ndim(lo) else [lo] * d, dtype=np.float64)[:d]
     hi = np.asarray(hi if np.ndim(hi) else [hi] * d, dtype=np.float64)[:d]
@@ -581,6 +634,9 @@ def setup(d, n, lo, hi, levelset, p, disc="cg", gamma=10.0, gamma_dg=10.0, shift
     prob.face_x_true = x_true
     prob.face_xi = xi
     prob.face_w = w_face
+    if taylor_order is not None and int(taylor_order) < 0:
+        raise ValueError("taylor_order must be None or >= 0")
+    prob.taylor_order = None if taylor_order is None else int(taylor_order)
     return prob
 
 
@@ -610,7 +666,8 @@ def sbm_face_matrix(prob: Problem, f: int) -> np.ndarray:
 
     with w_q = h^(d-1) * tangential Gauss weights, dn = (2 side - 1)/h d/dxi_axis the
     physical derivative along the outward surrogate normal, and xi_q the shifted
-    reference point (Eq. (1) bilinear form; Alg. 3)."""
+    reference point (Eq. (1) bilinear form; Alg. 3).  With a truncated extension (R8)
+    psi_j(xi_q) is replaced by E_m psi_j, the Taylor expansion about xi~_q of order m."""
     d, h = prob.d, prob.h
     _, a, s = (int(v) for v in prob.sbm_faces[f])
     xt = prob.face_xi_tilde[f]
@@ -619,7 +676,10 @@ def sbm_face_matrix(prob: Problem, f: int) -> np.ndarray:
     sgn = 2.0 * s - 1.0
     V_t = basis_values(prob.nodes, xt)  # psi_i(xi~_q)
     D_t = basis_gradients(prob.nodes, xt)[:, :, a] * (sgn / h)  # dn psi_i(xi~_q)
-    V_s = basis_values(prob.nodes, xs)  # psi_j(xi_q)
+    if prob.taylor_order is None:
+        V_s = basis_values(prob.nodes, xs)  # psi_j(xi_q)
+    else:
+        V_s = basis_taylor_values(prob.nodes, xt, xs, prob.taylor_order)  # E_m psi_j
     sig = prob.sigma_gamma
     nb = V_t.shape[1]
     B = np.zeros((nb, nb))
