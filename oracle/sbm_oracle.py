@@ -133,23 +133,23 @@ def lagrange_values(nodes: np.ndarray, x) -> np.ndarray:
 
 def lagrange_taylor_terms(nodes: np.ndarray, x0, dlt, m: int) -> np.ndarray:
     """Terms l_j^(k)(x0) dlt^k / k! of the Taylor expansion of each 1D Lagrange polynomial
-    about x0, for k = 0..m (k > p gives zero).  The derivatives come from the monomial
-    coefficients of l_j (numpy's polyfromroots / polyder).  x0, dlt: arrays of one shape;
-    result shape x0.shape + (m + 1, n)."""
+    about x0, for k = 0..m (k > p gives zero).  l_j re-expanded about x0 is
+    l_j(x0 + t) = prod_{l != j} (t - (z_l - x0)) / prod_{l != j} (z_j - z_l), whose monomial
+    coefficients (numpy's polyfromroots of the shifted roots) are l_j^(k)(x0) / k!.  (Forming
+    the coefficients about 0 and differentiating loses about 1e-11 relative at p = 8.)
+    x0, dlt: arrays of one shape; result shape x0.shape + (m + 1, n)."""
     P = np.polynomial.polynomial
     x0 = np.asarray(x0, dtype=np.float64)
     dlt = np.asarray(dlt, dtype=np.float64)
     n = len(nodes)
     out = np.zeros(x0.shape + (m + 1, n))
-    fact = 1.0
-    for k in range(m + 1):
-        if k > 0:
-            fact *= k
+    kmax = min(m, n - 1)
+    for idx in np.ndindex(x0.shape):
         for j in range(n):
             others = np.delete(nodes, j)
-            c = P.polyfromroots(others) / np.prod(nodes[j] - others)
-            dk = P.polyder(c, k) if k > 0 else c
-            out[..., k, j] = P.polyval(x0, dk) * dlt ** k / fact
+            c = P.polyfromroots(others - x0[idx]) / np.prod(nodes[j] - others)
+            for k in range(kmax + 1):
+                out[idx + (k, j)] = c[k] * dlt[idx] ** k
     return out
 
 

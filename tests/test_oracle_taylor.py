@@ -103,3 +103,31 @@ def test_taylor_terms_of_one_basis_function_by_hand():
 def test_negative_order_rejected():
     with pytest.raises(ValueError):
         O.setup(2, 4, -1.0, 1.0, DISK, 1, taylor_order=-1)
+
+
+@pytest.mark.parametrize("p", [4, 8])
+def test_taylor_terms_against_exact_rational_arithmetic(p):
+    """The terms from float inputs (GLL nodes, x0, dlt as stored) against the same terms
+    computed exactly with fractions: multiply out prod_{l != j} (x0 - z_l + t dlt) and divide
+    by prod_{l != j} (z_j - z_l).  Relative to the largest term, within 1e-14."""
+    from fractions import Fraction as Fr
+    nodes = O.gll_nodes(p)
+    rng = np.random.default_rng(p)
+    for _ in range(6):
+        x0, dlt = float(rng.uniform(0, 1)), float(rng.uniform(-1.2, 1.2))
+        got = O.lagrange_taylor_terms(nodes, np.array([x0]), np.array([dlt]), p)[0]
+        for j in range(p + 1):
+            others = [Fr(z) for k, z in enumerate(nodes) if k != j]
+            den = Fr(1)
+            for z in others:
+                den *= Fr(nodes[j]) - z
+            poly = [Fr(1)]
+            for z in others:
+                a = Fr(x0) - z
+                nxt = [Fr(0)] * (len(poly) + 1)
+                for k, c in enumerate(poly):
+                    nxt[k] += a * c
+                    nxt[k + 1] += Fr(dlt) * c
+                poly = nxt
+            exact = np.array([float(c / den) for c in poly])
+            assert np.max(np.abs(got[:, j] - exact)) <= 1e-14 * np.max(np.abs(exact))
