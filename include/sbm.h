@@ -156,6 +156,21 @@ sbm_status sbm_layout_stats(sbm_handle h, int64_t *n_bricks, int64_t *n_boundary
 sbm_status sbm_apply_parts(sbm_handle h, const void *u, void *v, int prec, int parts, void *stream);
 
 /*
+ * sbm_set_extension_order -- choose the extension E of the surrogate-face term (Eq. 1) for
+ * every later sbm_apply, sbm_apply_batch, sbm_diagonal and sbm_solve on h.  Sec. 2.1 defines
+ * E by a Taylor expansion of the solution about the surrogate point x~ along the shift
+ * d = x - x~.  m < 0 (the default after sbm_setup): the expansion to all orders, i.e. the face
+ * cell's polynomial evaluated at the shifted point (Sec. 3.3, Alg. 3).  m >= 0: the
+ * expansion kept to total order m, E_m u(x~) = sum over |alpha| <= m of
+ * D^alpha u_K(x~) d^alpha / alpha! (m = 1: value plus gradient; m >= dim * p equals the
+ * default up to rounding).  With m >= 0 the surrogate faces run in a separate kernel that adds
+ * its rows with atomics (results reproducible to rounding, not bitwise), and sbm_apply_parts
+ * returns SBM_EUNSUPPORTED.  Does not touch the device; not synchronised with work already
+ * enqueued on h (call it between, not during, applies).  Errors: EINVAL (NULL handle).
+ */
+sbm_status sbm_set_extension_order(sbm_handle h, int m);
+
+/*
  * sbm_apply_batch -- n independent applies v_i = A_i u_i, enqueued in order on one stream
  * (the kernels of each operator as sbm_apply launches them).  Same argument rules as
  * sbm_apply for every i; stops at the first failing entry and returns its status.

@@ -79,6 +79,7 @@ struct sbm_ctx {
   double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
   double h = 1.0;
   double gamma = 10.0, gamma_dg = 10.0, shift_scale = 1.0;
+  int taylor_m = -1;  // surrogate-face extension: < 0 full (point value at the shifted point), else E_m
   double sigma_gamma = 0.0, sigma_f = 0.0;
   int64_t n_cells = 0, n_dofs = 0, n_sbm = 0, n_int = 0;
   int nq_face = 1;   // (p+1)^(d-1)
@@ -135,6 +136,11 @@ void set_error(const std::string &msg);
 // Launchers (kernels.hip).  All asynchronous on stream.
 hipError_t launch_apply(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s);
 hipError_t launch_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s);
+// The operator of the handle's extension (kernels_taylor.hip): launch_apply / launch_diagonal
+// when the extension is the full one, else the cell term by launch_apply plus the truncated
+// surrogate-face term.  Every apply and diagonal of the library goes through these.
+hipError_t launch_operator(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s);
+hipError_t launch_operator_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s);
 // Brick shape (cells per direction) used by the CG kernel for (dim, p).
 void brick_dims(int dim, int p, int *bx, int *by, int *bz);
 // Vector kernels (vec.hip)

@@ -1112,7 +1112,7 @@ sbm_status sbm_apply(sbm_handle h, const void *u, void *v, int prec, void *strea
     set_error("sbm_apply: prec must be SBM_F64 or SBM_F32");
     return SBM_EINVAL;
   }
-  SBM_HIP_CHECK(launch_apply(h, u, v, prec, SBM_PART_ALL, (hipStream_t)stream));
+  SBM_HIP_CHECK(launch_operator(h, u, v, prec, SBM_PART_ALL, (hipStream_t)stream));
   return SBM_OK;
 }
 
@@ -1123,8 +1123,21 @@ sbm_status sbm_apply_parts(sbm_handle h, const void *u, void *v, int prec, int p
     set_error("sbm_apply_parts: invalid argument");
     return SBM_EINVAL;
   }
+  if (h->taylor_m >= 0) {
+    set_error("sbm_apply_parts: the diagnostic split is for the full extension only");
+    return SBM_EUNSUPPORTED;
+  }
   if (h->n_dofs == 0) return SBM_OK;
   SBM_HIP_CHECK(launch_apply(h, u, v, prec, parts, (hipStream_t)stream));
+  return SBM_OK;
+}
+
+sbm_status sbm_set_extension_order(sbm_handle h, int m) {
+  if (!h) {
+    set_error("sbm_set_extension_order: NULL handle");
+    return SBM_EINVAL;
+  }
+  h->taylor_m = m < 0 ? -1 : m;
   return SBM_OK;
 }
 

@@ -741,7 +741,7 @@ static sbm_status arnoldi_steps(sbm_ctx *c, int prec, T *V, T *vc, T *w, T *z, c
       hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(nb), dim3(kThreads), 0, s, dinv, vc, z, n);
       src = z;
     }
-    SBM_HIP_CHECK(launch_apply(c, src, w, prec, SBM_PART_ALL, s));
+    SBM_HIP_CHECK(launch_operator(c, src, w, prec, SBM_PART_ALL, s));
     // CGS2: h1 = V^T w; w -= V h1, h2 = V^T w; w -= V h2, |w|^2 and the rotation update
     const ArnoldiArgs aa{k, m, h1, h2, H, cs, sn, g, dres, fac};
     gs_launch<T, 0>(ws, V, m1, k + 1, nullptr, w, n, ws->partial, ws->ticket, h1, aa, s);
@@ -779,7 +779,7 @@ static sbm_status gmres_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *V, T *v
   double beta = 0.0;
   while (true) {
     // r = rhs - A x  -> V_0
-    SBM_HIP_CHECK(launch_apply(c, x, w, prec, SBM_PART_ALL, s));
+    SBM_HIP_CHECK(launch_operator(c, x, w, prec, SBM_PART_ALL, s));
     ++*applies;
     hipLaunchKernelGGL(residual_kernel<T>, dim3(nb), dim3(kThreads), 0, s, rhs, w, vc, n);
     SBM_HIP_CHECK(multidot<T>(vc, n, 1, vc, n, ws->partial, hn, s));
@@ -830,7 +830,7 @@ static sbm_status cg_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *r, T *p, T
   const int nb = nblocks(n);
   double *part_pq = ws->partial, *part_rr = ws->partial + kMaxBlocks;
   double *rr = ws->y;
-  SBM_HIP_CHECK(launch_apply(c, x, q, prec, SBM_PART_ALL, s));
+  SBM_HIP_CHECK(launch_operator(c, x, q, prec, SBM_PART_ALL, s));
   ++*applies;
   hipLaunchKernelGGL(cg_init_kernel<T>, dim3(nb), dim3(kThreads), 0, s, rhs, q, r, p, part_rr, n);
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, s, part_rr, nb, 1, rr);
@@ -845,7 +845,7 @@ static sbm_status cg_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *r, T *p, T
       res = std::sqrt(v);
       if (!(res > tol_abs) || !std::isfinite(res) || it >= max_it) break;
     }
-    SBM_HIP_CHECK(launch_apply(c, p, q, prec, SBM_PART_ALL, s));
+    SBM_HIP_CHECK(launch_operator(c, p, q, prec, SBM_PART_ALL, s));
     ++*applies;
     hipLaunchKernelGGL(cg_dot_kernel<T>, dim3(nb), dim3(kThreads), 0, s, p, q, part_pq, n);
     hipLaunchKernelGGL(cg_update_kernel<T>, dim3(nb), dim3(kThreads), 0, s, x, r, p, q, rr + cur, part_pq, nb,
@@ -876,7 +876,7 @@ static sbm_status cg_rr_run(sbm_ctx *c, const double *b, double *x, double tol_a
   double *rr = ws->y;
   // r = b - A64 x in FP64, its square norm into rr[slot] (read back), r32 = (float) r
   auto replace = [&](int slot, double *rn2) -> sbm_status {
-    SBM_HIP_CHECK(launch_apply(c, x, ws->t, SBM_F64, SBM_PART_ALL, s));
+    SBM_HIP_CHECK(launch_operator(c, x, ws->t, SBM_F64, SBM_PART_ALL, s));
     ++*applies64;
     hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
     SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, rr + slot, s));
@@ -906,7 +906,7 @@ static sbm_status cg_rr_run(sbm_ctx *c, const double *b, double *x, double tol_a
         if (!(res > tol_abs) || it >= max_it) break;
       }
     }
-    SBM_HIP_CHECK(launch_apply(c, p, q, SBM_F32, SBM_PART_ALL, s));
+    SBM_HIP_CHECK(launch_operator(c, p, q, SBM_F32, SBM_PART_ALL, s));
     ++*applies32;
     hipLaunchKernelGGL(cg_dot_kernel<float>, dim3(nb), dim3(kThreads), 0, s, p, q, part_pq, n);
     hipLaunchKernelGGL((cg_update_kernel<float, double>), dim3(nb), dim3(kThreads), 0, s, x, r, p, q, rr + cur,
@@ -1050,7 +1050,7 @@ sbm_status sbm_diagonal(sbm_handle h, void *diag, int prec, void *stream) {
     return SBM_EINVAL;
   }
   if (h->n_dofs == 0) return SBM_OK;
-  hipError_t e = launch_diagonal(h, diag, prec, (hipStream_t)stream);
+  hipError_t e = launch_operator_diagonal(h, diag, prec, (hipStream_t)stream);
   if (e == hipErrorNotSupported) {
     set_error("sbm_diagonal: not available for this discretisation");
     return SBM_EUNSUPPORTED;
@@ -1136,7 +1136,7 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
     // FP64 refinement: r = b - A x (FP64), c ~= A32^-1 (r / |r|) by FP32 GMRES, x += |r| c
     int total_its = 0;
     for (int outer = 0;; ++outer) {
-      SBM_HIP_CHECK(launch_apply(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
+      SBM_HIP_CHECK(launch_operator(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
       ++info->applies_f64;
       hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
       SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));
@@ -1184,7 +1184,7 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
     // space, so each inner solve should do as much of the work as FP32 allows.
     int total_its = 0;
     for (int outer = 0;; ++outer) {
-      SBM_HIP_CHECK(launch_apply(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
+      SBM_HIP_CHECK(launch_operator(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
       ++info->applies_f64;
       hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
       SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));  // |r|^2 stays in h[0]
@@ -1213,7 +1213,7 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
     info->inner_its = total_its;
   }
   // final true residual in FP64
-  SBM_HIP_CHECK(launch_apply(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
+  SBM_HIP_CHECK(launch_operator(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
   ++info->applies_f64;
   hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
   SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));

@@ -81,6 +81,7 @@ _lib.sbm_rhs.argtypes = [_P, _P, _P, _P, _P]
 _lib.sbm_solve.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                            _P, ctypes.POINTER(SolveInfo)]
 _lib.sbm_diagonal.argtypes = [_P, _P, ctypes.c_int, _P]
+_lib.sbm_set_extension_order.argtypes = [_P, ctypes.c_int]
 _lib.sbm_footprint_estimate.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                         ctypes.c_int64]
 _lib.sbm_footprint_estimate.restype = ctypes.c_size_t
@@ -170,7 +171,9 @@ class Operator:
     """One SBM operator (sbm_setup handle)."""
 
     def __init__(self, d, n, lo, hi, levelset, p, disc="cg", gamma=10.0, gamma_dg=10.0, shift_scale=1.0,
-                 host_only=False):
+                 host_only=False, taylor_order=None):
+        """taylor_order: None for the full extension (point value at the shifted point), m >= 0
+        for the Taylor expansion kept to total order m (sbm_set_extension_order)."""
         self.d, self.p, self.disc = d, p, disc
         keep = []
         m = _mesh(d, n, lo, hi)
@@ -188,6 +191,15 @@ class Operator:
         self.device_bytes = nbytes.value
         self.nq_face = (p + 1) ** (d - 1)
         self.nb = (p + 1) ** d
+        self.taylor_order = None
+        if taylor_order is not None:
+            self.set_extension_order(taylor_order)
+
+    def set_extension_order(self, m):
+        """sbm_set_extension_order: None or a negative m selects the full extension."""
+        m = -1 if m is None else int(m)
+        _check(_lib.sbm_set_extension_order(self._h, m), "sbm_set_extension_order")
+        self.taylor_order = None if m < 0 else m
 
     @property
     def handle(self):
