@@ -88,56 +88,90 @@ __device__ __forceinline__ int64_t local_dof(int disc_dg, const int32_t *__restr
   return disc_dg ? (int64_t)cell * NB + i : (int64_t)runs[(int64_t)cell * NP + i / N1] + i % N1;
 }
 
+// Slabs of the cell that split a face point's evaluation of E_m u over threads: p+1 where
+// (p+1)^d threads fit in a workgroup, else 1 (one thread takes every slab).
+template <int D, int N1>
+constexpr int taylor_slabs() {
+  return (D == 3 ? N1 * N1 * N1 : N1 * N1) <= kTaylorThreads ? N1 : 1;
+}
+
 // One workgroup per surrogate face (Eq. (1) face terms with E replaced by E_m):
 //   row_i = sum_q w_q [ -(dn u)(x~_q) psi_i(x~_q) - (dn psi_i)(x~_q) E_m u(x~_q)
 //                       + sigma_Gam E_m u(x~_q) psi_i(x~_q) ],
-// added into v.  Phase 1, one thread per face point: the Taylor terms of the three axes,
-// E_m u by contracting the cell values axis by axis with the order sum kept <= m, the normal
-// derivative at x~_q and the face weight.  Phase 2, one thread per local row.  FP64 inside.
+// added into v.  Phase 1, thread (q, slab): the Taylor terms of face point q along the d axes,
+// then its slab's share of E_m u (the cell values contracted axis by axis with the order sum
+// kept <= m) and of the normal derivative at x~_q; the slab shares are added in slab order.
+// Phase 2, one thread per face node: Rv = sum_q psi(x~_q) w_q (sigma E_m u - dn u) and
+// Rg = -sum_q psi(x~_q) w_q E_m u (2s-1)/h over the tangential basis.  Phase 3, one thread
+// per local row: Rv on the face's own nodes plus Rg times the normal derivative of the row's
+// 1D function.  FP64 inside; the 1D tables are staged in LDS.
 template <typename T, int D, int N1>
 __global__ __launch_bounds__(kTaylorThreads) void sbm_face_taylor_kernel(
     int n_faces, int disc_dg, int m, const int32_t *__restrict__ face_cell, const int32_t *__restrict__ face_code,
     const double *__restrict__ face_xi, const int32_t *__restrict__ runs, const T *__restrict__ u, T *__restrict__ v,
     TaylorTab tt, double h, double sigma) {
-  constexpr int NP = D == 3 ? N1 * N1 : N1, NB = NP * N1, P = N1 - 1;
+  constexpr int NP = D == 3 ? N1 * N1 : N1, NB = NP * N1, P = N1 - 1, S = taylor_slabs<D, N1>();
   __shared__ double su[NB];
-  __shared__ double s_eu[NP], s_dnu[NP], s_om[NP];
+  __shared__ double sN[N1 * N1], sDs[N1], sw[N1];
+  __shared__ double pe[S][NP], pd[S][NP];  // slab shares of E_m u and of the normal derivative
+  __shared__ double sA[NP], sB[NP], sRv[NP], sRg[NP];
   const int f = blockIdx.x;
   if (f >= n_faces) return;
   const int cell = face_cell[f], code = face_code[f], a = code >> 1, s = code & 1;
   const double sgn = s ? 1.0 : -1.0;
   for (int i = threadIdx.x; i < NB; i += blockDim.x) su[i] = (double)u[local_dof<D, N1>(disc_dg, runs, cell, i)];
+  for (int i = threadIdx.x; i < N1 * N1; i += blockDim.x) sN[i] = tt.N[i];
+  if (threadIdx.x < N1) {
+    sDs[threadIdx.x] = s ? tt.D1[threadIdx.x] : tt.D0[threadIdx.x];
+    sw[threadIdx.x] = tt.w[threadIdx.x];
+  }
   __syncthreads();
-  for (int q = threadIdx.x; q < NP; q += blockDim.x) {
+  // tangential axes of the face, lower one first (face point q = qb + N1 qc)
+  const int tb = a == 0 ? 1 : 0, tc = a == 2 ? 1 : 2;
+  for (int t = threadIdx.x; t < NP * S; t += blockDim.x) {
+    const int q = t % NP, slab = t / NP;
+    const int qb = q % N1, qc = D == 3 ? q / N1 : 0;
     double x0[D], dl[D];
     surrogate_point<D, N1>(tt, a, s, q, x0);
 #pragma unroll
     for (int k = 0; k < D; ++k) dl[k] = face_xi[((int64_t)f * NP + q) * D + k] - x0[k];
-    // c[k][i][j]: order-j Taylor term of basis function i along axis k
-    double c[D][N1][N1];
+    // c[k][i][j]: order-j Taylor term of basis function i along axis k < d-1 (the last axis
+    // is the slab axis: only the slab's own function is needed, cl below)
+    double c[D - 1][N1][N1];
 #pragma unroll
-    for (int k = 0; k < D; ++k)
+    for (int k = 0; k < D - 1; ++k)
 #pragma unroll
       for (int i = 0; i < N1; ++i) taylor_terms<N1>(tt, i, x0[k], dl[k], c[k][i]);
-    double eu = 0.0;
-    if constexpr (D == 3) {
-#pragma unroll
-      for (int i2 = 0; i2 < N1; ++i2) {
-        double b[N1][N1];  // b[j0][j1] = sum_{i0,i1} c0[i0][j0] c1[i1][j1] u[i0,i1,i2]
+    // factor of local index i along axis k in the normal derivative at x~_q
+    auto dfac = [&](int k, int i) {
+      return k == a ? sDs[i] : sN[(k == tb ? qb : qc) * N1 + i];
+    };
+    double eu = 0.0, dn = 0.0;
+    for (int il = slab; il < N1; il += S) {  // slab il: last local index (i2 in 3D, i1 in 2D)
+      double cl[N1];
+      taylor_terms<N1>(tt, il, x0[D - 1], dl[D - 1], cl);
+      if constexpr (D == 3) {
+        double b[N1][N1];  // b[j0][j1] = sum_{i0,i1} c0[i0][j0] c1[i1][j1] u[i0,i1,il]
 #pragma unroll
         for (int j0 = 0; j0 < N1; ++j0)
 #pragma unroll
           for (int j1 = 0; j1 < N1; ++j1) b[j0][j1] = 0.0;
+        const double f2 = dfac(2, il);
 #pragma unroll
         for (int i1 = 0; i1 < N1; ++i1) {
           double r[N1];
+          double g = 0.0;
+          const double f1 = dfac(1, i1);
 #pragma unroll
-          for (int j0 = 0; j0 < N1; ++j0) {
-            double acc = 0.0;
+          for (int j0 = 0; j0 < N1; ++j0) r[j0] = 0.0;
 #pragma unroll
-            for (int i0 = 0; i0 < N1; ++i0) acc += c[0][i0][j0] * su[i0 + N1 * i1 + NP * i2];
-            r[j0] = acc;
+          for (int i0 = 0; i0 < N1; ++i0) {
+            const double uv = su[i0 + N1 * i1 + NP * il];
+            g += dfac(0, i0) * uv;
+#pragma unroll
+            for (int j0 = 0; j0 < N1; ++j0) r[j0] += c[0][i0][j0] * uv;
           }
+          dn += f2 * f1 * g;
 #pragma unroll
           for (int j0 = 0; j0 < N1; ++j0)
 #pragma unroll
@@ -149,66 +183,60 @@ __global__ __launch_bounds__(kTaylorThreads) void sbm_face_taylor_kernel(
           for (int j1 = 0; j1 < N1; ++j1)
 #pragma unroll
             for (int j2 = 0; j2 < N1; ++j2)
-              if (j0 + j1 + j2 <= m) eu += c[2][i2][j2] * b[j0][j1];
-      }
-    } else {
-#pragma unroll
-      for (int i1 = 0; i1 < N1; ++i1) {
+              if (j0 + j1 + j2 <= m) eu += cl[j2] * b[j0][j1];
+      } else {
+        double g = 0.0;
+        const double f1 = dfac(1, il);
 #pragma unroll
         for (int j0 = 0; j0 < N1; ++j0) {
           double acc = 0.0;
 #pragma unroll
-          for (int i0 = 0; i0 < N1; ++i0) acc += c[0][i0][j0] * su[i0 + N1 * i1];
+          for (int i0 = 0; i0 < N1; ++i0) acc += c[0][i0][j0] * su[i0 + N1 * il];
 #pragma unroll
           for (int j1 = 0; j1 < N1; ++j1)
-            if (j0 + j1 <= m) eu += c[1][i1][j1] * acc;
+            if (j0 + j1 <= m) eu += cl[j1] * acc;
         }
+#pragma unroll
+        for (int i0 = 0; i0 < N1; ++i0) g += dfac(0, i0) * su[i0 + N1 * il];
+        dn += f1 * g;
       }
     }
-    // normal derivative at x~_q: (2s-1)/h l'_{i_a}(s) times the tangential interpolation
-    double dnu = 0.0;
-    for (int i = 0; i < NB; ++i) {
-      const int ik[3] = {i % N1, (i / N1) % N1, D == 3 ? i / (N1 * N1) : 0};
-      double tang = 1.0;
-      int qq = q;
+    pe[slab][q] = eu;
+    pd[slab][q] = dn;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < NP; q += blockDim.x) {
+    double eu = 0.0, dn = 0.0;
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        if (k == a) continue;
-        tang *= tt.N[(qq % N1) * N1 + ik[k]];
-        qq /= N1;
-      }
-      dnu += (s ? tt.D1[ik[a]] : tt.D0[ik[a]]) * tang * su[i];
+    for (int k = 0; k < S; ++k) {
+      eu += pe[k][q];
+      dn += pd[k][q];
     }
-    double om = 1.0;
-    int qq = q;
-#pragma unroll
-    for (int k = 0; k < D - 1; ++k) {
-      om *= tt.w[qq % N1] * h;
-      qq /= N1;
+    dn *= sgn / h;
+    double om = sw[q % N1] * h;
+    if constexpr (D == 3) om *= sw[q / N1] * h;
+    sA[q] = om * (sigma * eu - dn);  // tested against psi(x~_q)
+    sB[q] = -om * eu * sgn / h;      // tested against the normal derivative's 1D factor
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < NP; t += blockDim.x) {
+    const int jb = t % N1, jc = D == 3 ? t / N1 : 0;
+    double rv = 0.0, rg = 0.0;
+    for (int q = 0; q < NP; ++q) {
+      const double tang = sN[(q % N1) * N1 + jb] * (D == 3 ? sN[(q / N1) * N1 + jc] : 1.0);
+      rv += tang * sA[q];
+      rg += tang * sB[q];
     }
-    s_eu[q] = eu;
-    s_dnu[q] = sgn / h * dnu;
-    s_om[q] = om;
+    sRv[t] = rv;
+    sRg[t] = rg;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < NB; i += blockDim.x) {
     const int ik[3] = {i % N1, (i / N1) % N1, D == 3 ? i / (N1 * N1) : 0};
-    const double ds = s ? tt.D1[ik[a]] : tt.D0[ik[a]];
-    const bool on_face = ik[a] == s * P;
-    double row = 0.0;
-    for (int q = 0; q < NP; ++q) {
-      double tang = 1.0;
-      int qq = q;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        if (k == a) continue;
-        tang *= tt.N[(qq % N1) * N1 + ik[k]];
-        qq /= N1;
-      }
-      const double vt = on_face ? tang : 0.0;  // psi_i(x~_q)
-      const double dn = sgn / h * ds * tang;   // d psi_i / dn~ (x~_q)
-      row += s_om[q] * (-s_dnu[q] * vt - dn * s_eu[q] + sigma * s_eu[q] * vt);
-    }
+    const int ia = a == 0 ? ik[0] : (a == 1 ? ik[1] : ik[2]);
+    const int ib = tb == 0 ? ik[0] : ik[1];
+    const int node = ib + (D == 3 ? N1 * ik[tc] : 0);
+    const double row = (ia == s * P ? sRv[node] : 0.0) + sDs[ia] * sRg[node];
     unsafeAtomicAdd(v + local_dof<D, N1>(disc_dg, runs, cell, i), (T)row);
   }
 }
@@ -278,9 +306,9 @@ template <typename T, int D, int N1>
 hipError_t taylor_faces(const sbm_ctx *c, const T *u, T *v, hipStream_t s) {
   const int nf = (int)c->n_sbm;
   if (nf == 0) return hipSuccess;
-  // one thread per local row in the second phase (at least one wavefront)
-  constexpr int NB = (D == 3 ? N1 * N1 : N1) * N1;
-  constexpr int NT = NB < 64 ? 64 : (NB > kTaylorThreads ? kTaylorThreads : (NB + 63) / 64 * 64);
+  // one thread per (face point, slab) in the first phase (at least one wavefront)
+  constexpr int NW = (D == 3 ? N1 * N1 : N1) * taylor_slabs<D, N1>();
+  constexpr int NT = NW < 64 ? 64 : (NW > kTaylorThreads ? kTaylorThreads : (NW + 63) / 64 * 64);
   hipLaunchKernelGGL((sbm_face_taylor_kernel<T, D, N1>), dim3(nf), dim3(NT), 0, s, nf,
                      c->disc == SBM_DG, c->taylor_m, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, v,
                      make_taylor_tab(c->rules), c->h, c->sigma_gamma);
