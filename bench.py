@@ -144,6 +144,53 @@ def configs_section(torch, sbm, inputs, steps, graph_batch):
     return out
 
 
+TAYLOR_SOLVES = [
+    # (name, workload, overrides, max_it): shifted GMRES(64) to 1e-10, default extension vs E_1
+    ("sphere3d_q2_n32", "sphere3d_q4", {"p": 2, "n": 32}, 1500),
+    ("sphere3d_q4", "sphere3d_q4", {}, 600),
+    ("torus3d_dg_q3", "torus3d_dg", {}, 1000),
+]
+
+
+def taylor_section(torch, sbm, inputs, op, vecs, steps, graph_batch):
+    """The truncated Taylor extension E_m (sbm_set_extension_order) on the headline operator:
+    apply time for m = 1 and m = p against the default extension (FP64 and FP32), then
+    shifted GMRES(64) solves with E_1 against the default (status, iterations, residual
+    reached, seconds)."""
+    out = {"workload": "sphere3d_q4", "apply": {}, "solves": []}
+    for m in (None, 1, op.p):
+        op.set_extension_order(m)
+        rec = {}
+        for prec, (u, v) in vecs.items():
+            for _ in range(3):
+                op.apply(u, v)
+            t, _, n = time_launches(torch, lambda: op.apply(u, v), steps, graph_batch)
+            rec[prec] = {"ms_per_apply": t * 1e3, "dofs_per_s": op.n_dofs / t, "applies": n}
+        out["apply"]["default" if m is None else f"m{m}"] = rec
+        print(f"# taylor apply m={m}: f64 {rec['f64']['ms_per_apply']:.4f} ms, f32 {rec['f32']['ms_per_apply']:.4f} ms",
+              file=sys.stderr, flush=True)
+    op.set_extension_order(None)
+    for name, wname, over, max_it in TAYLOR_SOLVES:
+        w = inputs.workload(wname, **over)
+        sop = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"])
+        u_fn, f_fn = inputs.manufactured(w["d"])
+        cq, bp = sop.rhs_points()
+        b = torch.empty(sop.n_dofs, dtype=torch.float64, device="cuda")
+        sop.rhs(f_fn(cq.reshape(-1, w["d"])), u_fn(bp.reshape(-1, w["d"])), b)
+        rec = {"case": name, "n_dofs": sop.n_dofs, "max_it": max_it}
+        for m in (None, 1):
+            sop.set_extension_order(m)
+            x = torch.zeros_like(b)
+            info = sop.solve(b, x, rel_tol=1e-10, max_it=max_it, mode="gmres", restart=64)
+            rec["default" if m is None else f"m{m}"] = {
+                "status": sbm.status_name(info["status"]), "krylov_its": info["inner_its"],
+                "rel_residual": info["rel_residual"], "seconds": info["seconds"]}
+        print(f"# taylor solve {name}: {rec}", file=sys.stderr, flush=True)
+        out["solves"].append(rec)
+        sop.close()
+    return out
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The brute-force C oracle (OpenMP) on this host, on the same workload: as many full
     applies as fit in about budget_s seconds (at least one)."""
@@ -275,6 +322,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' applies")
     ap.add_argument("--solve", action="store_true", help="also time the FP64 and FP32+IR solves")
+    ap.add_argument("--no-taylor", action="store_true", help="skip the truncated-Taylor extension section")
     ap.add_argument("--profile-run", action="store_true", help="few eager applies + copies (counter runs)")
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-max-it", type=int, default=100)
@@ -362,6 +410,9 @@ def main():
                  "brick_kernel_frac": res["f32"]["b_brick"] / res["f32"]["t_brick"] / 1e9 / HBM_PEAK_GBS},
         "setup_s": t_setup,
     }
+    if not args.no_taylor:
+        out["taylor_extension"] = taylor_section(torch, sbm, inputs, op, {"f64": (u64, v64), "f32": (u32, v32)},
+                                                 min(args.steps, 200), gb)
     if not args.no_configs:
         out["other_configs"] = configs_section(torch, sbm, inputs, min(args.steps, 200), gb)
     if args.solve:
