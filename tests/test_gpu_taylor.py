@@ -120,3 +120,24 @@ def test_full_order_equals_default_at_size(dtype):
     print(f"  rel diff {err:.3e}", flush=True)
     assert err <= TOL[dtype], err
     op.close()
+
+
+def test_extension_order_accuracy_on_the_disk():
+    """2D disk Q2 on 32^2 cells, GMRES(128) to 1e-11: the L2 error against the manufactured
+    solution (oracle quadrature) grows as the extension is truncated (full < E_2 < E_1), and
+    the first-order extension still converges to a useful solution."""
+    u_fn, f_fn = inputs.manufactured(2)
+    errs = {}
+    for m in (None, 2, 1):
+        ref = O.setup(2, 32, -1.0, 1.0, DISK, 2, taylor_order=m)
+        op = sbm.Operator(2, 32, -1.0, 1.0, DISK, 2, taylor_order=m)
+        cq, bp = op.rhs_points()
+        b = torch.empty(op.n_dofs, dtype=torch.float64, device="cuda")
+        op.rhs(f_fn(cq.reshape(-1, 2)), u_fn(bp.reshape(-1, 2)), b)
+        x = torch.zeros_like(b)
+        info = op.solve(b, x, rel_tol=1e-11, max_it=20000, mode="gmres", restart=128)
+        assert info["status"] == sbm.SBM_OK, (m, info)
+        errs[m] = O.l2_error(ref, x.cpu().numpy(), u_fn)
+        print(f"  m={m}: its={info['inner_its']} L2 error {errs[m]:.3e}", flush=True)
+        op.close()
+    assert errs[None] < errs[2] < errs[1] < 1e-2, errs
