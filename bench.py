@@ -275,13 +275,14 @@ def serve_section(n_req, max_it, rate, slots, budget_gb):
     """Request stream (p in 2..6, 16^3..64^3 cells, ellipsoid or 8-ball union, CG or SIPG,
     FP32 GMRES inside FP64 refinement to 1e-10 with an iteration cap).  First closed loop (all
     requests queued at t = 0) for the capacity mu in solves/s, then open loop with Poisson
-    arrivals at 0.7 mu (rate > 0 overrides the open-loop rate)."""
+    arrivals at 0.7 mu (rate > 0 overrides the open-loop rate); then the same requests in closed
+    loop with the first-order extension E_1 and a 10x iteration cap."""
     from paper_2507_17053_amd import inputs
     from paper_2507_17053_amd.serving import Server
 
-    def one(reqs, time_scale):
+    def one(reqs, time_scale, cap=max_it):
         srv = Server(budget_bytes=int(budget_gb * (1 << 30)), slots=slots, mode="gmres_ir", rel_tol=1e-10,
-                     max_it=max_it, restart=32)
+                     max_it=cap, restart=32)
         s = srv.run(reqs, time_scale=time_scale)
         res = list(s["results"].values())
         rr = sorted(r["info"].get("rel_residual", float("nan")) for r in res)
@@ -294,8 +295,13 @@ def serve_section(n_req, max_it, rate, slots, budget_gb):
     mu = closed["solves_per_s"]
     lam = rate if rate > 0 else 0.7 * mu
     opened = one(inputs.serving_requests(n_req, seed=2, rate=lam), 1.0)
+    # the same requests with the first-order extension E_1 (Krylov methods converge on it),
+    # closed loop with a 10x larger iteration cap
+    first = one([dict(r, taylor_order=1) for r in inputs.serving_requests(n_req, seed=2, rate=1.0)], 0.0,
+                cap=10 * max_it)
     return {"closed_loop": closed, "open_loop": dict(opened, arrival_rate_per_s=lam), "slots": slots,
-            "hbm_budget_GB": budget_gb, "krylov_cap": max_it}
+            "hbm_budget_GB": budget_gb, "krylov_cap": max_it,
+            "closed_loop_first_order_extension": dict(first, krylov_cap=10 * max_it)}
 
 
 def profile_run(torch, sbm, inputs, n=5):

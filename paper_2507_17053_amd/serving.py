@@ -120,9 +120,13 @@ def percentile(xs, q):
 class Server:
     """Runs a request stream on the GPU through the library (see module docstring)."""
 
-    def __init__(self, budget_bytes, slots=4, mode="gmres_ir", rel_tol=1e-10, max_it=400, restart=32):
+    def __init__(self, budget_bytes, slots=4, mode="gmres_ir", rel_tol=1e-10, max_it=400, restart=32,
+                 taylor_order=None):
+        """taylor_order: extension of the surrogate-face term for requests that do not name one
+        (None: the full extension; m >= 0: the Taylor expansion kept to order m)."""
         self.sched = Scheduler(budget_bytes, slots)
         self.mode, self.rel_tol, self.max_it, self.restart = mode, rel_tol, max_it, restart
+        self.taylor_order = taylor_order
         self.lock = threading.Lock()
         self.done = threading.Condition(self.lock)
         self.results = {}
@@ -141,7 +145,8 @@ class Server:
         import torch
 
         from . import inputs, sbm
-        op = sbm.Operator(req["d"], req["n"], req["lo"], req["hi"], req["levelset"], req["p"], disc=req["disc"])
+        op = sbm.Operator(req["d"], req["n"], req["lo"], req["hi"], req["levelset"], req["p"], disc=req["disc"],
+                          taylor_order=req.get("taylor_order", self.taylor_order))
         try:
             u_fn, f_fn = inputs.manufactured(req["d"])
             cq, bp = op.rhs_points()

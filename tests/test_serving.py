@@ -97,3 +97,23 @@ def test_each_result_same_alone_and_in_the_mix():
         rel = np.linalg.norm(x_mix - x_alone) / np.linalg.norm(x_alone)
         assert rel <= bound, (r["id"], rel, bound)
     torch.cuda.synchronize()
+
+
+@pytest.mark.gpu
+def test_request_extension_order_reaches_the_operator():
+    """A request naming taylor_order = 1 is solved with the first-order extension: its
+    solution solves the oracle's E_1 system (and not the full-extension one)."""
+    pytest.importorskip("torch")
+    from paper_2507_17053_amd.serving import Server
+    from oracle import sbm_oracle as O
+
+    r = dict(SOLVABLE[0], id=0, arrival=0.0, taylor_order=1)
+    srv = Server(budget_bytes=8 << 30, slots=1, mode="gmres", rel_tol=1e-10, max_it=8000, restart=64)
+    x, info = srv.solve_one(r)
+    assert info["status"] == 0, info
+    u_fn, f_fn = inputs.manufactured(r["d"])
+    for m, ok in ((1, True), (None, False)):
+        ref = O.setup(r["d"], r["n"], r["lo"], r["hi"], r["levelset"], r["p"], disc=r["disc"], taylor_order=m)
+        b = O.rhs(ref, f_fn, u_fn)
+        res = np.linalg.norm(b - O.assemble(ref) @ x) / np.linalg.norm(b)
+        assert (res <= 2e-10) == ok, (m, res)
