@@ -13,8 +13,6 @@
 // term (and the DG interior faces) through the default kernels with the surrogate faces left
 // out, then adds the faces' rows from sbm_face_taylor_kernel.  The diagonal is the default one
 // plus a correction of its surrogate-face term.
-#include <algorithm>
-
 #include "sbm_internal.h"
 
 namespace sbm {
