@@ -175,13 +175,23 @@ __global__ __launch_bounds__(kTaylorThreads) void sbm_face_taylor_kernel(
 #pragma unroll
             for (int j1 = 0; j1 < N1; ++j1) b[j0][j1] += c[1][i1][j1] * r[j0];
         }
+        // sum over j0 + j1 + j2 <= m of cl[j2] b[j0][j1]: b summed along its anti-diagonals
+        // (j0 + j1 = k) first, then each order j2 takes the diagonals k <= m - j2
+        double bd[2 * N1 - 1];
+#pragma unroll
+        for (int k = 0; k < 2 * N1 - 1; ++k) bd[k] = 0.0;
 #pragma unroll
         for (int j0 = 0; j0 < N1; ++j0)
 #pragma unroll
-          for (int j1 = 0; j1 < N1; ++j1)
+          for (int j1 = 0; j1 < N1; ++j1) bd[j0 + j1] += b[j0][j1];
 #pragma unroll
-            for (int j2 = 0; j2 < N1; ++j2)
-              if (j0 + j1 + j2 <= m) eu += cl[j2] * b[j0][j1];
+        for (int j2 = 0; j2 < N1; ++j2) {
+          double t = 0.0;
+#pragma unroll
+          for (int k = 0; k < 2 * N1 - 1; ++k)
+            if (k + j2 <= m) t += bd[k];
+          eu += cl[j2] * t;
+        }
       } else {
         double g = 0.0;
         const double f1 = dfac(1, il);
