@@ -86,3 +86,19 @@ def test_library_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(sbm._lib, name), name
     assert set(sbm.EXPORTED) <= declared
+
+
+def test_extension_order_host_logic():
+    """sbm_set_extension_order needs no device: NULL handle -> EINVAL; any order is accepted
+    and a negative one restores the full extension; the diagnostic split then refuses."""
+    assert sbm._lib.sbm_set_extension_order(None, 1) == sbm.SBM_EINVAL
+    op = sbm.Operator(3, 4, -1.0, 1.0, inputs.sphere((0, 0, 0), 0.8), 2, host_only=True, taylor_order=1)
+    assert op.taylor_order == 1
+    op.set_extension_order(None)
+    assert op.taylor_order is None
+    assert sbm._lib.sbm_set_extension_order(op.handle, -5) == sbm.SBM_OK
+    assert sbm._lib.sbm_set_extension_order(op.handle, 3) == sbm.SBM_OK
+    # host-only handles refuse device work before the order is looked at
+    st = sbm._lib.sbm_apply_parts(op.handle, ctypes.c_void_p(8), ctypes.c_void_p(16), 0, sbm.PART_ALL, None)
+    assert st == sbm.SBM_EINVAL
+    op.close()
