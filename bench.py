@@ -304,10 +304,11 @@ def serve_section(n_req, max_it, rate, slots, budget_gb):
             "closed_loop_first_order_extension": dict(first, krylov_cap=10 * max_it)}
 
 
-def profile_run(torch, sbm, inputs, n=5):
-    """A few eager FP64 applies and plain device copies of n_dofs doubles, for counter runs."""
+def profile_run(torch, sbm, inputs, n=5, order=None):
+    """A few eager FP64 applies and plain device copies of n_dofs doubles, for counter runs
+    (order: extension order set on the operator first; None keeps the full extension)."""
     w = inputs.workload("sphere3d_q4")
-    op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"])
+    op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"], taylor_order=order)
     u = torch.from_numpy(inputs.uniform_vector(op.n_dofs, seed=0)).to("cuda")
     v = torch.empty_like(u)
     for _ in range(n):
@@ -315,7 +316,8 @@ def profile_run(torch, sbm, inputs, n=5):
     for _ in range(n):
         v.copy_(u)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_run": True, "n_dofs": op.n_dofs, "copy_bytes_each_way": 8 * op.n_dofs}))
+    print(json.dumps({"profile_run": True, "n_dofs": op.n_dofs, "copy_bytes_each_way": 8 * op.n_dofs,
+                      "taylor_order": order}))
 
 
 def main():
@@ -330,6 +332,8 @@ def main():
     ap.add_argument("--solve", action="store_true", help="also time the FP64 and FP32+IR solves")
     ap.add_argument("--no-taylor", action="store_true", help="skip the truncated-Taylor extension section")
     ap.add_argument("--profile-run", action="store_true", help="few eager applies + copies (counter runs)")
+    ap.add_argument("--profile-order", type=int, default=None,
+                    help="with --profile-run: extension order of the operator (default: full extension)")
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-max-it", type=int, default=100)
     ap.add_argument("--serve-rate", type=float, default=0.0,
@@ -344,7 +348,7 @@ def main():
     from paper_2507_17053_amd import inputs, sbm
 
     if args.profile_run:
-        profile_run(torch, sbm, inputs)
+        profile_run(torch, sbm, inputs, order=args.profile_order)
         return
 
     w = inputs.workload(args.workload)
