@@ -44,8 +44,9 @@ TaylorTab make_taylor_tab(const Rules1D &r) {
 }
 
 // Taylor terms of the 1D basis function j about x0: c[k] = l_j^(k)(x0) dlt^k / k!, k = 0..p.
-// They are the coefficients of t^k in l_j(x0 + t dlt) = cinv_j prod_{l != j} (x0 - z_l + t dlt),
-// formed by multiplying out the p linear factors.
+// They are the coefficients of t^k in l_j(x0 + t dlt) = cinv_j prod_{l != j} (x0 - z_l + t dlt):
+// the p linear factors (x0 - z_l) + s are multiplied out in s = t dlt (one multiply-add per
+// coefficient and factor), and coefficient k is then scaled by cinv_j dlt^k.
 template <int N1>
 __device__ __forceinline__ void taylor_terms(const TaylorTab &tt, int j, double x0, double dlt, double (&c)[N1]) {
   double poly[N1];
@@ -56,11 +57,15 @@ __device__ __forceinline__ void taylor_terms(const TaylorTab &tt, int j, double 
     if (l == j) continue;
     const double a = x0 - tt.z[l];
 #pragma unroll
-    for (int k = N1 - 1; k >= 1; --k) poly[k] = a * poly[k] + dlt * poly[k - 1];
+    for (int k = N1 - 1; k >= 1; --k) poly[k] = a * poly[k] + poly[k - 1];
     poly[0] *= a;
   }
+  double scale = tt.cinv[j];
 #pragma unroll
-  for (int k = 0; k < N1; ++k) c[k] = tt.cinv[j] * poly[k];
+  for (int k = 0; k < N1; ++k) {
+    c[k] = scale * poly[k];
+    scale *= dlt;
+  }
 }
 
 // Reference coordinates of the surrogate point of face point q on face (a, s): xi~_a = s, the
