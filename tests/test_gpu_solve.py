@@ -211,11 +211,14 @@ def test_long_restart_at_size_matches_torch_gmres(mode):
     """GMRES(100) on 274,625 DoFs (3D Q2, 32^3 cells: the Gram-Schmidt kernels sweep several row
     blocks per workgroup and more than 64 columns), 100 steps from x = 0, against the same
     GMRES written with torch FP64 vector operations around the operator's own FP64 apply
-    (parity-tested separately).  FP64: residuals agree to 1e-6 relative; FP32 inner GMRES with
+    (parity-tested separately).  The operator is the symmetric positive definite limit
+    (shift 0), on which 100 steps reduce the residual steadily: on the shifted operator a
+    random right-hand side leaves it near 0.99, where its last digits follow the rounding of
+    the reference's own reductions.  FP64: residuals agree to 1e-6 relative; FP32 inner GMRES with
     FP64 refinement: the solution reaches the same residual within a factor of 2 (or 1e-5, the
     reach of the FP32 inner solve)."""
     ls = inputs.sphere((0, 0, 0), 0.75)
-    op = sbm.Operator(3, 32, -1.0, 1.0, ls, 2, disc="cg", shift_scale=1.0)
+    op = sbm.Operator(3, 32, -1.0, 1.0, ls, 2, disc="cg", shift_scale=0.0)
     n = op.n_dofs
     gen = torch.Generator(device="cpu").manual_seed(7)
     b = torch.rand(n, generator=gen, dtype=torch.float64).cuda() - 0.5
@@ -248,6 +251,7 @@ def test_long_restart_at_size_matches_torch_gmres(mode):
     info = op.solve(b, x, rel_tol=1e-14, max_it=m, mode=mode, restart=m)
     assert info["status"] == sbm.SBM_ENOCONV, info
     rel = (b - A(x)).norm().item() / beta
+    print(f"  {mode}: device {rel:.6e}, reference {rel_ref:.6e}", flush=True)
     assert abs(rel - info["rel_residual"]) <= 1e-8 * rel, (rel, info)
     if mode == "gmres":
         assert info["inner_its"] == m, info
