@@ -57,7 +57,14 @@ enum {
   SBM_LS_ELLIPSOID = 1,    /* axis-aligned, semi_axes[k], centred at centre */
   SBM_LS_TORUS = 2,        /* 3D only: axis z through centre, major radius R, minor r */
   SBM_LS_SPHERE_UNION = 3, /* union of n_spheres balls (centres n x 3 row-major, radii) */
-  SBM_LS_HALFSPACE = 4     /* normal . x - offset with a unit normal */
+  SBM_LS_HALFSPACE = 4,    /* normal . x - offset with a unit normal */
+  SBM_LS_CALLBACK = 5      /* user phi and grad phi (fields phi, grad, user below); closest
+                              points by the level-set Newton iteration of Sec. 4.4,
+                              x <- x - phi(x) grad phi(x) / |grad phi(x)|^2 from the surrogate
+                              point, until |phi| <= 1e-14 or 50 steps (the point reached is
+                              on the boundary, and is the closest one when phi is a distance
+                              function or its gradient lines are straight).  The callbacks are
+                              called from the thread that calls sbm_setup only, during it. */
 };
 
 /* Uniform Cartesian background mesh: n[k] cells on [lo[k], hi[k]], k < dim. */
@@ -79,6 +86,10 @@ typedef struct {
   int n_spheres;          /* SBM_LS_SPHERE_UNION: the arrays below are copied by sbm_setup */
   const double *centres;  /* host, n_spheres x 3 (the third entry is ignored in 2D) */
   const double *radii;    /* host, n_spheres */
+  /* SBM_LS_CALLBACK: phi(x, user) and grad(x, g, user) for a point x of dim coordinates */
+  double (*phi)(const double *x, void *user);
+  void (*grad)(const double *x, double *g, void *user);
+  void *user;
 } sbm_levelset;
 
 typedef struct {

@@ -252,6 +252,8 @@ def phi(ls: dict, x: np.ndarray) -> np.ndarray:
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     kind = ls["kind"]
     d = x.shape[1]
+    if kind == "callback":
+        return np.asarray(ls["phi"](x), dtype=np.float64)
     if kind == "sphere":
         c = np.asarray(ls["centre"], dtype=np.float64)[:d]
         s = np.zeros(x.shape[0])
@@ -477,7 +479,32 @@ def closest_point(ls: dict, x: np.ndarray) -> np.ndarray:
     if kind == "sphere_union":
         return _closest_union(np.asarray(ls["centres"], dtype=np.float64)[:, :d],
                               np.asarray(ls["radii"], dtype=np.float64), x)
+    if kind == "callback":
+        return _closest_newton(ls, x)
     raise ValueError(f"unknown level-set kind {kind!r}")
+
+
+def _closest_newton(ls: dict, x: np.ndarray) -> np.ndarray:
+    """Level-set Newton projection (Sec. 4.4: the projection is a Newton solve on the level
+    set): per point, y <- y - phi(y) grad phi(y) / |grad phi(y)|^2 from y = x, stopping when
+    |phi(y)| <= 1e-14; a point that needs more than 50 steps is an error.  This reaches a
+    point of the boundary; it is the closest one for a distance function or, more generally,
+    when the gradient lines are straight (spheres, tori given by their distance)."""
+    y = np.array(x, dtype=np.float64)
+    todo = np.ones(y.shape[0], dtype=bool)
+    for it in range(51):
+        ph = np.asarray(ls["phi"](y[todo]), dtype=np.float64)
+        done = np.abs(ph) <= 1e-14
+        idx = np.flatnonzero(todo)
+        todo[idx[done]] = False
+        if not todo.any():
+            return y
+        if it == 50:
+            break
+        g = np.asarray(ls["grad"](y[todo]), dtype=np.float64)
+        g2 = np.sum(g * g, axis=1)
+        y[todo] -= ph[~done][:, None] * g / g2[:, None]
+    raise ValueError("level-set Newton projection did not reach |phi| <= 1e-14 in 50 steps")
 
 
 # ----------------------------------------------------------------------------------------

@@ -38,6 +38,9 @@ struct LevelSet {
   double normal[3] = {1, 0, 0};
   std::vector<double> cs;  // n x 3
   std::vector<double> rs;
+  double (*cb_phi)(const double *, void *) = nullptr;  // SBM_LS_CALLBACK
+  void (*cb_grad)(const double *, double *, void *) = nullptr;
+  void *cb_user = nullptr;
   double phi(const double *x) const;
   void closest(const double *x, double *out) const;  // exact closest point on {phi = 0}
 };

@@ -188,8 +188,38 @@ double LevelSet::phi(const double *x) const {
       }
       return best;
     }
+    case SBM_LS_CALLBACK: {
+      double xx[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < d; ++k) xx[k] = x[k];
+      return cb_phi(xx, cb_user);
+    }
   }
   return 0.0;
+}
+
+// Level-set Newton projection onto {phi = 0} (the projection of Sec. 4.4): from x, repeat
+// x <- x - phi(x) grad phi(x) / |grad phi(x)|^2 until |phi| <= 1e-14 or 50 steps.  Returns false
+// if the tolerance was not met or the gradient vanished.
+static bool closest_newton(const LevelSet &L, const double *x, double *out) {
+  const int d = L.dim;
+  double y[3] = {0.0, 0.0, 0.0}, g[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < d; ++k) y[k] = x[k];
+  for (int it = 0; it <= 50; ++it) {
+    const double ph = L.cb_phi(y, L.cb_user);
+    if (!std::isfinite(ph)) break;
+    if (std::fabs(ph) <= 1e-14) {
+      for (int k = 0; k < d; ++k) out[k] = y[k];
+      return true;
+    }
+    if (it == 50) break;
+    L.cb_grad(y, g, L.cb_user);
+    double g2 = 0.0;
+    for (int k = 0; k < d; ++k) g2 += g[k] * g[k];
+    if (!(g2 > 0.0) || !std::isfinite(g2)) break;
+    for (int k = 0; k < d; ++k) y[k] -= ph * g[k] / g2;
+  }
+  for (int k = 0; k < d; ++k) out[k] = std::numeric_limits<double>::quiet_NaN();
+  return false;
 }
 
 // Ellipsoid: x_k = a_k^2 y_k / (a_k^2 + t) with t the largest root of
@@ -432,6 +462,9 @@ void LevelSet::closest(const double *x, double *out) const {
     }
     case SBM_LS_SPHERE_UNION:
       closest_union(cs, rs, d, x, out);
+      return;
+    case SBM_LS_CALLBACK:
+      closest_newton(*this, x, out);
       return;
   }
 }
@@ -814,6 +847,15 @@ static sbm_status host_setup(sbm_ctx *c, const sbm_mesh *mesh, const sbm_levelse
         }
       }
       break;
+    case SBM_LS_CALLBACK:
+      if (!ls->phi || !ls->grad) {
+        set_error("sbm_setup: callback level set needs phi and grad");
+        return SBM_EINVAL;
+      }
+      L.cb_phi = ls->phi;
+      L.cb_grad = ls->grad;
+      L.cb_user = ls->user;
+      break;
     default:
       set_error("sbm_setup: unknown level-set kind");
       return SBM_EINVAL;
@@ -914,7 +956,8 @@ static sbm_status host_setup(sbm_ctx *c, const sbm_mesh *mesh, const sbm_levelse
     }
     return ok;
   };
-  const int64_t nthr = std::max<int64_t>(
+  // user callbacks are called from this thread only
+  const int64_t nthr = L.kind == SBM_LS_CALLBACK ? 1 : std::max<int64_t>(
       1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 16, (nf * np) / 4096}));
   bool proj_ok = true;
   if (nthr <= 1) {

@@ -42,6 +42,12 @@ def sphere_union(seed: int = 1, n: int = 8, r_range=(0.15, 0.35), c_range=(-0.6,
     return {"kind": "sphere_union", "centres": centres.numpy().copy(), "radii": radii.numpy().copy()}
 
 
+def callback(phi, grad, dim):
+    """Level set given by functions of an (N, dim) array of points: phi(X) -> (N,) values and
+    grad(X) -> (N, dim) gradients (the library calls them one point at a time)."""
+    return {"kind": "callback", "phi": phi, "grad": grad, "dim": int(dim)}
+
+
 def sphere(centre, radius):
     return {"kind": "sphere", "centre": list(map(float, centre)), "radius": float(radius)}
 

@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 SBM_OK, SBM_EINVAL, SBM_ENOMEM, SBM_EHIP, SBM_ENOCONV, SBM_EUNSUPPORTED = range(6)
 SBM_CG, SBM_DG = 0, 1
 SBM_F64, SBM_F32 = 0, 1
-LS_KINDS = {"sphere": 0, "ellipsoid": 1, "torus": 2, "sphere_union": 3, "halfspace": 4}
+LS_KINDS = {"sphere": 0, "ellipsoid": 1, "torus": 2, "sphere_union": 3, "halfspace": 4, "callback": 5}
 SOLVE_MODES = {"gmres": 0, "gmres_ir": 1, "cg": 2, "cg_ir": 3, "cg_rr": 4}
 _STATUS = {0: "SBM_OK", 1: "SBM_EINVAL", 2: "SBM_ENOMEM", 3: "SBM_EHIP", 4: "SBM_ENOCONV",
            5: "SBM_EUNSUPPORTED"}
@@ -46,7 +46,11 @@ class _LevelSet(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("centre", ctypes.c_double * 3), ("radius", ctypes.c_double),
                 ("semi_axes", ctypes.c_double * 3), ("R", ctypes.c_double), ("r", ctypes.c_double),
                 ("normal", ctypes.c_double * 3), ("offset", ctypes.c_double),
-                ("n_spheres", ctypes.c_int), ("centres", ctypes.c_void_p), ("radii", ctypes.c_void_p)]
+                ("n_spheres", ctypes.c_int), ("centres", ctypes.c_void_p), ("radii", ctypes.c_void_p),
+                ("phi", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("user", ctypes.c_void_p)]
+
+_PHI_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+_GRAD_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
 
 
 class _Options(ctypes.Structure):
@@ -141,6 +145,27 @@ def _levelset(ls: dict, keep: list):
         s.n_spheres = int(rs.shape[0])
         s.centres = c3.ctypes.data
         s.radii = rs.ctypes.data
+    if ls["kind"] == "callback":
+        d, fphi, fgrad = ls["dim"], ls["phi"], ls["grad"]
+
+        def phi_c(x, _user):
+            return float(fphi(np.array([[x[k] for k in range(d)]], dtype=np.float64))[0])
+
+        def grad_c(x, g, _user):
+            gv = fgrad(np.array([[x[k] for k in range(d)]], dtype=np.float64))[0]
+            for k in range(d):
+                g[k] = float(gv[k])
+
+        # a missing function stays NULL (sbm_setup rejects it); the C side calls them during
+        # sbm_setup only
+        if fphi is not None:
+            cp = _PHI_FN(phi_c)
+            keep.append(cp)
+            s.phi = ctypes.cast(cp, ctypes.c_void_p)
+        if fgrad is not None:
+            cg = _GRAD_FN(grad_c)
+            keep.append(cg)
+            s.grad = ctypes.cast(cg, ctypes.c_void_p)
     return s
 
 

@@ -215,3 +215,33 @@ def test_footprint_estimate_bounds_setup_allocation():
         op = sbm.Operator(d, n, -1.0, 1.0, ls, p, disc=disc)
         est = sbm.footprint_estimate(d, n, -1.0, 1.0, p, disc, op.n_cells, op.n_sbm_faces)
         assert est >= op.device_bytes, (d, n, p, disc, est, op.device_bytes)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("case", ["disk2d-squared", "torus3d-distance"])
+def test_apply_with_callback_level_set_matches_oracle(case, dtype):
+    """A level set given by user functions (closest points by the level-set Newton iteration)
+    end to end: setup, apply, compared with the oracle built from the same functions."""
+    if case == "disk2d-squared":
+        c = np.array([0.05, -0.03])
+        ls = inputs.callback(lambda X: np.sum((X - c) ** 2, axis=1) - 0.49, lambda X: 2.0 * (X - c), 2)
+        d, n, p, disc = 2, 16, 3, "cg"
+    else:
+        def phi(X):
+            rho = np.sqrt(X[:, 0] ** 2 + X[:, 1] ** 2)
+            return np.sqrt((rho - 0.55) ** 2 + X[:, 2] ** 2) - 0.4
+
+        def grad(X):
+            rho = np.sqrt(X[:, 0] ** 2 + X[:, 1] ** 2)
+            q = np.sqrt((rho - 0.55) ** 2 + X[:, 2] ** 2)
+            f = (rho - 0.55) / (rho * q)
+            return np.stack([f * X[:, 0], f * X[:, 1], X[:, 2] / q], axis=1)
+
+        ls = inputs.callback(phi, grad, 3)
+        d, n, p, disc = 3, 8, 3, "dg"
+    ref = O.setup(d, n, -1.0, 1.0, ls, p, disc=disc)
+    u = inputs.uniform_vector(ref.n_dofs, seed=0)
+    op = sbm.Operator(d, n, -1.0, 1.0, ls, p, disc=disc)
+    assert op.n_dofs == ref.n_dofs
+    err = _rel(_gpu_apply(op, u, dtype), O.assemble(ref) @ u)
+    assert err <= TOL[dtype], err

@@ -119,3 +119,46 @@ def test_active_cells_lie_inside_convex_domain():
     for c in prob.cells:
         x = prob.lo + prob.h * (c + pts)
         assert np.all(O.phi(ls, x) < 1e-15)
+
+
+def test_callback_newton_projection_is_exact_for_radial_level_sets():
+    """The level-set Newton projection (callback kind) moves along grad phi; for a sphere given
+    as |x - c| - r or |x - c|^2 - r^2, and a torus given by its distance, the gradient lines
+    are straight, so it must land on the exact closest point."""
+    rng = np.random.default_rng(5)
+    c = np.array([0.1, -0.2, 0.05])
+    X = rng.uniform(-1, 1, (200, 3))
+    exact = O.closest_point({"kind": "sphere", "centre": list(c), "radius": 0.6}, X)
+    for phi, grad in [(lambda Y: np.linalg.norm(Y - c, axis=1) - 0.6,
+                       lambda Y: (Y - c) / np.linalg.norm(Y - c, axis=1)[:, None]),
+                      (lambda Y: np.sum((Y - c) ** 2, axis=1) - 0.36, lambda Y: 2.0 * (Y - c))]:
+        got = O.closest_point(inputs.callback(phi, grad, 3), X)
+        assert np.abs(got - exact).max() <= 1e-12
+
+    def tphi(Y):
+        rho = np.sqrt(Y[:, 0] ** 2 + Y[:, 1] ** 2)
+        return np.sqrt((rho - 0.6) ** 2 + Y[:, 2] ** 2) - 0.25
+
+    def tgrad(Y):
+        rho = np.sqrt(Y[:, 0] ** 2 + Y[:, 1] ** 2)
+        q = np.sqrt((rho - 0.6) ** 2 + Y[:, 2] ** 2)
+        f = (rho - 0.6) / (rho * q)
+        return np.stack([f * Y[:, 0], f * Y[:, 1], Y[:, 2] / q], axis=1)
+
+    Xt = X[np.sqrt(X[:, 0] ** 2 + X[:, 1] ** 2) > 0.05]
+    exact_t = O.closest_point(inputs.torus(0.6, 0.25), Xt)
+    got_t = O.closest_point(inputs.callback(tphi, tgrad, 3), Xt)
+    assert np.abs(got_t - exact_t).max() <= 1e-12
+
+
+def test_callback_newton_projection_lands_on_the_boundary_or_fails():
+    """Implicit ellipse: every projected point has |phi| <= 1e-14; a level set without zeros
+    (phi = |x|^2 + 1) makes the projection raise."""
+    a = np.array([0.8, 0.45])
+    ls = inputs.callback(lambda Y: np.sum((Y / a) ** 2, axis=1) - 1.0, lambda Y: 2.0 * Y / a ** 2, 2)
+    X = np.random.default_rng(6).uniform(-1, 1, (100, 2))
+    got = O.closest_point(ls, X)
+    assert np.abs(ls["phi"](got)).max() <= 1e-14
+    none = inputs.callback(lambda Y: np.sum(Y ** 2, axis=1) + 1.0, lambda Y: 2.0 * Y, 2)
+    with pytest.raises(ValueError):
+        O.closest_point(none, X[:3])

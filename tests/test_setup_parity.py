@@ -25,6 +25,41 @@ CASES = [
 ]
 
 
+def _cb_disk_squared():
+    """Disk r = 0.7 at (0.05, -0.03) as phi = |x - c|^2 - r^2 (not a distance function)."""
+    c = np.array([0.05, -0.03])
+    return inputs.callback(lambda X: np.sum((X - c) ** 2, axis=1) - 0.49, lambda X: 2.0 * (X - c), 2)
+
+
+def _cb_torus_distance():
+    """Torus R = 0.6, r = 0.3 (axis z) by its distance function."""
+    def phi(X):
+        rho = np.sqrt(X[:, 0] ** 2 + X[:, 1] ** 2)
+        return np.sqrt((rho - 0.6) ** 2 + X[:, 2] ** 2) - 0.3
+
+    def grad(X):
+        rho = np.sqrt(X[:, 0] ** 2 + X[:, 1] ** 2)
+        q = np.sqrt((rho - 0.6) ** 2 + X[:, 2] ** 2)
+        f = (rho - 0.6) / (rho * q)
+        return np.stack([f * X[:, 0], f * X[:, 1], X[:, 2] / q], axis=1)
+
+    return inputs.callback(phi, grad, 3)
+
+
+def _cb_ellipse_implicit():
+    """Ellipse semi-axes (0.8, 0.45) as (x/a)^2 + (y/b)^2 - 1: the Newton projection reaches
+    the boundary but not the closest point; both sides follow the same iteration."""
+    a = np.array([0.8, 0.45])
+    return inputs.callback(lambda X: np.sum((X / a) ** 2, axis=1) - 1.0, lambda X: 2.0 * X / a ** 2, 2)
+
+
+CASES += [
+    (2, 16, _cb_disk_squared(), 2, "cg"),
+    (3, 10, _cb_torus_distance(), 3, "dg"),
+    (2, 12, _cb_ellipse_implicit(), 3, "cg"),
+]
+
+
 @pytest.mark.parametrize("d,n,ls,p,disc", CASES)
 def test_setup_matches_oracle(d, n, ls, p, disc):
     ref = O.setup(d, n, -1.0, 1.0, ls, p, disc=disc)
@@ -102,3 +137,10 @@ def test_extension_order_host_logic():
     st = sbm._lib.sbm_apply_parts(op.handle, ctypes.c_void_p(8), ctypes.c_void_p(16), 0, sbm.PART_ALL, None)
     assert st == sbm.SBM_EINVAL
     op.close()
+
+
+def test_callback_without_gradient_rejected():
+    ls = _cb_disk_squared()
+    bad = dict(ls, grad=None)
+    with pytest.raises(sbm.SbmError, match="phi and grad"):
+        sbm.Operator(2, 8, -1.0, 1.0, bad, 1, host_only=True)
