@@ -43,26 +43,28 @@ TaylorTab make_taylor_tab(const Rules1D &r) {
   return t;
 }
 
-// Taylor terms of the 1D basis function j about x0: c[k] = l_j^(k)(x0) dlt^k / k!, k = 0..p.
-// They are the coefficients of t^k in l_j(x0 + t dlt) = cinv_j prod_{l != j} (x0 - z_l + t dlt):
-// the p linear factors (x0 - z_l) + s are multiplied out in s = t dlt (one multiply-add per
-// coefficient and factor), and coefficient k is then scaled by cinv_j dlt^k.
-template <int N1>
-__device__ __forceinline__ void taylor_terms(const TaylorTab &tt, int j, double x0, double dlt, double (&c)[N1]) {
-  double poly[N1];
+// Taylor terms of the 1D basis function j about x0: c[k] = l_j^(k)(x0) dlt^k / k!, k < JN
+// (JN <= p+1 orders kept).  They are the coefficients of t^k in
+// l_j(x0 + t dlt) = cinv_j prod_{l != j} (x0 - z_l + t dlt): the p linear factors (x0 - z_l) + s
+// are multiplied out in s = t dlt (one multiply-add per coefficient and factor; coefficient k
+// depends on coefficients <= k only, so dropping the higher ones is exact), and coefficient k is
+// then scaled by cinv_j dlt^k.
+template <int N1, int JN = N1>
+__device__ __forceinline__ void taylor_terms(const TaylorTab &tt, int j, double x0, double dlt, double (&c)[JN]) {
+  double poly[JN];
 #pragma unroll
-  for (int k = 0; k < N1; ++k) poly[k] = k == 0 ? 1.0 : 0.0;
+  for (int k = 0; k < JN; ++k) poly[k] = k == 0 ? 1.0 : 0.0;
 #pragma unroll
   for (int l = 0; l < N1; ++l) {
     if (l == j) continue;
     const double a = x0 - tt.z[l];
 #pragma unroll
-    for (int k = N1 - 1; k >= 1; --k) poly[k] = a * poly[k] + poly[k - 1];
+    for (int k = JN - 1; k >= 1; --k) poly[k] = a * poly[k] + poly[k - 1];
     poly[0] *= a;
   }
   double scale = tt.cinv[j];
 #pragma unroll
-  for (int k = 0; k < N1; ++k) {
+  for (int k = 0; k < JN; ++k) {
     c[k] = scale * poly[k];
     scale *= dlt;
   }
@@ -107,8 +109,9 @@ constexpr int taylor_slabs() {
 // Phase 2, one thread per face node: Rv = sum_q psi(x~_q) w_q (sigma E_m u - dn u) and
 // Rg = -sum_q psi(x~_q) w_q E_m u (2s-1)/h over the tangential basis.  Phase 3, one thread
 // per local row: Rv on the face's own nodes plus Rg times the normal derivative of the row's
-// 1D function.  FP64 inside; the 1D tables are staged in LDS.
-template <typename T, int D, int N1>
+// 1D function.  FP64 inside; the 1D tables are staged in LDS.  JN: Taylor orders carried per
+// axis (p+1, or 2 for a launch with m <= 1).
+template <typename T, int D, int N1, int JN>
 __global__ __launch_bounds__(kTaylorThreads) void sbm_face_taylor_kernel(
     int n_faces, int disc_dg, int m, const int32_t *__restrict__ face_cell, const int32_t *__restrict__ face_code,
     const double *__restrict__ face_xi, const int32_t *__restrict__ runs, const T *__restrict__ u, T *__restrict__ v,
@@ -140,60 +143,60 @@ __global__ __launch_bounds__(kTaylorThreads) void sbm_face_taylor_kernel(
     for (int k = 0; k < D; ++k) dl[k] = face_xi[((int64_t)f * NP + q) * D + k] - x0[k];
     // c[k][i][j]: order-j Taylor term of basis function i along axis k < d-1 (the last axis
     // is the slab axis: only the slab's own function is needed, cl below)
-    double c[D - 1][N1][N1];
+    double c[D - 1][N1][JN];
 #pragma unroll
     for (int k = 0; k < D - 1; ++k)
 #pragma unroll
-      for (int i = 0; i < N1; ++i) taylor_terms<N1>(tt, i, x0[k], dl[k], c[k][i]);
+      for (int i = 0; i < N1; ++i) taylor_terms<N1, JN>(tt, i, x0[k], dl[k], c[k][i]);
     // factor of local index i along axis k in the normal derivative at x~_q
     auto dfac = [&](int k, int i) {
       return k == a ? sDs[i] : sN[(k == tb ? qb : qc) * N1 + i];
     };
     double eu = 0.0, dn = 0.0;
     for (int il = slab; il < N1; il += S) {  // slab il: last local index (i2 in 3D, i1 in 2D)
-      double cl[N1];
-      taylor_terms<N1>(tt, il, x0[D - 1], dl[D - 1], cl);
+      double cl[JN];
+      taylor_terms<N1, JN>(tt, il, x0[D - 1], dl[D - 1], cl);
       if constexpr (D == 3) {
-        double b[N1][N1];  // b[j0][j1] = sum_{i0,i1} c0[i0][j0] c1[i1][j1] u[i0,i1,il]
+        double b[JN][JN];  // b[j0][j1] = sum_{i0,i1} c0[i0][j0] c1[i1][j1] u[i0,i1,il]
 #pragma unroll
-        for (int j0 = 0; j0 < N1; ++j0)
+        for (int j0 = 0; j0 < JN; ++j0)
 #pragma unroll
-          for (int j1 = 0; j1 < N1; ++j1) b[j0][j1] = 0.0;
+          for (int j1 = 0; j1 < JN; ++j1) b[j0][j1] = 0.0;
         const double f2 = dfac(2, il);
 #pragma unroll
         for (int i1 = 0; i1 < N1; ++i1) {
-          double r[N1];
+          double r[JN];
           double g = 0.0;
           const double f1 = dfac(1, i1);
 #pragma unroll
-          for (int j0 = 0; j0 < N1; ++j0) r[j0] = 0.0;
+          for (int j0 = 0; j0 < JN; ++j0) r[j0] = 0.0;
 #pragma unroll
           for (int i0 = 0; i0 < N1; ++i0) {
             const double uv = su[i0 + N1 * i1 + NP * il];
             g += dfac(0, i0) * uv;
 #pragma unroll
-            for (int j0 = 0; j0 < N1; ++j0) r[j0] += c[0][i0][j0] * uv;
+            for (int j0 = 0; j0 < JN; ++j0) r[j0] += c[0][i0][j0] * uv;
           }
           dn += f2 * f1 * g;
 #pragma unroll
-          for (int j0 = 0; j0 < N1; ++j0)
+          for (int j0 = 0; j0 < JN; ++j0)
 #pragma unroll
-            for (int j1 = 0; j1 < N1; ++j1) b[j0][j1] += c[1][i1][j1] * r[j0];
+            for (int j1 = 0; j1 < JN; ++j1) b[j0][j1] += c[1][i1][j1] * r[j0];
         }
         // sum over j0 + j1 + j2 <= m of cl[j2] b[j0][j1]: b summed along its anti-diagonals
         // (j0 + j1 = k) first, then each order j2 takes the diagonals k <= m - j2
-        double bd[2 * N1 - 1];
+        double bd[2 * JN - 1];
 #pragma unroll
-        for (int k = 0; k < 2 * N1 - 1; ++k) bd[k] = 0.0;
+        for (int k = 0; k < 2 * JN - 1; ++k) bd[k] = 0.0;
 #pragma unroll
-        for (int j0 = 0; j0 < N1; ++j0)
+        for (int j0 = 0; j0 < JN; ++j0)
 #pragma unroll
-          for (int j1 = 0; j1 < N1; ++j1) bd[j0 + j1] += b[j0][j1];
+          for (int j1 = 0; j1 < JN; ++j1) bd[j0 + j1] += b[j0][j1];
 #pragma unroll
-        for (int j2 = 0; j2 < N1; ++j2) {
+        for (int j2 = 0; j2 < JN; ++j2) {
           double t = 0.0;
 #pragma unroll
-          for (int k = 0; k < 2 * N1 - 1; ++k)
+          for (int k = 0; k < 2 * JN - 1; ++k)
             if (k + j2 <= m) t += bd[k];
           eu += cl[j2] * t;
         }
@@ -201,12 +204,12 @@ __global__ __launch_bounds__(kTaylorThreads) void sbm_face_taylor_kernel(
         double g = 0.0;
         const double f1 = dfac(1, il);
 #pragma unroll
-        for (int j0 = 0; j0 < N1; ++j0) {
+        for (int j0 = 0; j0 < JN; ++j0) {
           double acc = 0.0;
 #pragma unroll
           for (int i0 = 0; i0 < N1; ++i0) acc += c[0][i0][j0] * su[i0 + N1 * il];
 #pragma unroll
-          for (int j1 = 0; j1 < N1; ++j1)
+          for (int j1 = 0; j1 < JN; ++j1)
             if (j0 + j1 <= m) eu += cl[j1] * acc;
         }
 #pragma unroll
@@ -322,9 +325,15 @@ hipError_t taylor_faces(const sbm_ctx *c, const T *u, T *v, hipStream_t s) {
   // one thread per (face point, slab) in the first phase (at least one wavefront)
   constexpr int NW = (D == 3 ? N1 * N1 : N1) * taylor_slabs<D, N1>();
   constexpr int NT = NW < 64 ? 64 : (NW > kTaylorThreads ? kTaylorThreads : (NW + 63) / 64 * 64);
-  hipLaunchKernelGGL((sbm_face_taylor_kernel<T, D, N1>), dim3(nf), dim3(NT), 0, s, nf,
-                     c->disc == SBM_DG, c->taylor_m, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, v,
-                     make_taylor_tab(c->rules), c->h, c->sigma_gamma);
+  // orders 0 and 1 only for m <= 1 (the first-order extension), all p+1 otherwise
+  if (c->taylor_m <= 1)
+    hipLaunchKernelGGL((sbm_face_taylor_kernel<T, D, N1, 2>), dim3(nf), dim3(NT), 0, s, nf, c->disc == SBM_DG,
+                       c->taylor_m, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, v,
+                       make_taylor_tab(c->rules), c->h, c->sigma_gamma);
+  else
+    hipLaunchKernelGGL((sbm_face_taylor_kernel<T, D, N1, N1>), dim3(nf), dim3(NT), 0, s, nf, c->disc == SBM_DG,
+                       c->taylor_m, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, v,
+                       make_taylor_tab(c->rules), c->h, c->sigma_gamma);
   return hipGetLastError();
 }
 
