@@ -118,7 +118,9 @@ enum { SBM_SETUP_HOST_ONLY = 1 };
 sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int disc,
                      const sbm_options *opts, sbm_handle *out);
 
-/* Counts and the device bytes the handle holds.  Any output pointer may be NULL. */
+/* Counts and the device bytes the handle holds: its operator data and scratch from
+ * sbm_setup, plus the solver workspace once a solve has allocated it.  Any output pointer
+ * may be NULL. */
 sbm_status sbm_info(sbm_handle h, int64_t *n_dofs, int64_t *n_cells, int64_t *n_sbm_faces,
                     int64_t *n_interior_faces, size_t *device_bytes);
 
@@ -132,9 +134,11 @@ const char *sbm_last_error(void);
  * sbm_apply -- v = A u (Sec. 3.5 workflow: cell loop, then surrogate faces; for DG the
  * interior faces are evaluated cell by cell).  u and v are device vectors of n_dofs
  * entries of the precision prec (SBM_F64: double, SBM_F32: float); v is overwritten and
- * must not alias u.  Asynchronous on stream; never synchronises.  A CG handle owns a
- * scratch buffer used by every apply, so applies of the same handle must be ordered on
- * one stream (applies of different handles may run concurrently).
+ * must not alias u.  Asynchronous on stream; never synchronises.  A handle owns a scratch
+ * buffer used by every apply (surrogate-face results; for CG also the brick-boundary
+ * partial sums), so applies of the same handle must be ordered on one stream (applies of
+ * different handles may run concurrently).  With the default extension the result is
+ * bitwise reproducible: every sum is taken in a fixed order (no atomics).
  * Errors: EINVAL (NULL handle/pointer, u == v, bad prec), EHIP (launch failure).
  */
 sbm_status sbm_apply(sbm_handle h, const void *u, void *v, int prec, void *stream);
@@ -142,10 +146,10 @@ sbm_status sbm_apply(sbm_handle h, const void *u, void *v, int prec, void *strea
 /*
  * sbm_apply_parts -- diagnostic split of sbm_apply: v = (selected parts of A) u, with
  * SBM_PART_CELLS the cell term (for DG including the interior faces) and
- * SBM_PART_SBM_FACES the surrogate-boundary faces; SBM_PART_ALL gives sbm_apply.  For DG,
- * SBM_PART_SBM_FACES alone adds the face term into v instead of overwriting it.  It exists
- * to time the cell and surrogate-face work separately (the share of time spent in
- * surrogate faces, Sec. 4.3).  Same argument rules as sbm_apply.  Asynchronous.
+ * SBM_PART_SBM_FACES the surrogate-boundary faces; SBM_PART_ALL gives sbm_apply.  v is
+ * overwritten in every case.  It exists to time the cell and surrogate-face work separately
+ * (the share of time spent in surrogate faces, Sec. 4.3) and to check each term on its own.
+ * Same argument rules as sbm_apply.  Asynchronous.
  */
 enum { SBM_PART_CELLS = 2, SBM_PART_SBM_FACES = 4, SBM_PART_ALL = 6,
        SBM_PART_NO_ASSEMBLY = 8,  /* CG: skip the final sum over brick-boundary DoFs (those
@@ -257,7 +261,9 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
  */
 sbm_status sbm_diagonal(sbm_handle h, void *diag, int prec, void *stream);
 
-/* Device bytes sbm_setup would allocate for this problem (host-side estimate, no setup). */
+/* Upper bound of the device bytes sbm_setup allocates for a problem on this mesh with at
+ * most n_cells_hint active cells and n_faces_hint surrogate faces (host-side, no setup; the
+ * solver workspace is not included).  0 for invalid arguments. */
 size_t sbm_footprint_estimate(const sbm_mesh *mesh, int p, int disc, int64_t n_cells_hint,
                               int64_t n_faces_hint);
 

@@ -73,16 +73,22 @@ class NativeApply:
         gx, gw = O.gauss_rule(prob.p + 1)
         self.gx, self.gw = np.ascontiguousarray(gx), np.ascontiguousarray(gw)
 
-    def __call__(self, u: np.ndarray, n_threads: int = 0) -> np.ndarray:
+    def __call__(self, u: np.ndarray, n_threads: int = 0, parts=("cell", "sbm", "dg")) -> np.ndarray:
+        """v = A u with the terms named in parts: "cell" (Laplace cell term), "sbm"
+        (surrogate-boundary faces), "dg" (SIPG interior faces, DG only).  A part left out is
+        handed to the C code as zero entities (no faces, or a zero cell matrix)."""
         lib = _load()
         pr = self.prob
         u = np.ascontiguousarray(u, dtype=np.float64)
         v = np.empty(pr.n_dofs)
         ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        cm = self.cell_matrix if "cell" in parts else np.zeros_like(self.cell_matrix)
+        n_sbm = self.sbm_cell.shape[0] if "sbm" in parts else 0
+        n_int = self.int_k1.shape[0] if "dg" in parts else 0
         rc = lib.oracle_apply(pr.d, pr.p, pr.n_dofs, self.cell_dofs.shape[0], ptr(self.cell_dofs),
-                              ptr(self.cell_matrix), self.sbm_cell.shape[0], ptr(self.sbm_cell),
+                              ptr(cm), n_sbm, ptr(self.sbm_cell),
                               ptr(self.sbm_axis), ptr(self.sbm_side), ptr(self.sbm_xi),
-                              self.int_k1.shape[0], ptr(self.int_k1), ptr(self.int_k2),
+                              n_int, ptr(self.int_k1), ptr(self.int_k2),
                               ptr(self.int_axis), ptr(self.gll), ptr(self.gx), ptr(self.gw),
                               pr.h, pr.sigma_gamma, pr.sigma_f, ptr(u), ptr(v), int(n_threads))
         if rc != 0:

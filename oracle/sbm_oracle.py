@@ -845,51 +845,3 @@ def solve_direct(A: sp.csr_matrix, b: np.ndarray) -> np.ndarray:
     """Sparse direct solve (tiny meshes only)."""
     import scipy.sparse.linalg as spla
     return spla.spsolve(A.tocsc(), b)
-
-
-def krylov_cg(A, b, tol=1e-12, max_it=100000):
-    """Textbook conjugate gradients from x0 = 0 (used to check which Krylov method the
-    nonsymmetric operator tolerates).  Returns (x, iterations, relative residual)."""
-    x = np.zeros_like(b)
-    r = b.copy()
-    pdir = r.copy()
-    rr = r @ r
-    nb = np.sqrt(b @ b)
-    for it in range(1, max_it + 1):
-        Ap = A @ pdir
-        alpha = rr / (pdir @ Ap)
-        x += alpha * pdir
-        r -= alpha * Ap
-        rr_new = r @ r
-        if np.sqrt(rr_new) <= tol * nb:
-            return x, it, np.sqrt(rr_new) / nb
-        pdir = r + (rr_new / rr) * pdir
-        rr = rr_new
-    return x, max_it, np.sqrt(rr) / nb
-
-
-def krylov_bicgstab(A, b, tol=1e-12, max_it=100000):
-    """Textbook BiCGStab (van der Vorst) from x0 = 0.  Returns (x, iterations, rel. residual)."""
-    x = np.zeros_like(b)
-    r = b.copy()
-    r0 = r.copy()
-    rho = alpha = omega = 1.0
-    v = np.zeros_like(b)
-    pdir = np.zeros_like(b)
-    nb = np.sqrt(b @ b)
-    for it in range(1, max_it + 1):
-        rho_new = r0 @ r
-        beta = (rho_new / rho) * (alpha / omega)
-        pdir = r + beta * (pdir - omega * v)
-        v = A @ pdir
-        alpha = rho_new / (r0 @ v)
-        s = r - alpha * v
-        t = A @ s
-        omega = (t @ s) / (t @ t)
-        x += alpha * pdir + omega * s
-        r = s - omega * t
-        rho = rho_new
-        res = np.sqrt(r @ r) / nb
-        if res <= tol:
-            return x, it, res
-    return x, max_it, np.sqrt(r @ r) / nb

@@ -7,10 +7,13 @@
 //                   surrogate-boundary faces (Alg. 3); points strictly inside the brick are
 //                   then stored to v directly, points on the brick's boundary (shared with
 //                   neighbouring bricks) go to halo slots that halo_reduce_kernel sums.
-//   sbm_face_kernel DG surrogate-boundary faces (Alg. 3), atomics into the cell blocks.
+//   sbm_face_kernel DG surrogate-boundary faces (Alg. 3): (Rv, Rg) per face node.
 //   dg_cell_kernel  DG: Laplace cell term plus the SIPG terms of the cell's interior faces,
-//                   evaluated cell by cell (Alg. 2 split per side); every cell writes only
-//                   its own block.
+//                   evaluated cell by cell (Alg. 2 split per side), plus the rows of the
+//                   cell's surrogate faces; every cell writes only its own block.
+//
+// Every sum (cells into the brick lattice, face rows, brick-boundary planes, DG face rows) is
+// taken in an order fixed by the setup, with no atomics: applies are bitwise reproducible.
 //
 // Work layout: an "entity" (cell or face) is handled by NP = (p+1)^(d-1) consecutive threads,
 // EPB entities at a time per workgroup.  Thread t of an entity owns one pencil of p+1
@@ -464,8 +467,8 @@ struct BrickCfg {
   static constexpr int EPC0 = (sizeof(T) == 8 && D == 3 && P == 4) ? 4 : EPB;
   static constexpr int EPC = EPC0 < EPB ? EPC0 : EPB;
   static constexpr int NTILE = EPC < NG ? EPC + 1 : NG;  // tile pairs
-  // LDS in doubles: the lattice accumulator (FP64 in both precisions: LDS atomic adds in FP32
-  // were measured ~20x slower than in FP64 on gfx950), then either the two sweep arrays of
+  // LDS in doubles: the lattice accumulator (FP64 in both precisions: the cell and face rows
+  // are summed into it in FP64), then either the two sweep arrays of
   // the full path (in FP64 the first one is the accumulator itself) or the per-cell tiles.
   static constexpr int TAIL_SWEEP = NL;  // FP64: LB; FP32: LA and LB
   static constexpr int TAIL_CELLS = (2 * NTILE * NB * (int)sizeof(T) + 7) / 8;
@@ -671,13 +674,18 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
       T xn[N1], out[N1];
       gather_pencil<T, D, N1>(br.runs + (int64_t)(actn ? idn : 0) * NP, u, t, actn, xn);
       kron_cell<T, D, N1>(tab, t, x, A, B, scale, out);
-      if (act) {
-#pragma unroll
-        for (int i = 0; i < N1; ++i) atomicAdd(&acc[loc + run_off + i], (double)out[i]);
-      }
 #pragma unroll
       for (int i = 0; i < N1; ++i) x[i] = xn[i];
-      __syncthreads();
+      // the batch's cells add their rows in slot order (a cell's runs are disjoint), so every
+      // lattice point sums its cells in the same order on every launch: bitwise reproducible
+      const int nslot = (c1 - b) < EPC ? (c1 - b) : EPC;
+      for (int k = 0; k < nslot; ++k) {
+        if (le == k) {
+#pragma unroll
+          for (int i = 0; i < N1; ++i) acc[loc + run_off + i] += (double)out[i];
+        }
+        __syncthreads();
+      }
     }
   }
   if (parts & SBM_PART_SBM_FACES) {
@@ -687,20 +695,31 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     constexpr int SL1 = LX, SL2 = LX * LY;  // lattice strides of axes 1 and 2
     for (int b = f0; b < f1e; b += EPB) {
       const int f = b + le;
-      if (le < EPB && f < f1e) {
+      const bool fact = le < EPB && f < f1e;
+      int node = 0, Sa = 0;
+      T row[N1];
+      if (fact) {
         const FaceAxes<D, N1> fa(br.face_code[f]);
         const int loc = br.face_loc[f];
         const T Rv = fbuf[(int64_t)f * 2 * NP + t], Rg = fbuf[(int64_t)f * 2 * NP + NP + t];
         const int a = fa.a;
         const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
         // normal axis a; tangential axes in increasing order (b < c), as in FaceAxes
-        const int Sa = (a == 0) ? 1 : (a == 1 ? SL1 : SL2);
+        Sa = (a == 0) ? 1 : (a == 1 ? SL1 : SL2);
         const int Sb = (a == 0) ? SL1 : 1;
         const int Sc = (D == 3) ? ((a == 2) ? SL1 : SL2) : 0;
-        const int node = loc + jb * Sb + jc * Sc;
+        node = loc + jb * Sb + jc * Sc;
 #pragma unroll
-        for (int ia = 0; ia < N1; ++ia)
-          atomicAdd(&acc[node + ia * Sa], (double)face_row<T, D, N1>(tab, fa, ia, Rv, Rg));
+        for (int ia = 0; ia < N1; ++ia) row[ia] = face_row<T, D, N1>(tab, fa, ia, Rv, Rg);
+      }
+      // faces add in slot order (one face's node lines are disjoint): reproducible sums
+      const int nslot = (f1e - b) < EPB ? (f1e - b) : EPB;
+      for (int k = 0; k < nslot; ++k) {
+        if (fact && le == k) {
+#pragma unroll
+          for (int ia = 0; ia < N1; ++ia) acc[node + ia * Sa] += (double)row[ia];
+        }
+        __syncthreads();
       }
     }
   }
@@ -912,22 +931,22 @@ __global__ __launch_bounds__(256, 4) void sbm_face_cg_kernel(int n_faces, const 
   }
 }
 
-// DG surrogate-boundary faces: one entity = one face, atomics into the cell block of v.
+// DG surrogate-boundary faces: one entity = one face.  Output per face: Rv and Rg at its NP
+// face nodes (fbuf[f][0][t], fbuf[f][1][t]); the DG cell kernels add the face's rows into the
+// cell's block in face order, so the apply has no atomics and is bitwise reproducible.
 // ------------------------------------------------------------------------------------
 template <typename T, int D, int N1, int EPB>
 __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_t *__restrict__ face_cell,
                                                        const int32_t *__restrict__ face_code,
                                                        const double *__restrict__ face_xi, const T *__restrict__ u,
-                                                       T *__restrict__ v, KTab<T, N1> tab, KScal sc) {
+                                                       T *__restrict__ fbuf, KTab<T, N1> tab, KScal sc) {
   constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
   __shared__ T su_all[EPB * NB];
-  __shared__ T sw_all[EPB * NB];
   __shared__ T f_all[4 * EPB * NP];
   const int le = threadIdx.x / NP, t = threadIdx.x - le * NP;
   const int f = xcd_block() * EPB + le;
   const bool act = f < n_faces;
   T *su = su_all + le * NB;
-  T *sw = sw_all + le * NB;
   T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
   double xp[D];
 #pragma unroll
@@ -941,16 +960,9 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
   __syncthreads();
   T Rv, Rg;
   sbm_face_eval<T, D, N1>(tab, sc, t, act, fa, xp, su, f1, f2, f3, f4, Rv, Rg);
-  {
-    const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
-    const int node_off = jb * fa.Sb + jc * fa.Sc;
-#pragma unroll
-    for (int ia = 0; ia < N1; ++ia) sw[ia * fa.Sa + node_off] = face_row<T, D, N1>(tab, fa, ia, Rv, Rg);
-  }
-  __syncthreads();
   if (act) {
-#pragma unroll
-    for (int i = 0; i < N1; ++i) atomic_add(v + base + i, sw[N1 * t + i]);
+    fbuf[(int64_t)f * 2 * NP + t] = Rv;
+    fbuf[(int64_t)f * 2 * NP + NP + t] = Rg;
   }
 }
 
@@ -959,12 +971,12 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
 // shifted point is split over the slabs (each thread one slab's (p+1)^2 terms) and the slab
 // sums are added in slab order, as in sbm_face_eval; the face-node phases (normal
 // derivative, Gauss interpolation, integration) run in every slab with identical results;
-// each thread adds one of the face's rows.  For p <= 5 ((p+1)^3 <= 256).
+// slab 0 stores the face's (Rv, Rg) as sbm_face_kernel does.  For p <= 5 ((p+1)^3 <= 256).
 template <typename T, int N1, int EPB>
 __global__ __launch_bounds__(256) void sbm_face_slab_kernel(int n_faces, const int32_t *__restrict__ face_cell,
                                                             const int32_t *__restrict__ face_code,
                                                             const double *__restrict__ face_xi,
-                                                            const T *__restrict__ u, T *__restrict__ v,
+                                                            const T *__restrict__ u, T *__restrict__ fbuf,
                                                             KTab<T, N1> tab, KScal sc) {
   constexpr int D = 3, NP = N1 * N1, NB = NP * N1;
   __shared__ T su_all[EPB * NB];
@@ -1028,7 +1040,10 @@ __global__ __launch_bounds__(256) void sbm_face_slab_kernel(int n_faces, const i
   __syncthreads();
   T Rv, Rg;
   face_integrate<T, D, N1>(tab, t, f1, f2, f3, f4, Rv, Rg);
-  if (act) atomic_add(v + base + i2 * fa.Sa + node_off, face_row<T, D, N1>(tab, fa, i2, Rv, Rg));
+  if (act && i2 == 0) {
+    fbuf[(int64_t)f * 2 * NP + t] = Rv;
+    fbuf[(int64_t)f * 2 * NP + NP + t] = Rg;
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -1043,8 +1058,9 @@ __global__ __launch_bounds__(256) void sbm_face_slab_kernel(int n_faces, const i
 // degrees with more than 128 threads per cell in the parallel form below.
 template <typename T, int D, int N1, int EPB>
 __global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int32_t *__restrict__ nbr,
-                                                      const T *__restrict__ u, T *__restrict__ v,
-                                                      KTab<T, N1> tab, KScal sc, T scale) {
+                                                      const T *__restrict__ u, const T *__restrict__ fbuf,
+                                                      T *__restrict__ v, KTab<T, N1> tab, KScal sc, T scale,
+                                                      int parts) {
   constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, P = N1 - 1;
   __shared__ T su_all[EPB * NB];
   __shared__ T sa_all[EPB * NB];
@@ -1057,6 +1073,7 @@ __global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int
   T *su = su_all + le * NB, *A = sa_all + le * NB, *B = sb_all + le * NB, *sw = sw_all + le * NB;
   T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
   const T h = T(sc.h), sigf = T(sc.sigma_f);
+  const bool use_int = (parts & SBM_PART_CELLS) != 0, use_sbm = (parts & SBM_PART_SBM_FACES) != 0;
 
   // neighbours of the 2d faces, and the first neighbour's run for this thread: every
   // neighbour's values are loaded one face ahead, so the loads overlap the previous face
@@ -1082,9 +1099,9 @@ __global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int
     for (int k = 0; k < N1; ++k) x[k] = su[t + NP * k];
     kron_cell<T, D, N1>(tab, t, x, A, B, scale, out);
 #pragma unroll
-    for (int i = 0; i < N1; ++i) sw[N1 * t + i] = out[i];
+    for (int i = 0; i < N1; ++i) sw[N1 * t + i] = use_int ? out[i] : T(0);
   }
-  // ---- interior faces ----
+  // ---- interior faces, and the surrogate faces' rows (results of sbm_face_kernel) ----
   const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
 #pragma unroll
   for (int code = 0; code < 2 * D; ++code) {
@@ -1129,7 +1146,13 @@ __global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int
     __syncthreads();
     T Rv, Rg;
     face_integrate<T, D, N1>(tab, t, f1, f2, f3, f4, Rv, Rg);
-    if (has) {
+    const bool sbmf = nbs[code] < -1 && use_sbm;  // surrogate face -2 - nbs[code]
+    if (sbmf) {
+      const int64_t fo = (int64_t)(-2 - nbs[code]) * 2 * NP;
+      Rv = fbuf[fo + t];
+      Rg = fbuf[fo + NP + t];
+    }
+    if ((has && use_int) || sbmf) {
 #pragma unroll
       for (int ia = 0; ia < N1; ++ia)
         sw[ia * fa.Sa + node_off] += ((ia == fa.s * P) ? Rv : T(0)) + (fa.s ? tab.D1[ia] : tab.D0[ia]) * Rg;
@@ -1147,7 +1170,7 @@ __global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int
 // 2 axis + side) with its own neighbour tile and scratch, all faces at once; group 0 also
 // forms the cell term (the other groups pass its barriers on a shared scratch pair of tiles).
 // Then every row of the cell adds the cell term and the faces' rows in face order (the order
-// of a face-by-face loop).
+// of a face-by-face loop); a face without a neighbour contributes the surrogate face's rows.
 template <typename T, int D, int N1>
 constexpr int dg_cells_per_block(bool one_wave) {
   constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, TPC = 2 * D * NP;
@@ -1162,8 +1185,9 @@ constexpr int dg_cells_per_block(bool one_wave) {
 
 template <typename T, int D, int N1, int EPB>
 __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t *__restrict__ nbr,
-                                                      const T *__restrict__ u, T *__restrict__ v,
-                                                      KTab<T, N1> tab, KScal sc, T scale) {
+                                                      const T *__restrict__ u, const T *__restrict__ fbuf,
+                                                      T *__restrict__ v, KTab<T, N1> tab, KScal sc, T scale,
+                                                      int parts) {
   constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, P = N1 - 1, NF = 2 * D, TPC = NF * NP;
   __shared__ T su_all[EPB * NB];           // own tile
   __shared__ T sab_all[(2 * EPB + 2) * NB];  // cell-term tiles (A, B) per cell + one shared scratch pair
@@ -1181,6 +1205,7 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
   T *fw = f_all + (le * NF + g) * 6 * NP;
   T *f1 = fw, *f2 = fw + NP, *f3 = fw + 2 * NP, *f4 = fw + 3 * NP, *fRv = fw + 4 * NP, *fRg = fw + 5 * NP;
   const T h = T(sc.h), sigf = T(sc.sigma_f);
+  const bool use_int = (parts & SBM_PART_CELLS) != 0, use_sbm = (parts & SBM_PART_SBM_FACES) != 0;
 
   // loads: group 0 the cell's own block (thread t = run), group g the neighbour across face g
   const int nb = act ? nbr[(int64_t)cell * NF + g] : -1;
@@ -1226,8 +1251,18 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
     __syncthreads();
     T Rv, Rg;
     face_integrate<T, D, N1>(tab, t, f1, f2, f3, f4, Rv, Rg);
-    fRv[t] = has ? Rv : T(0);
-    fRg[t] = has ? Rg : T(0);
+    if (has) {
+      fRv[t] = use_int ? Rv : T(0);
+      fRg[t] = use_int ? Rg : T(0);
+    } else if (nb < -1 && use_sbm) {
+      // surrogate face -2 - nb: its (Rv, Rg) from sbm_face_kernel, rows formed as for the others
+      const int64_t fo = (int64_t)(-2 - nb) * 2 * NP;
+      fRv[t] = fbuf[fo + t];
+      fRg[t] = fbuf[fo + NP + t];
+    } else {
+      fRv[t] = T(0);
+      fRg[t] = T(0);
+    }
   }
   // ---- cell term (group 0; the other groups on the shared scratch tiles) ----
   {
@@ -1237,7 +1272,7 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
     kron_cell<T, D, N1>(tab, t, x, A, B, scale, out);
     if (g == 0) {
 #pragma unroll
-      for (int i = 0; i < N1; ++i) sw[N1 * t + i] = out[i];
+      for (int i = 0; i < N1; ++i) sw[N1 * t + i] = use_int ? out[i] : T(0);
     }
   }
   __syncthreads();
@@ -1291,7 +1326,7 @@ KTab<T, N1> make_ktab(const Rules1D &r) {
 }
 
 template <typename T, int D, int N1>
-hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t s) {
+hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t s, const Scratch &scr) {
   constexpr int NP = Shape<D, N1>::NP;
   const KTab<T, N1> tab = make_ktab<T, N1>(c->rules);
   const KScal sc{c->h, c->sigma_gamma, c->sigma_f};
@@ -1303,8 +1338,8 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
       const BrickArgs br{c->d_brick_cell_off, c->d_brick_runs, c->d_brick_cell_loc, c->d_brick_face_off,
                          c->d_brick_face_loc, c->d_face_code,  c->d_row_base,       c->d_row_gmask,
                          c->d_row_bmask,      c->d_row_hbase};
-      T *halo = (T *)c->d_halo;
-      T *fbuf = (T *)c->d_fbuf;
+      T *halo = (T *)scr.halo;
+      T *fbuf = (T *)scr.fbuf;
       if (nf > 0 && (parts & SBM_PART_SBM_FACES) && !(parts & SBM_PART_REUSE_FACES)) {
         constexpr int EF = epb<T, D, N1, 2, 0>();
         hipLaunchKernelGGL((sbm_face_cg_kernel<T, D, N1, EF>), dim3((nf + EF - 1) / EF), dim3(EF * NP), 0, s, nf,
@@ -1319,9 +1354,31 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
       }
     }
   } else {
+    // surrogate faces first (their (Rv, Rg) go to fbuf), then the cell kernel writes every
+    // cell's block once: cell term, interior faces and the surrogate faces' rows in face order
+    T *fbuf = (T *)scr.fbuf;
+    if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
+      if constexpr (D == 3 && Shape<D, N1>::NB <= 256) {
+        constexpr int NB = Shape<D, N1>::NB, E = 256 / NB, E1 = (64 / NB < 1) ? 1 : 64 / NB;
+        if ((nf + E - 1) / E >= two_per_cu())
+          hipLaunchKernelGGL((sbm_face_slab_kernel<T, N1, E>), dim3((nf + E - 1) / E), dim3(E * NB), 0, s, nf,
+                             c->d_face_cell, c->d_face_code, c->d_face_xi, u, fbuf, tab, sc);
+        else
+          hipLaunchKernelGGL((sbm_face_slab_kernel<T, N1, E1>), dim3((nf + E1 - 1) / E1), dim3(E1 * NB), 0, s,
+                             nf, c->d_face_cell, c->d_face_code, c->d_face_xi, u, fbuf, tab, sc);
+      } else {
+        constexpr int E = epb<T, D, N1, 1, 0>(), E1 = epb_one_wave<T, D, N1, 1>();
+        if ((nf + E - 1) / E >= two_per_cu())
+          hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s, nf,
+                             c->d_face_cell, c->d_face_code, c->d_face_xi, u, fbuf, tab, sc);
+        else
+          hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E1>), dim3((nf + E1 - 1) / E1), dim3(E1 * NP), 0, s, nf,
+                             c->d_face_cell, c->d_face_code, c->d_face_xi, u, fbuf, tab, sc);
+      }
+    }
     // entities per workgroup: as many as fit, unless that leaves fewer than two workgroups
     // per compute unit; then one wavefront's worth
-    if (nc > 0 && (parts & SBM_PART_CELLS)) {
+    if (nc > 0 && (parts & (SBM_PART_CELLS | SBM_PART_SBM_FACES))) {
       // faces in parallel where a cell needs at most 128 threads (3D p <= 3, 2D): measured 7 %
       // (FP64) to 20 % (FP32) faster at 3D p=3; at 3D p=5 its 216-thread, 31 KB cells leave the
       // grid in more than one round and the face-by-face form is faster
@@ -1331,37 +1388,18 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
         constexpr int E = dg_cells_per_block<T, D, N1>(false), E1 = dg_cells_per_block<T, D, N1>(true);
         if ((nc + E - 1) / E >= two_per_cu())
           hipLaunchKernelGGL((dg_cell_kernel<T, D, N1, E>), dim3((nc + E - 1) / E), dim3(E * TPC), 0, s, nc,
-                             c->d_nbr, u, v, tab, sc, scale);
+                             c->d_nbr, u, (const T *)fbuf, v, tab, sc, scale, parts);
         else
           hipLaunchKernelGGL((dg_cell_kernel<T, D, N1, E1>), dim3((nc + E1 - 1) / E1), dim3(E1 * TPC), 0, s, nc,
-                             c->d_nbr, u, v, tab, sc, scale);
+                             c->d_nbr, u, (const T *)fbuf, v, tab, sc, scale, parts);
       } else {
         constexpr int E = epb<T, D, N1, 4, 0>(), E1 = epb_one_wave<T, D, N1, 4>();
         if ((nc + E - 1) / E >= two_per_cu())
           hipLaunchKernelGGL((dg_cell_seq_kernel<T, D, N1, E>), dim3((nc + E - 1) / E), dim3(E * NP), 0, s, nc,
-                             c->d_nbr, u, v, tab, sc, scale);
+                             c->d_nbr, u, (const T *)fbuf, v, tab, sc, scale, parts);
         else
           hipLaunchKernelGGL((dg_cell_seq_kernel<T, D, N1, E1>), dim3((nc + E1 - 1) / E1), dim3(E1 * NP), 0, s,
-                             nc, c->d_nbr, u, v, tab, sc, scale);
-      }
-    }
-    if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
-      if constexpr (D == 3 && Shape<D, N1>::NB <= 256) {
-        constexpr int NB = Shape<D, N1>::NB, E = 256 / NB, E1 = (64 / NB < 1) ? 1 : 64 / NB;
-        if ((nf + E - 1) / E >= two_per_cu())
-          hipLaunchKernelGGL((sbm_face_slab_kernel<T, N1, E>), dim3((nf + E - 1) / E), dim3(E * NB), 0, s, nf,
-                             c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
-        else
-          hipLaunchKernelGGL((sbm_face_slab_kernel<T, N1, E1>), dim3((nf + E1 - 1) / E1), dim3(E1 * NB), 0, s,
-                             nf, c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
-      } else {
-        constexpr int E = epb<T, D, N1, 2, 0>(), E1 = epb_one_wave<T, D, N1, 2>();
-        if ((nf + E - 1) / E >= two_per_cu())
-          hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E>), dim3((nf + E - 1) / E), dim3(E * NP), 0, s, nf,
-                             c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
-        else
-          hipLaunchKernelGGL((sbm_face_kernel<T, D, N1, E1>), dim3((nf + E1 - 1) / E1), dim3(E1 * NP), 0, s, nf,
-                             c->d_face_cell, c->d_face_code, c->d_face_xi, u, v, tab, sc);
+                             nc, c->d_nbr, u, (const T *)fbuf, v, tab, sc, scale, parts);
       }
     }
   }
@@ -1496,16 +1534,16 @@ hipError_t diag_dim(const sbm_ctx *c, T *diag, hipStream_t s) {
 }
 
 template <typename T, int D>
-hipError_t apply_dim(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t s) {
+hipError_t apply_dim(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t s, const Scratch &scr) {
   switch (c->p) {
-    case 1: return apply_impl<T, D, 2>(c, u, v, parts, s);
-    case 2: return apply_impl<T, D, 3>(c, u, v, parts, s);
-    case 3: return apply_impl<T, D, 4>(c, u, v, parts, s);
-    case 4: return apply_impl<T, D, 5>(c, u, v, parts, s);
-    case 5: return apply_impl<T, D, 6>(c, u, v, parts, s);
-    case 6: return apply_impl<T, D, 7>(c, u, v, parts, s);
-    case 7: return apply_impl<T, D, 8>(c, u, v, parts, s);
-    case 8: return apply_impl<T, D, 9>(c, u, v, parts, s);
+    case 1: return apply_impl<T, D, 2>(c, u, v, parts, s, scr);
+    case 2: return apply_impl<T, D, 3>(c, u, v, parts, s, scr);
+    case 3: return apply_impl<T, D, 4>(c, u, v, parts, s, scr);
+    case 4: return apply_impl<T, D, 5>(c, u, v, parts, s, scr);
+    case 5: return apply_impl<T, D, 6>(c, u, v, parts, s, scr);
+    case 6: return apply_impl<T, D, 7>(c, u, v, parts, s, scr);
+    case 7: return apply_impl<T, D, 8>(c, u, v, parts, s, scr);
+    case 8: return apply_impl<T, D, 9>(c, u, v, parts, s, scr);
   }
   return hipErrorInvalidValue;
 }
@@ -1532,13 +1570,25 @@ hipError_t launch_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s
   return c->dim == 3 ? diag_dim<float, 3>(c, (float *)diag, s) : diag_dim<float, 2>(c, (float *)diag, s);
 }
 
-hipError_t launch_apply(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s) {
+size_t apply_scratch_bytes(const sbm_ctx *c, int prec) {
+  const size_t s = prec == SBM_F64 ? sizeof(double) : sizeof(float);
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t halo = c->disc == SBM_CG ? ((size_t)1 << c->dim) * (size_t)c->n_halo_dofs * s : 0;
+  const size_t fbuf = (size_t)c->n_sbm * 2 * (size_t)c->nq_face * s;
+  return up(halo) + up(fbuf);
+}
+
+hipError_t launch_apply(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s,
+                        const Scratch *scr) {
+  Scratch use;
+  use.halo = (scr && scr->halo) ? scr->halo : c->d_halo;
+  use.fbuf = (scr && scr->fbuf) ? scr->fbuf : c->d_fbuf;
   if (prec == SBM_F64) {
-    return c->dim == 3 ? apply_dim<double, 3>(c, (const double *)u, (double *)v, parts, s)
-                       : apply_dim<double, 2>(c, (const double *)u, (double *)v, parts, s);
+    return c->dim == 3 ? apply_dim<double, 3>(c, (const double *)u, (double *)v, parts, s, use)
+                       : apply_dim<double, 2>(c, (const double *)u, (double *)v, parts, s, use);
   }
-  return c->dim == 3 ? apply_dim<float, 3>(c, (const float *)u, (float *)v, parts, s)
-                     : apply_dim<float, 2>(c, (const float *)u, (float *)v, parts, s);
+  return c->dim == 3 ? apply_dim<float, 3>(c, (const float *)u, (float *)v, parts, s, use)
+                     : apply_dim<float, 2>(c, (const float *)u, (float *)v, parts, s, use);
 }
 
 }  // namespace sbm

@@ -375,12 +375,13 @@ hipError_t taylor_run(const sbm_ctx *c, const void *u, void *v, void *diag, hipS
 
 }  // namespace
 
-hipError_t launch_operator(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s) {
-  if (c->taylor_m < 0 || !(parts & SBM_PART_SBM_FACES)) return launch_apply(c, u, v, prec, parts, s);
+hipError_t launch_operator(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s,
+                           const Scratch *scr) {
+  if (c->taylor_m < 0 || !(parts & SBM_PART_SBM_FACES)) return launch_apply(c, u, v, prec, parts, s, scr);
   // the cell term (DG: with the interior faces) overwrites v; the surrogate faces add into it
   const int rest = parts & ~(SBM_PART_SBM_FACES | SBM_PART_REUSE_FACES);
   if (rest & SBM_PART_CELLS) {
-    hipError_t e = launch_apply(c, u, v, prec, rest, s);
+    hipError_t e = launch_apply(c, u, v, prec, rest, s, scr);
     if (e != hipSuccess) return e;
   }
   return prec == SBM_F64 ? taylor_run<double>(c, u, v, nullptr, s) : taylor_run<float>(c, u, v, nullptr, s);

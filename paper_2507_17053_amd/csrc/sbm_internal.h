@@ -95,7 +95,7 @@ struct sbm_ctx {
   std::vector<double> face_xi;     // n_sbm x nq x dim
   std::vector<double> face_xtrue;  // n_sbm x nq x dim
   std::vector<int32_t> runs;       // CG: n_cells x (p+1)^(d-1) first DoF of each x-run
-  std::vector<int32_t> nbr;        // n_cells x 2d neighbour rank or -1
+  std::vector<int32_t> nbr;        // n_cells x 2d: neighbour rank, or -2 - f for surrogate face f
   // CG bricks: BX x BY x BZ blocks of background cells, one workgroup each
   int brick[3] = {1, 1, 1};
   int64_t n_bricks = 0;
@@ -115,7 +115,7 @@ struct sbm_ctx {
   int32_t *d_row_hbase = nullptr, *d_halo_dof = nullptr;
   uint8_t *d_halo_mask = nullptr;
   void *d_halo = nullptr;  // 2^d x n_halo_dofs doubles (also used as floats); per-handle scratch
-  void *d_fbuf = nullptr;  // CG: n_sbm x 2 x (p+1)^(d-1) doubles, surrogate-face results; per-handle scratch
+  void *d_fbuf = nullptr;  // n_sbm x 2 x (p+1)^(d-1) doubles, surrogate-face results; per-handle scratch
   int32_t *d_brick_cell_off = nullptr, *d_brick_runs = nullptr, *d_brick_cell_loc = nullptr;
   int32_t *d_face_runs = nullptr;
   int32_t *d_brick_face_off = nullptr, *d_brick_face_loc = nullptr;
@@ -136,16 +136,29 @@ struct sbm_ctx {
 namespace sbm {
 // Thread-local last error.
 void set_error(const std::string &msg);
+// Scratch of one apply: the CG halo planes and the surrogate-face results.  NULL members (or
+// a NULL Scratch) select the handle's own buffers (d_halo, d_fbuf).
+struct Scratch {
+  void *halo = nullptr;
+  void *fbuf = nullptr;
+};
+// Bytes of scratch one apply of c needs in precision prec (elements of the apply's type):
+// halo planes and face results, each rounded up to 256 bytes.
+size_t apply_scratch_bytes(const sbm_ctx *c, int prec);
 // Launchers (kernels.hip).  All asynchronous on stream.
-hipError_t launch_apply(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s);
+hipError_t launch_apply(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s,
+                        const Scratch *scr = nullptr);
 hipError_t launch_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s);
 // The operator of the handle's extension (kernels_taylor.hip): launch_apply / launch_diagonal
 // when the extension is the full one, else the cell term by launch_apply plus the truncated
 // surrogate-face term.  Every apply and diagonal of the library goes through these.
-hipError_t launch_operator(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s);
+hipError_t launch_operator(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s,
+                           const Scratch *scr = nullptr);
 hipError_t launch_operator_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s);
 // Brick shape (cells per direction) used by the CG kernel for (dim, p).
 void brick_dims(int dim, int p, int *bx, int *by, int *bz);
+// Device bytes of the handle's solver workspace (0 before the first solve).
+size_t workspace_bytes(const sbm_ctx *c);
 // Vector kernels (vec.hip)
 hipError_t vec_fill(void *x, int64_t n, double val, int prec, hipStream_t s);
 }  // namespace sbm

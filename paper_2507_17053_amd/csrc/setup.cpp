@@ -909,7 +909,8 @@ static sbm_status host_setup(sbm_ctx *c, const sbm_mesh *mesh, const sbm_levelse
         nbv[a] += s ? 1 : -1;
         int32_t nr = -1;
         if (nbv[a] >= 0 && nbv[a] < c->n[a]) nr = rank[(nbv[2] * ny + nbv[1]) * nx + nbv[0]];
-        c->nbr[r * 2 * d + 2 * a + s] = nr;
+        // a missing neighbour is a surrogate face f, stored as -2 - f (every reader tests < 0)
+        c->nbr[r * 2 * d + 2 * a + s] = nr >= 0 ? nr : (int32_t)(-2 - (int64_t)c->faces.size() / 3);
         if (nr < 0) {
           c->faces.push_back((int32_t)r);
           c->faces.push_back(a);
@@ -1094,6 +1095,7 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
     plan.scratch(c->d_fbuf, (size_t)c->n_sbm * 2 * c->nq_face * sizeof(double));
   } else {
     plan.add(c->d_nbr, c->nbr);
+    plan.scratch(c->d_fbuf, (size_t)c->n_sbm * 2 * c->nq_face * sizeof(double));
   }
   plan.add(c->d_face_cell, fcell);
   plan.add(c->d_face_code, fcode);
@@ -1121,7 +1123,7 @@ sbm_status sbm_info(sbm_handle h, int64_t *n_dofs, int64_t *n_cells, int64_t *n_
   if (n_cells) *n_cells = h->n_cells;
   if (n_sbm_faces) *n_sbm_faces = h->n_sbm;
   if (n_interior_faces) *n_interior_faces = h->n_int;
-  if (device_bytes) *device_bytes = h->device_bytes;
+  if (device_bytes) *device_bytes = h->device_bytes + sbm::workspace_bytes(h);
   return SBM_OK;
 }
 
@@ -1283,24 +1285,43 @@ sbm_status sbm_export_cell_dofs(sbm_handle h, int64_t *dofs) {
 
 size_t sbm_footprint_estimate(const sbm_mesh *mesh, int p, int disc, int64_t n_cells_hint,
                               int64_t n_faces_hint) {
-  if (!mesh || p < 1 || p > kMaxP) return 0;
+  // An upper bound of what sbm_setup allocates for at most n_cells_hint active cells and
+  // n_faces_hint surrogate faces: every array of the handle's arena (one hipMalloc), sized by
+  // bounds that hold for any geometry, each rounded up to 256 bytes as the arena does.
+  if (!mesh || p < 1 || p > kMaxP || (mesh->dim != 2 && mesh->dim != 3) || n_cells_hint < 0 ||
+      n_faces_hint < 0)
+    return 0;
   const int d = mesh->dim;
   const int64_t n1 = p + 1;
   const int64_t nb = (d == 3) ? n1 * n1 * n1 : n1 * n1;
   const int64_t np = (d == 3) ? n1 * n1 : n1;
-  const int64_t nc = n_cells_hint;
-  const int64_t ndofs = (disc == SBM_CG) ? nc * (int64_t)std::pow((double)p, d) + 3 * np * nc / n1 : nc * nb;
+  const int64_t nc = n_cells_hint, nf = n_faces_hint;
+  auto up = [](int64_t b) { return (size_t)((b + 255) / 256 * 256); };
   size_t b = 0;
   if (disc == SBM_CG) {
-    // run bases (cell order and brick order), per-face run bases and face results, halo slots
-    // (at most about one per DoF), brick row descriptors (16 bytes per lattice row, about
-    // (p+1) rows per cell)
-    b += 8 * nc * np + n_faces_hint * (4 * np + 8 * nb) + 8 * ndofs + 16 * nc * n1 * (d == 3 ? n1 : 1);
+    const int64_t ndofs = nc * nb;  // every active cell touches (p+1)^d lattice points
+    int bx = 1, by = 1, bz = 1;
+    brick_dims(d, p, &bx, &by, &bz);
+    const int64_t B[3] = {bx, by, d == 3 ? bz : 1};
+    // brick-boundary points of one cell: on each axis it meets both brick planes if the brick
+    // is one cell wide there, else at most one
+    int64_t inner = 1;
+    for (int k = 0; k < d; ++k) inner *= (n1 - (B[k] == 1 ? 2 : 1));
+    const int64_t halo = std::min<int64_t>(ndofs, nc * (nb - inner));
+    const int64_t rows = (B[1] * p + 1) * (d == 3 ? B[2] * p + 1 : 1);  // lattice rows per brick
+    const int64_t nbricks = nc;                                        // every brick has a cell
+    b += up(4 * nc * np) * 2;                                          // runs, brick_runs
+    b += up(4 * (nbricks + 1)) * 2 + up(4 * nc) + up(4 * nf);          // offsets, cell/face locations
+    b += up(4 * nf * np);                                              // face_runs
+    b += 4 * up(4 * nbricks * rows);                                   // row descriptors
+    b += up(4 * halo) + up(halo);                                      // halo DoF ids and masks
+    b += up(((int64_t)1 << d) * 8 * halo);                             // halo planes (FP64)
   } else {
-    b += 4 * nc * 2 * d;
+    b += up(4 * nc * 2 * d);  // neighbour table
   }
-  b += n_faces_hint * (8 + np * d * 8);
-  return b + (size_t)ndofs * 8;
+  b += up(8 * nf * 2 * np);                              // surrogate-face results (FP64)
+  b += up(4 * nf) * 2 + up(8 * nf * np * d);             // face cell, code, shifted points
+  return b;
 }
 
 }  // extern "C"

@@ -585,11 +585,14 @@ struct Workspace {
   double *gm = nullptr;       // GMRES state: H ((m+1) x m), cs, sn (m), g (m+1), res (m), factor
   unsigned *ticket = nullptr; // block counter of the single-pass reductions (0 between launches)
   void *arena = nullptr;      // the allocation holding all of the above
+  size_t bytes = 0;           // device bytes held: the arena plus the Jacobi diagonals
   bool have_diag = false;
   // grid of each Gram-Schmidt kernel: as many blocks as fit on the device at once (no partial
   // last round), index [FP32][log2(CPW) - 1, 4 for the kernel of more than 64 columns][MODE]
   int gs_grid[2][5][3] = {};
 };
+
+size_t workspace_bytes(const sbm_ctx *c) { return c->ws ? c->ws->bytes : 0; }
 
 void free_workspace(sbm_ctx *c) {
   Workspace *ws = c->ws;
@@ -642,6 +645,7 @@ static hipError_t ensure_workspace(sbm_ctx *c, int m, bool need32) {
   }
   hipError_t e = hipMalloc(&ws->arena, off);
   if (e != hipSuccess) return e;
+  ws->bytes = off;
   for (auto &set : parts) set(static_cast<char *>(ws->arena));
   return hipMemset(ws->ticket, 0, sizeof(unsigned));
 }
@@ -1099,6 +1103,7 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
         set_error("sbm_solve: out of device memory");
         return SBM_ENOMEM;
       }
+      ws->bytes += sizeof(double) * n;
     }
     sbm_status st = sbm_diagonal(h, ws->dinv, SBM_F64, stream);
     if (st != SBM_OK) {
@@ -1108,9 +1113,12 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
     hipLaunchKernelGGL(invert_kernel, dim3(nb), dim3(kThreads), 0, s, ws->dinv, n);
     dinv = ws->dinv;
     if (mode == SBM_SOLVE_GMRES_IR) {
-      if (!ws->dinv32 && hipMalloc(&ws->dinv32, sizeof(float) * n) != hipSuccess) {
-        set_error("sbm_solve: out of device memory");
-        return SBM_ENOMEM;
+      if (!ws->dinv32) {
+        if (hipMalloc(&ws->dinv32, sizeof(float) * n) != hipSuccess) {
+          set_error("sbm_solve: out of device memory");
+          return SBM_ENOMEM;
+        }
+        ws->bytes += sizeof(float) * n;
       }
       hipLaunchKernelGGL(cast_f64_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->dinv, ws->dinv32, n);
       dinv32 = ws->dinv32;

@@ -213,7 +213,6 @@ class Operator:
         _check(_lib.sbm_info(h, ctypes.byref(nd), ctypes.byref(nc), ctypes.byref(nf), ctypes.byref(ni),
                              ctypes.byref(nbytes)), "sbm_info")
         self.n_dofs, self.n_cells, self.n_sbm_faces, self.n_interior_faces = nd.value, nc.value, nf.value, ni.value
-        self.device_bytes = nbytes.value
         self.nq_face = (p + 1) ** (d - 1)
         self.nb = (p + 1) ** d
         self.taylor_order = None
@@ -229,6 +228,14 @@ class Operator:
     @property
     def handle(self):
         return self._h
+
+    @property
+    def device_bytes(self):
+        """Device bytes the handle holds now (sbm_info): operator data and scratch, plus the
+        solver workspace once a solve has allocated it."""
+        nbytes = ctypes.c_size_t()
+        _check(_lib.sbm_info(self._h, None, None, None, None, ctypes.byref(nbytes)), "sbm_info")
+        return nbytes.value
 
     def close(self):
         if getattr(self, "_h", None):

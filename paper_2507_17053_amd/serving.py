@@ -72,13 +72,31 @@ class Scheduler:
         return not self.pending and not self.active
 
 
-def footprint_bytes(n_dofs: int, device_bytes: int, restart: int, mixed: bool) -> int:
-    """Device bytes a solve holds: operator data + b, x + GMRES workspace (FP64 basis and
-    work vectors, plus the FP32 copies in the mixed mode)."""
-    ws = 8 * n_dofs * (restart + 1 + 4)
+def _up(b: int) -> int:
+    return (int(b) + 255) // 256 * 256
+
+
+def workspace_bytes(n_dofs: int, restart: int, mixed: bool, jacobi: bool = False) -> int:
+    """Device bytes of the solver workspace sbm_solve allocates for GMRES(restart) on n_dofs
+    unknowns, piece by piece as the library carves it (every piece on a 256-byte boundary):
+    FP64 basis of restart + 1 row-tiled columns, five FP64 work vectors, the block partials of
+    the reductions (1024 blocks) and the small Hessenberg state; in the mixed mode the FP32
+    basis and five FP32 work vectors; with Jacobi the FP64 (and FP32) inverse diagonal."""
+    n = max(1, int(n_dofs))
+    m = int(restart)
+    npad = (n + 127) // 128 * 128
+    b = _up(8 * npad * (m + 1)) + 5 * _up(8 * n) + _up(8 * 1024 * (m + 2)) + _up(8 * 3 * (m + 2))
+    b += _up(8 * (m + 2)) + _up(8 * ((m + 1) * m + 4 * m + 2)) + _up(4)
     if mixed:
-        ws += 4 * n_dofs * (restart + 1 + 4)
-    return int(device_bytes + 16 * n_dofs + ws)
+        b += _up(4 * npad * (m + 1)) + 5 * _up(4 * n)
+    if jacobi:
+        b += 8 * n + (4 * n if mixed else 0)
+    return b
+
+
+def footprint_bytes(n_dofs: int, device_bytes: int, restart: int, mixed: bool, jacobi: bool = False) -> int:
+    """Device bytes a solve holds: operator data and scratch + b, x + the solver workspace."""
+    return int(device_bytes + 16 * n_dofs + workspace_bytes(n_dofs, restart, mixed, jacobi))
 
 
 def _phi_sign(ls, x):
@@ -121,11 +139,12 @@ class Server:
     """Runs a request stream on the GPU through the library (see module docstring)."""
 
     def __init__(self, budget_bytes, slots=4, mode="gmres_ir", rel_tol=1e-10, max_it=400, restart=32,
-                 taylor_order=None):
+                 taylor_order=None, jacobi=False):
         """taylor_order: extension of the surrogate-face term for requests that do not name one
         (None: the full extension; m >= 0: the Taylor expansion kept to order m)."""
         self.sched = Scheduler(budget_bytes, slots)
         self.mode, self.rel_tol, self.max_it, self.restart = mode, rel_tol, max_it, restart
+        self.jacobi = bool(jacobi)
         self.taylor_order = taylor_order
         self.lock = threading.Lock()
         self.done = threading.Condition(self.lock)
@@ -133,12 +152,16 @@ class Server:
 
     def _estimate(self, req):
         """Upper-bound footprint from the number of background cells whose vertices are all
-        inside the domain (vectorised vertex test; no setup)."""
+        inside the domain (vectorised vertex test; no setup): the library's bound of the
+        operator's device data (at most 2d surrogate faces per cell) plus b, x and the exact
+        workspace layout of the solve for at most n_cells (p+1)^d unknowns."""
+        from . import sbm
         n_cells = count_inside_cells(req)
         nb = (req["p"] + 1) ** req["d"]
         n_dofs = n_cells * nb  # bound for CG, exact for DG
-        dev = n_cells * nb * 8 + n_cells * 64 * nb // (req["p"] + 1)  # maps, bricks, face data
-        return footprint_bytes(n_dofs, dev, self.restart, self.mode == "gmres_ir"), n_dofs
+        dev = sbm.footprint_estimate(req["d"], req["n"], req["lo"], req["hi"], req["p"], req["disc"], n_cells,
+                                     2 * req["d"] * n_cells)
+        return footprint_bytes(n_dofs, dev, self.restart, self.mode == "gmres_ir", self.jacobi), n_dofs
 
     def solve_one(self, req, stream=None):
         """Setup, right-hand side and solve of one request on `stream`; returns (x, info)."""
@@ -155,7 +178,8 @@ class Server:
                 op.rhs(f_fn(cq.reshape(-1, req["d"])), u_fn(bp.reshape(-1, req["d"])), b, stream=stream)
                 x = torch.zeros_like(b)
                 info = op.solve(b, x, rel_tol=self.rel_tol, max_it=self.max_it, mode=self.mode,
-                                restart=self.restart, stream=stream)
+                                restart=self.restart, jacobi=self.jacobi, stream=stream)
+                info["device_bytes"] = op.device_bytes
                 xh = x.cpu().numpy() if stream is None else _to_host(x, stream)
             info["n_dofs"] = op.n_dofs
             return xh, info

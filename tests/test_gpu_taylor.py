@@ -1,6 +1,6 @@
 """GPU parity of the truncated-Taylor extension E_m (sbm_set_extension_order) against the FP64
 oracle's assembled operator with the same order: the apply (FP64 <= 1e-12, FP32 <= 5e-6
-relative), the diagonal, a GMRES solve, and at full size the identity E_m = E for m >= d p
+relative, norm-wise and row by row scaled by (|A||u|)_i), the diagonal, a GMRES solve, and at full size the identity E_m = E for m >= d p
 (the Taylor series of the cell polynomial terminates)."""
 
 import numpy as np
@@ -8,6 +8,7 @@ import pytest
 
 from oracle import sbm_oracle as O
 from paper_2507_17053_amd import inputs
+from parity_util import row_scaled_excess, sampled_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -50,11 +51,16 @@ def test_taylor_apply_matches_oracle(d, n, ls, p, disc, m, dtype):
     ref = O.setup(d, n, -1.0, 1.0, ls, p, disc=disc, taylor_order=m)
     A = O.assemble(ref)
     u = inputs.uniform_vector(ref.n_dofs, seed=0)
+    ui = u if dtype == torch.float64 else u.astype(np.float32).astype(np.float64)
     op = sbm.Operator(d, n, -1.0, 1.0, ls, p, disc=disc, taylor_order=m)
     v = _gpu_apply(op, u, dtype)
-    err = _rel(v, A @ u)
-    print(f"  rel err {err:.3e}", flush=True)
+    vref = A @ ui
+    err = _rel(v, vref)
+    ex, i = row_scaled_excess(v, vref, A, ui, TOL[dtype])
+    print(f"  rel err {err:.3e}, worst row {i}: {ex:.3f} of the row bar", flush=True)
     assert err <= TOL[dtype], err
+    # every row within tol * (|A||u|)_i: the interior rows cannot hide under the face rows
+    assert ex <= 1.0, (i, v[i], vref[i])
     op.close()
 
 
@@ -119,6 +125,34 @@ def test_full_order_equals_default_at_size(dtype):
     err = _rel(v12, v_full)
     print(f"  rel diff {err:.3e}", flush=True)
     assert err <= TOL[dtype], err
+    op.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("wname,over,m", [("sphere3d_q4", {}, 1), ("sphere3d_q4", {}, None),
+                                          ("torus3d_dg", {"p": 3}, 1)],
+                         ids=["sphere64-q4-E1", "sphere64-q4-full", "torus32-q3-dg-E1"])
+def test_full_size_sampled_rows_match_oracle(wname, over, m, dtype):
+    """Full workload size, in the launch configuration the benchmark times: the rows of the
+    DoFs of 48 surrogate-face cells and 48 other cells (sampled with a fixed seed), each
+    compared with the oracle's row formed from its local matrices, within tol (|A||u|)_i."""
+    w = inputs.workload(wname, **over)
+    ref = O.setup(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"], taylor_order=m)
+    op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"], taylor_order=m)
+    print(f"case {wname} {over} m={m} dtype={dtype} n_dofs={ref.n_dofs}", flush=True)
+    u = inputs.uniform_vector(ref.n_dofs, seed=0)
+    ui = u if dtype == torch.float64 else u.astype(np.float32).astype(np.float64)
+    v = _gpu_apply(op, u, dtype)
+    rng = np.random.default_rng(7)
+    face_cells = np.unique(ref.sbm_faces[:, 0])
+    other = np.setdiff1d(np.arange(ref.cells.shape[0]), face_cells)
+    pick = np.concatenate([rng.choice(face_cells, 48, replace=False), rng.choice(other, 48, replace=False)])
+    dofs = np.unique(ref.cell_dofs[pick].ravel())
+    vref, scale = sampled_rows(O, ref, ui, dofs)
+    ratio = np.abs(v[dofs] - vref) / (TOL[dtype] * scale)
+    i = int(np.argmax(ratio))
+    print(f"  {dofs.size} rows, worst {ratio[i]:.3f} of the row bar", flush=True)
+    assert ratio[i] <= 1.0, (dofs[i], v[dofs[i]], vref[i])
     op.close()
 
 

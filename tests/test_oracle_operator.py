@@ -166,3 +166,18 @@ def test_disk_config_counts():
     assert prob.cells.shape[0] == 77
     assert prob.sbm_faces.shape[0] == 40
     assert prob.n_dofs == 349
+
+
+@pytest.mark.parametrize("disc,m", [("cg", None), ("cg", 1), ("dg", None), ("dg", 2)])
+def test_sampled_rows_equal_assembled_rows(disc, m):
+    """The row-at-a-time oracle used by the full-size GPU tests equals the assembled matrix's
+    rows, and its scale is at least |A||u| (local terms are summed in absolute value)."""
+    from parity_util import sampled_rows
+    prob = O.setup(3, 6, -1.0, 1.0, {"kind": "sphere", "centre": [0.0, 0.0, 0.0], "radius": 0.75}, 2,
+                   disc=disc, taylor_order=m)
+    A = O.assemble(prob)
+    u = np.random.default_rng(3).uniform(-1, 1, prob.n_dofs)
+    dofs = np.arange(0, prob.n_dofs, 7)
+    v, s = sampled_rows(O, prob, u, dofs)
+    assert np.allclose(v, (A @ u)[dofs], rtol=0, atol=1e-12 * np.abs(A @ u).max())
+    assert np.all(s >= (abs(A) @ np.abs(u))[dofs] * (1 - 1e-12))
