@@ -144,6 +144,23 @@ const char *sbm_last_error(void);
 sbm_status sbm_apply(sbm_handle h, const void *u, void *v, int prec, void *stream);
 
 /*
+ * sbm_apply_noalloc -- sbm_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same operator,
+ * kernels, arguments and result as sbm_apply (bitwise equal with the default extension), but
+ * the apply's scratch is taken from a static device array of 96 MiB held by the library on
+ * each device it runs on (until the process ends) instead of the handle's own buffers.  The
+ * call allocates nothing and never synchronises.  Every call on one device shares that array
+ * and leaves its contents behind: calls that overlap on one device (other streams or threads)
+ * race and give wrong results; calls ordered on one stream are safe.  The first call on a
+ * device looks up that device's array address (that device must be current).
+ * Errors: EINVAL (as sbm_apply, or the handle needs more scratch than 96 MiB in this
+ * precision -- the CG brick-boundary sums take 2^dim x boundary DoFs values and the
+ * surrogate faces 2 (p+1)^(dim-1) values each: a 64^3 Q4 sphere needs 67 MB in FP64; the
+ * message states the size), EHIP.
+ */
+sbm_status sbm_apply_noalloc(sbm_handle h, const void *u, void *v, int prec, void *stream);
+
+/*
  * sbm_apply_parts -- diagnostic split of sbm_apply: v = (selected parts of A) u, with
  * SBM_PART_CELLS the cell term (for DG including the interior faces) and
  * SBM_PART_SBM_FACES the surrogate-boundary faces; SBM_PART_ALL gives sbm_apply.  v is

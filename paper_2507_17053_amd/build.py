@@ -21,7 +21,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["setup.cpp", "kernels_apply.hip", "kernels_taylor.hip", "vec.hip", "solver.hip"]
+SOURCES = ["setup.cpp", "kernels_apply.hip", "kernels_taylor.hip", "vec.hip", "solver.hip",
+           "apply_noalloc.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -77,6 +77,7 @@ _lib.sbm_destroy.restype = None
 _lib.sbm_last_error.restype = ctypes.c_char_p
 _lib.sbm_apply.argtypes = [_P, _P, _P, ctypes.c_int, _P]
 _lib.sbm_apply_parts.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]
+_lib.sbm_apply_noalloc.argtypes = [_P, _P, _P, ctypes.c_int, _P]
 _lib.sbm_apply_batch.argtypes = [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                  ctypes.c_int, _P]
 _lib.sbm_dof_points.argtypes = [_P, _P]
@@ -94,7 +95,8 @@ for _n in ("sbm_export_cells", "sbm_export_sbm_faces", "sbm_export_face_xi", "sb
 
 PART_CELLS, PART_SBM_FACES, PART_ALL, PART_NO_ASSEMBLY, PART_REUSE_FACES = 2, 4, 6, 8, 16
 _lib.sbm_layout_stats.argtypes = [_P, _I64P, _I64P, _I64P]
-EXPORTED = ["sbm_setup", "sbm_info", "sbm_destroy", "sbm_last_error", "sbm_apply", "sbm_apply_parts",
+EXPORTED = ["sbm_setup", "sbm_info", "sbm_destroy", "sbm_last_error", "sbm_apply", "sbm_apply_noalloc",
+            "sbm_apply_parts",
             "sbm_apply_batch", "sbm_layout_stats",
             "sbm_dof_points", "sbm_rhs_points", "sbm_rhs", "sbm_solve", "sbm_diagonal",
             "sbm_footprint_estimate", "sbm_export_cells", "sbm_export_sbm_faces", "sbm_export_face_xi",
@@ -260,6 +262,19 @@ class Operator:
         if not (u.is_contiguous() and v.is_contiguous()):
             raise ValueError("vectors must be contiguous")
         _check(_lib.sbm_apply(self._h, _dptr(u), _dptr(v), prec, _stream_ptr(stream)), "sbm_apply")
+
+    def apply_noalloc(self, u, v, stream=None):
+        """sbm_apply_noalloc: v = A u with the library's static device scratch (no allocation)."""
+        import torch
+        prec = SBM_F64 if u.dtype == torch.float64 else SBM_F32
+        if v.dtype != u.dtype:
+            raise TypeError("u and v must have the same dtype")
+        if u.numel() != self.n_dofs or v.numel() != self.n_dofs:
+            raise ValueError("vector length must be n_dofs")
+        if not (u.is_contiguous() and v.is_contiguous()):
+            raise ValueError("vectors must be contiguous")
+        _check(_lib.sbm_apply_noalloc(self._h, _dptr(u), _dptr(v), prec, _stream_ptr(stream)),
+               "sbm_apply_noalloc")
 
     def apply_parts(self, u, v, parts, stream=None):
         """Diagnostic subset of the apply launches (see sbm_apply_parts)."""

@@ -112,6 +112,17 @@ def test_host_only_handle_refuses_apply():
     assert st == sbm.SBM_EINVAL
 
 
+def test_noalloc_apply_host_checks():
+    """sbm_apply_noalloc refuses a NULL handle and a host-only handle before touching the
+    device."""
+    assert sbm._lib.sbm_apply_noalloc(None, ctypes.c_void_p(8), ctypes.c_void_p(16), 0, None) == sbm.SBM_EINVAL
+    op = sbm.Operator(3, 4, -1.0, 1.0, inputs.sphere((0, 0, 0), 0.8), 2, host_only=True)
+    st = sbm._lib.sbm_apply_noalloc(op.handle, ctypes.c_void_p(8), ctypes.c_void_p(16), 0, None)
+    assert st == sbm.SBM_EINVAL
+    assert b"HOST_ONLY" in sbm._lib.sbm_last_error()
+    op.close()
+
+
 def test_library_exports_every_declared_symbol():
     import os
     import re
