@@ -61,7 +61,9 @@ enum {
   SBM_LS_CALLBACK = 5      /* user phi and grad phi (fields phi, grad, user below); closest
                               points by the level-set Newton iteration of Sec. 4.4,
                               x <- x - phi(x) grad phi(x) / |grad phi(x)|^2 from the surrogate
-                              point, until |phi| <= 1e-14 or 50 steps (the point reached is
+                              point, until the step |phi| / |grad phi| is at most
+                              8 eps max(1, max_k |x_k|) (scale-aware), at most 50 steps,
+                              else setup fails with SBM_EINVAL (the point reached is
                               on the boundary, and is the closest one when phi is a distance
                               function or its gradient lines are straight).  The callbacks are
                               called from the thread that calls sbm_setup only, during it. */

@@ -486,25 +486,32 @@ def closest_point(ls: dict, x: np.ndarray) -> np.ndarray:
 
 def _closest_newton(ls: dict, x: np.ndarray) -> np.ndarray:
     """Level-set Newton projection (Sec. 4.4: the projection is a Newton solve on the level
-    set): per point, y <- y - phi(y) grad phi(y) / |grad phi(y)|^2 from y = x, stopping when
-    |phi(y)| <= 1e-14; a point that needs more than 50 steps is an error.  This reaches a
-    point of the boundary; it is the closest one for a distance function or, more generally,
-    when the gradient lines are straight (spheres, tori given by their distance)."""
+    set): per point, y <- y - phi(y) grad phi(y) / |grad phi(y)|^2 from y = x.  The paper does
+    not fix a stopping rule; the one used here is scale-aware: stop when the Newton step
+    |phi(y)| / |grad phi(y)| is at most 8 eps max(1, max_k |y_k|) (eps = 2^-52), i.e. when the
+    point is within a few units in the last place of the zero set, whatever the scaling of phi.
+    A point that needs more than 50 steps is an error.  This reaches a point of the boundary;
+    it is the closest one for a distance function or, more generally, when the gradient lines
+    are straight (spheres, tori given by their distance)."""
+    eps = np.finfo(np.float64).eps
     y = np.array(x, dtype=np.float64)
     todo = np.ones(y.shape[0], dtype=bool)
     for it in range(51):
-        ph = np.asarray(ls["phi"](y[todo]), dtype=np.float64)
-        done = np.abs(ph) <= 1e-14
         idx = np.flatnonzero(todo)
+        yt = y[idx]
+        ph = np.asarray(ls["phi"](yt), dtype=np.float64)
+        g = np.asarray(ls["grad"](yt), dtype=np.float64)
+        g2 = np.sum(g * g, axis=1)
+        scale = np.maximum(1.0, np.max(np.abs(yt), axis=1))
+        done = np.isfinite(ph) & (np.abs(ph) <= 8.0 * eps * np.sqrt(g2) * scale)
         todo[idx[done]] = False
         if not todo.any():
             return y
         if it == 50:
             break
-        g = np.asarray(ls["grad"](y[todo]), dtype=np.float64)
-        g2 = np.sum(g * g, axis=1)
-        y[todo] -= ph[~done][:, None] * g / g2[:, None]
-    raise ValueError("level-set Newton projection did not reach |phi| <= 1e-14 in 50 steps")
+        step = ~done
+        y[idx[step]] -= ph[step][:, None] * g[step] / g2[step][:, None]
+    raise ValueError("level-set Newton projection did not converge in 50 steps")
 
 
 # ----------------------------------------------------------------------------------------

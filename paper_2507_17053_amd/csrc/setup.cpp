@@ -198,24 +198,29 @@ double LevelSet::phi(const double *x) const {
 }
 
 // Level-set Newton projection onto {phi = 0} (the projection of Sec. 4.4): from x, repeat
-// x <- x - phi(x) grad phi(x) / |grad phi(x)|^2 until |phi| <= 1e-14 or 50 steps.  Returns false
-// if the tolerance was not met or the gradient vanished.
+// x <- x - phi(x) grad phi(x) / |grad phi(x)|^2 until the Newton step |phi| / |grad phi| is at
+// most 8 eps max(1, max_k |x_k|) (a few units in the last place of the point, whatever the
+// scaling of phi), at most 50 steps.  Returns false if that was not met or the gradient
+// vanished.
 static bool closest_newton(const LevelSet &L, const double *x, double *out) {
   const int d = L.dim;
+  const double eps = std::numeric_limits<double>::epsilon();
   double y[3] = {0.0, 0.0, 0.0}, g[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < d; ++k) y[k] = x[k];
   for (int it = 0; it <= 50; ++it) {
     const double ph = L.cb_phi(y, L.cb_user);
     if (!std::isfinite(ph)) break;
-    if (std::fabs(ph) <= 1e-14) {
+    L.cb_grad(y, g, L.cb_user);
+    double g2 = 0.0, ymax = 1.0;
+    for (int k = 0; k < d; ++k) {
+      g2 += g[k] * g[k];
+      ymax = std::max(ymax, std::fabs(y[k]));
+    }
+    if (std::fabs(ph) <= 8.0 * eps * std::sqrt(g2) * ymax) {
       for (int k = 0; k < d; ++k) out[k] = y[k];
       return true;
     }
-    if (it == 50) break;
-    L.cb_grad(y, g, L.cb_user);
-    double g2 = 0.0;
-    for (int k = 0; k < d; ++k) g2 += g[k] * g[k];
-    if (!(g2 > 0.0) || !std::isfinite(g2)) break;
+    if (it == 50 || !(g2 > 0.0) || !std::isfinite(g2)) break;
     for (int k = 0; k < d; ++k) y[k] -= ph * g[k] / g2;
   }
   for (int k = 0; k < d; ++k) out[k] = std::numeric_limits<double>::quiet_NaN();

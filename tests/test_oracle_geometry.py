@@ -152,13 +152,41 @@ def test_callback_newton_projection_is_exact_for_radial_level_sets():
 
 
 def test_callback_newton_projection_lands_on_the_boundary_or_fails():
-    """Implicit ellipse: every projected point has |phi| <= 1e-14; a level set without zeros
-    (phi = |x|^2 + 1) makes the projection raise."""
+    """Implicit ellipse: every projected point lies on the boundary to rounding (first-order
+    distance |phi| / |grad phi| <= 1e-14); a level set without zeros (phi = |x|^2 + 1) makes the
+    projection raise."""
     a = np.array([0.8, 0.45])
     ls = inputs.callback(lambda Y: np.sum((Y / a) ** 2, axis=1) - 1.0, lambda Y: 2.0 * Y / a ** 2, 2)
     X = np.random.default_rng(6).uniform(-1, 1, (100, 2))
     got = O.closest_point(ls, X)
-    assert np.abs(ls["phi"](got)).max() <= 1e-14
+    assert np.max(np.abs(ls["phi"](got)) / np.linalg.norm(ls["grad"](got), axis=1)) <= 1e-14
     none = inputs.callback(lambda Y: np.sum(Y ** 2, axis=1) + 1.0, lambda Y: 2.0 * Y, 2)
     with pytest.raises(ValueError):
         O.closest_point(none, X[:3])
+
+
+@pytest.mark.parametrize("case", ["scaled-distance", "squared-r10", "squared-c50-r30"])
+def test_callback_newton_projection_is_scale_aware(case):
+    """The Newton stop is relative to the point and the gradient, so level sets that are
+    scaled, or whose values are large near the boundary, project as accurately as a distance
+    function: 100 (|x - c| - r), |x|^2 - 10^2 and |x - (50, 50)|^2 - 30^2 all land on the exact
+    closest point of their circle (an absolute |phi| stop fails on many of these points)."""
+    rng = np.random.default_rng(11)
+    if case == "scaled-distance":
+        c, r = np.array([0.05, -0.03]), 0.75
+        phi = lambda Y: 100.0 * (np.linalg.norm(Y - c, axis=1) - r)
+        grad = lambda Y: 100.0 * (Y - c) / np.linalg.norm(Y - c, axis=1)[:, None]
+        X = rng.uniform(-1, 1, (300, 2))
+    elif case == "squared-r10":
+        c, r = np.array([0.0, 0.0]), 10.0
+        phi = lambda Y: np.sum((Y - c) ** 2, axis=1) - r * r
+        grad = lambda Y: 2.0 * (Y - c)
+        X = rng.uniform(-12, 12, (300, 2))
+    else:
+        c, r = np.array([50.0, 50.0]), 30.0
+        phi = lambda Y: np.sum((Y - c) ** 2, axis=1) - r * r
+        grad = lambda Y: 2.0 * (Y - c)
+        X = rng.uniform(15, 85, (300, 2))
+    exact = O.closest_point({"kind": "sphere", "centre": list(c), "radius": r}, X)
+    got = O.closest_point(inputs.callback(phi, grad, 2), X)
+    assert np.abs(got - exact).max() <= 1e-12 * max(1.0, np.abs(c).max() + r)

@@ -53,11 +53,43 @@ def _cb_ellipse_implicit():
     return inputs.callback(lambda X: np.sum((X / a) ** 2, axis=1) - 1.0, lambda X: 2.0 * X / a ** 2, 2)
 
 
+def _cb_scaled_distance():
+    """Disk r = 0.75 at (0.05, -0.03) as 100 (|x - c| - r): a distance function scaled by 100."""
+    c = np.array([0.05, -0.03])
+    return inputs.callback(lambda X: 100.0 * (np.linalg.norm(X - c, axis=1) - 0.75),
+                           lambda X: 100.0 * (X - c) / np.linalg.norm(X - c, axis=1)[:, None], 2)
+
+
+def _cb_big_squared(c, r):
+    """Circle of radius r at c as |x - c|^2 - r^2 (large values near the boundary)."""
+    c = np.asarray(c, dtype=np.float64)
+    return inputs.callback(lambda X: np.sum((X - c) ** 2, axis=1) - r * r, lambda X: 2.0 * (X - c), 2)
+
+
 CASES += [
     (2, 16, _cb_disk_squared(), 2, "cg"),
     (3, 10, _cb_torus_distance(), 3, "dg"),
     (2, 12, _cb_ellipse_implicit(), 3, "cg"),
+    (2, 16, _cb_scaled_distance(), 3, "cg"),
 ]
+
+# (mesh lo, hi) of the callback cases whose circles are far from [-1, 1]^2
+BIG = [((-12.0, 12.0), _cb_big_squared((0.0, 0.0), 10.0)),
+       ((15.0, 85.0), _cb_big_squared((50.0, 50.0), 30.0))]
+
+
+@pytest.mark.parametrize("lohi,ls", BIG, ids=["squared-r10", "squared-c50-r30"])
+def test_setup_with_large_squared_distance_matches_oracle(lohi, ls):
+    """Level sets whose values near the boundary are far from O(1): the scale-aware Newton
+    stop accepts every projected point (an absolute |phi| stop fails on many), and the
+    library's setup equals the oracle's."""
+    lo, hi = lohi
+    ref = O.setup(2, 20, lo, hi, ls, 2)
+    op = sbm.Operator(2, 20, lo, hi, ls, 2, host_only=True)
+    assert op.n_cells == ref.cells.shape[0] > 0
+    np.testing.assert_array_equal(op.export_sbm_faces(), ref.sbm_faces)
+    assert np.abs(op.export_face_xi() - ref.face_xi).max() <= 1e-12
+    op.close()
 
 
 @pytest.mark.parametrize("d,n,ls,p,disc", CASES)
