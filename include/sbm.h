@@ -100,10 +100,14 @@ typedef struct {
   double shift_scale;      /* d is scaled by this factor; 1 = the method, 0 = no shift */
   int flags;               /* SBM_SETUP_HOST_ONLY: build the host-side data only (no device
                               allocation; the handle then serves sbm_info, sbm_dof_points,
-                              sbm_rhs_points and the sbm_export_* calls, nothing else) */
+                              sbm_rhs_points and the sbm_export_* calls, nothing else);
+                              SBM_SETUP_HOST_BUILD: build the geometry, numbering and layout on
+                              host threads and upload them (the default for the analytic
+                              level-set kinds builds them with device kernels; results are
+                              identical; user level sets are always built on the host) */
 } sbm_options;
 
-enum { SBM_SETUP_HOST_ONLY = 1 };
+enum { SBM_SETUP_HOST_ONLY = 1, SBM_SETUP_HOST_BUILD = 2 };
 
 /*
  * sbm_setup -- build one operator (Sec. 3.4 data structures, Sec. 4.4 initialisation).

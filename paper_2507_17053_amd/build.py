@@ -22,7 +22,10 @@ LIB = os.path.join(HERE, "libsbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["setup.cpp", "kernels_apply.hip", "kernels_taylor.hip", "vec.hip", "solver.hip",
-           "apply_noalloc.hip"]
+           "apply_noalloc.hip", "setup_gpu.hip"]
+# per-file flags: the device setup evaluates the level sets with the same floating-point
+# operations as the host build (no multiply-add contraction), so both agree bit for bit
+EXTRA = {"setup_gpu.hip": ["-ffp-contract=off"], "setup.cpp": ["-ffp-contract=off"]}
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -31,7 +34,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-at
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + COMMON
+    cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + EXTRA.get(src, [])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/sbm.h"
+#include "levelset.h"
 
 namespace sbm {
 
@@ -43,6 +44,7 @@ struct LevelSet {
   void *cb_user = nullptr;
   double phi(const double *x) const;
   void closest(const double *x, double *out) const;  // exact closest point on {phi = 0}
+  LsParams params() const;                            // analytic kinds (host pointers)
 };
 
 // Kernel-side tables, passed by value (kernel arguments live in the constant kernarg
@@ -157,6 +159,16 @@ hipError_t launch_operator(const sbm_ctx *c, const void *u, void *v, int prec, i
 hipError_t launch_operator_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s);
 // Brick shape (cells per direction) used by the CG kernel for (dim, p).
 void brick_dims(int dim, int p, int *bx, int *by, int *bz);
+// Brick numbering from the per-slot cell and face counts of the brick grid: key_of[b] is the
+// grid slot of brick b, bid[slot] its brick number (-1 if empty).  Every one of the 8 XCD
+// ranges gets an equal share of the face-carrying bricks, first, then of the others (see
+// xcd_block).  Returns the number of face-carrying bricks.
+int64_t order_bricks(const std::vector<int32_t> &count, const std::vector<int32_t> &fcount,
+                     std::vector<int64_t> &key_of, std::vector<int32_t> &bid);
+// Setup on the device (setup_gpu.hip) for the analytic level-set kinds: after prepare(), builds
+// the geometry, the DoF numbering and the brick layout with kernels, fills the handle's arena
+// and the host copies (cells, faces, shifted and true points, runs).
+sbm_status device_setup(sbm_ctx *c);
 // Device bytes of the handle's solver workspace (0 before the first solve).
 size_t workspace_bytes(const sbm_ctx *c);
 // Vector kernels (vec.hip)

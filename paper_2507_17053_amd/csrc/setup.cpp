@@ -153,48 +153,32 @@ static double norm_d(const double *v, int d) {
   return std::sqrt(s);
 }
 
-double LevelSet::phi(const double *x) const {
-  const int d = dim;
-  switch (kind) {
-    case SBM_LS_SPHERE: {
-      double s = 0;
-      for (int k = 0; k < d; ++k) s += (x[k] - centre[k]) * (x[k] - centre[k]);
-      return std::sqrt(s) - radius;
-    }
-    case SBM_LS_ELLIPSOID: {
-      double s = 0;
-      for (int k = 0; k < d; ++k) {
-        const double t = (x[k] - centre[k]) / semi[k];
-        s += t * t;
-      }
-      return s - 1.0;
-    }
-    case SBM_LS_TORUS: {
-      const double y0 = x[0] - centre[0], y1 = x[1] - centre[1], y2 = x[2] - centre[2];
-      const double rho = std::sqrt(y0 * y0 + y1 * y1);
-      return std::sqrt((rho - R) * (rho - R) + y2 * y2) - r;
-    }
-    case SBM_LS_HALFSPACE: {
-      double s = 0;
-      for (int k = 0; k < d; ++k) s += normal[k] * x[k];
-      return s - offset;
-    }
-    case SBM_LS_SPHERE_UNION: {
-      double best = std::numeric_limits<double>::infinity();
-      for (size_t i = 0; i < rs.size(); ++i) {
-        double s = 0;
-        for (int k = 0; k < d; ++k) s += (x[k] - cs[3 * i + k]) * (x[k] - cs[3 * i + k]);
-        best = std::min(best, std::sqrt(s) - rs[i]);
-      }
-      return best;
-    }
-    case SBM_LS_CALLBACK: {
-      double xx[3] = {0.0, 0.0, 0.0};
-      for (int k = 0; k < d; ++k) xx[k] = x[k];
-      return cb_phi(xx, cb_user);
-    }
+LsParams LevelSet::params() const {
+  LsParams P;
+  P.kind = kind;
+  P.dim = dim;
+  for (int k = 0; k < 3; ++k) {
+    P.centre[k] = centre[k];
+    P.semi[k] = semi[k];
+    P.normal[k] = normal[k];
   }
-  return 0.0;
+  P.radius = radius;
+  P.R = R;
+  P.r = r;
+  P.offset = offset;
+  P.n_spheres = (int)rs.size();
+  P.cs = cs.data();
+  P.rs = rs.data();
+  return P;
+}
+
+double LevelSet::phi(const double *x) const {
+  if (kind == SBM_LS_CALLBACK) {
+    double xx[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < dim; ++k) xx[k] = x[k];
+    return cb_phi(xx, cb_user);
+  }
+  return ls_phi(params(), x);
 }
 
 // Level-set Newton projection onto {phi = 0} (the projection of Sec. 4.4): from x, repeat
@@ -227,251 +211,12 @@ static bool closest_newton(const LevelSet &L, const double *x, double *out) {
   return false;
 }
 
-// Ellipsoid: x_k = a_k^2 y_k / (a_k^2 + t) with t the largest root of
-// F(t) = sum (a_k y_k / (a_k^2 + t))^2 - 1, found by Newton from the left end of a bracket
-// (bisection if that fails).
-static void closest_ellipsoid(const double *a, const double *c, int d, const double *x, double *out) {
-  double y[3], a2[3];
-  double amin2 = std::numeric_limits<double>::infinity();
-  int kmin = 0;
-  for (int k = 0; k < d; ++k) {
-    y[k] = x[k] - c[k];
-    a2[k] = a[k] * a[k];
-    if (a2[k] < amin2) {
-      amin2 = a2[k];
-      kmin = k;
-    }
-  }
-  auto F = [&](double t) {
-    double s = 0;
-    for (int k = 0; k < d; ++k)
-      if (y[k] != 0.0) {
-        const double q = a[k] * y[k] / (a2[k] + t);
-        s += q * q;
-      }
-    return s - 1.0;
-  };
-  double lo = -amin2;
-  for (int k = 0; k < d; ++k)
-    if (y[k] != 0.0) lo = std::max(lo, -a2[k] + a[k] * std::fabs(y[k]));
-  double hs = 0;
-  for (int k = 0; k < d; ++k) hs += a2[k] * y[k] * y[k];
-  double hi = std::max(0.0, std::sqrt(hs));
-  if (lo == -amin2 && y[kmin] == 0.0 && F(lo) <= 0.0) {
-    double s = 0;
-    for (int k = 0; k < d; ++k) {
-      if (k == kmin) continue;
-      out[k] = a2[k] * y[k] / (a2[k] - amin2);
-      s += (out[k] / a[k]) * (out[k] / a[k]);
-    }
-    out[kmin] = a[kmin] * std::sqrt(std::max(0.0, 1.0 - s));
-    for (int k = 0; k < d; ++k) out[k] += c[k];
+void LevelSet::closest(const double *x, double *out) const {
+  if (kind == SBM_LS_CALLBACK) {
+    closest_newton(*this, x, out);
     return;
   }
-  // F is convex and decreasing on (-amin2, inf), and F(lo) >= 0 (a term with y_k != 0 is
-  // at least 1 at -a_k^2 + a_k |y_k|): a tangent lies below F, so Newton's method from lo
-  // moves right monotonically and never passes the root.  It stops when F reaches 0 or the
-  // step no longer moves t; bisection on [lo, hi] is the fallback.
-  double t = lo;
-  bool done = false;
-  for (int it = 0; it < 100; ++it) {
-    double f = -1.0, df = 0.0;
-    for (int k = 0; k < d; ++k)
-      if (y[k] != 0.0) {
-        const double den = a2[k] + t, q = a[k] * y[k] / den;
-        f += q * q;
-        df -= 2.0 * q * q / den;
-      }
-    if (!(f > 0.0)) {
-      done = f == 0.0 || it > 0;  // at or (by rounding) just past the root
-      break;
-    }
-    if (!(df < 0.0)) break;
-    const double tn = t - f / df;
-    if (!(tn > t) || !(tn <= hi)) {
-      done = !(tn > t);
-      break;
-    }
-    t = tn;
-  }
-  if (!done) {
-    for (int it = 0; it < 400; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (mid <= lo || mid >= hi) break;
-      if (F(mid) > 0.0)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    t = 0.5 * (lo + hi);
-  }
-  for (int k = 0; k < d; ++k) out[k] = c[k] + a2[k] * y[k] / (a2[k] + t);
-}
-
-// Union of balls: nearest among the critical points of the distance on every boundary
-// stratum (each sphere: nearest/farthest point; each pairwise circle: nearest/farthest
-// point, or the two intersection points in 2D; each triple point in 3D) that is not
-// strictly inside another ball.  Candidates are visited in a fixed order and the first
-// strict minimum wins.
-static void closest_union(const std::vector<double> &cs, const std::vector<double> &rs, int d,
-                          const double *x, double *out) {
-  const int S = (int)rs.size();
-  double best = std::numeric_limits<double>::infinity();
-  bool found = false;
-  auto consider = [&](const double *pt, int o0, int o1, int o2) {
-    for (int l = 0; l < S; ++l) {
-      if (l == o0 || l == o1 || l == o2) continue;
-      double s = 0;
-      for (int k = 0; k < d; ++k) s += (pt[k] - cs[3 * l + k]) * (pt[k] - cs[3 * l + k]);
-      if (std::sqrt(s) < rs[l]) return;
-    }
-    double s = 0;
-    for (int k = 0; k < d; ++k) s += (pt[k] - x[k]) * (pt[k] - x[k]);
-    const double dist = std::sqrt(s);
-    if (dist < best) {
-      best = dist;
-      found = true;
-      for (int k = 0; k < d; ++k) out[k] = pt[k];
-    }
-  };
-  // Every point of sphere i is at least lb[i] = | |x - c_i| - r_i | from x, so a seam or triple
-  // point of spheres whose bounds exceed the best distance so far (with a margin far above
-  // rounding) cannot be selected and is skipped: the result is that of the full enumeration.
-  std::vector<double> lb(S);
-  for (int i = 0; i < S; ++i) {
-    double u[3];
-    for (int k = 0; k < d; ++k) u[k] = x[k] - cs[3 * i + k];
-    lb[i] = std::fabs(norm_d(u, d) - rs[i]);
-  }
-  auto hopeless = [&](double bound) { return bound > best * (1.0 + 1e-12) + 1e-300; };
-  double pt[3];
-  for (int i = 0; i < S; ++i) {
-    double u[3];
-    for (int k = 0; k < d; ++k) u[k] = x[k] - cs[3 * i + k];
-    double nu = norm_d(u, d);
-    if (nu == 0.0) {
-      for (int k = 0; k < d; ++k) u[k] = 0.0;
-      u[0] = 1.0;
-      nu = 1.0;
-    }
-    for (int k = 0; k < d; ++k) pt[k] = cs[3 * i + k] + rs[i] * u[k] / nu;
-    consider(pt, i, -1, -1);
-    for (int k = 0; k < d; ++k) pt[k] = cs[3 * i + k] - rs[i] * u[k] / nu;
-    consider(pt, i, -1, -1);
-  }
-  for (int i = 0; i < S; ++i)
-    for (int j = i + 1; j < S; ++j) {
-      if (hopeless(std::max(lb[i], lb[j]))) continue;
-      double e[3];
-      for (int k = 0; k < d; ++k) e[k] = cs[3 * j + k] - cs[3 * i + k];
-      const double D = norm_d(e, d);
-      if (!(std::fabs(rs[i] - rs[j]) < D && D < rs[i] + rs[j])) continue;
-      for (int k = 0; k < d; ++k) e[k] /= D;
-      const double t = (D * D + rs[i] * rs[i] - rs[j] * rs[j]) / (2.0 * D);
-      const double rho = std::sqrt(rs[i] * rs[i] - t * t);
-      double m[3];
-      for (int k = 0; k < d; ++k) m[k] = cs[3 * i + k] + t * e[k];
-      if (d == 2) {
-        const double perp[2] = {-e[1], e[0]};
-        for (int k = 0; k < 2; ++k) pt[k] = m[k] + rho * perp[k];
-        consider(pt, i, j, -1);
-        for (int k = 0; k < 2; ++k) pt[k] = m[k] - rho * perp[k];
-        consider(pt, i, j, -1);
-      } else {
-        double w[3], ym[3];
-        for (int k = 0; k < 3; ++k) ym[k] = x[k] - m[k];
-        const double pr = ym[0] * e[0] + ym[1] * e[1] + ym[2] * e[2];
-        for (int k = 0; k < 3; ++k) w[k] = ym[k] - pr * e[k];
-        double nw = norm_d(w, 3);
-        if (nw == 0.0) {
-          double a3[3] = {0, 0, 0};
-          int km = 0;
-          for (int k = 1; k < 3; ++k)
-            if (std::fabs(e[k]) < std::fabs(e[km])) km = k;
-          a3[km] = 1.0;
-          const double ad = a3[0] * e[0] + a3[1] * e[1] + a3[2] * e[2];
-          for (int k = 0; k < 3; ++k) w[k] = a3[k] - ad * e[k];
-          nw = norm_d(w, 3);
-        }
-        for (int k = 0; k < 3; ++k) pt[k] = m[k] + rho * w[k] / nw;
-        consider(pt, i, j, -1);
-        for (int k = 0; k < 3; ++k) pt[k] = m[k] - rho * w[k] / nw;
-        consider(pt, i, j, -1);
-      }
-    }
-  if (d == 3) {
-    for (int i = 0; i < S; ++i)
-      for (int j = i + 1; j < S; ++j)
-        for (int l = j + 1; l < S; ++l) {
-          if (hopeless(std::max({lb[i], lb[j], lb[l]}))) continue;
-          // three-sphere intersection in the frame (ex, ey, ez) anchored at c_i
-          const double *c1 = &cs[3 * i], *c2 = &cs[3 * j], *c3 = &cs[3 * l];
-          double ex[3], ey[3], ez[3];
-          for (int k = 0; k < 3; ++k) ex[k] = c2[k] - c1[k];
-          const double dd = norm_d(ex, 3);
-          if (dd == 0.0) continue;
-          for (int k = 0; k < 3; ++k) ex[k] /= dd;
-          double c31[3];
-          for (int k = 0; k < 3; ++k) c31[k] = c3[k] - c1[k];
-          const double ii = ex[0] * c31[0] + ex[1] * c31[1] + ex[2] * c31[2];
-          for (int k = 0; k < 3; ++k) ey[k] = c31[k] - ii * ex[k];
-          const double ney = norm_d(ey, 3);
-          if (ney == 0.0) continue;
-          for (int k = 0; k < 3; ++k) ey[k] /= ney;
-          ez[0] = ex[1] * ey[2] - ex[2] * ey[1];
-          ez[1] = ex[2] * ey[0] - ex[0] * ey[2];
-          ez[2] = ex[0] * ey[1] - ex[1] * ey[0];
-          const double jj = ey[0] * c31[0] + ey[1] * c31[1] + ey[2] * c31[2];
-          const double r1 = rs[i], r2 = rs[j], r3 = rs[l];
-          const double xx = (r1 * r1 - r2 * r2 + dd * dd) / (2.0 * dd);
-          const double yy = (r1 * r1 - r3 * r3 + ii * ii + jj * jj) / (2.0 * jj) - (ii / jj) * xx;
-          const double z2 = r1 * r1 - xx * xx - yy * yy;
-          if (z2 <= 0.0) continue;
-          const double zz = std::sqrt(z2);
-          for (int sgn = 1; sgn >= -1; sgn -= 2) {
-            for (int k = 0; k < 3; ++k) pt[k] = c1[k] + xx * ex[k] + yy * ey[k] + sgn * zz * ez[k];
-            consider(pt, i, j, l);
-          }
-        }
-  }
-  if (!found)
-    for (int k = 0; k < d; ++k) out[k] = std::numeric_limits<double>::quiet_NaN();
-}
-
-void LevelSet::closest(const double *x, double *out) const {
-  const int d = dim;
-  switch (kind) {
-    case SBM_LS_SPHERE: {
-      double u[3];
-      for (int k = 0; k < d; ++k) u[k] = x[k] - centre[k];
-      const double nu = norm_d(u, d);
-      for (int k = 0; k < d; ++k) out[k] = centre[k] + radius * u[k] / nu;
-      return;
-    }
-    case SBM_LS_ELLIPSOID:
-      closest_ellipsoid(semi, centre, d, x, out);
-      return;
-    case SBM_LS_TORUS: {
-      const double y0 = x[0] - centre[0], y1 = x[1] - centre[1], y2 = x[2] - centre[2];
-      const double rho = std::sqrt(y0 * y0 + y1 * y1);
-      const double core[3] = {R * y0 / rho, R * y1 / rho, 0.0};
-      const double u[3] = {y0 - core[0], y1 - core[1], y2 - core[2]};
-      const double nu = norm_d(u, 3);
-      for (int k = 0; k < 3; ++k) out[k] = centre[k] + core[k] + r * u[k] / nu;
-      return;
-    }
-    case SBM_LS_HALFSPACE: {
-      const double ph = phi(x);
-      for (int k = 0; k < d; ++k) out[k] = x[k] - ph * normal[k];
-      return;
-    }
-    case SBM_LS_SPHERE_UNION:
-      closest_union(cs, rs, d, x, out);
-      return;
-    case SBM_LS_CALLBACK:
-      closest_newton(*this, x, out);
-      return;
-  }
+  ls_closest(params(), x, out);
 }
 
 }  // namespace sbm
@@ -539,6 +284,32 @@ static void free_device(sbm_ctx *c) {
 // workgroup each), list each brick's cells and surrogate faces, and describe every
 // lattice row of the brick box by (id of its first DoF, mask of points that are DoFs,
 // mask of points touched by the brick's own cells).  id: global lattice -> DoF id or -1.
+namespace sbm {
+int64_t order_bricks(const std::vector<int32_t> &count, const std::vector<int32_t> &fcount,
+                     std::vector<int64_t> &key_of, std::vector<int32_t> &bid) {
+  std::vector<int64_t> with_f, without_f;
+  for (size_t k = 0; k < count.size(); ++k)
+    if (count[k] > 0) (fcount[k] > 0 ? with_f : without_f).push_back((int64_t)k);
+  const int64_t nbt = (int64_t)(with_f.size() + without_f.size());
+  const int64_t nwf = (int64_t)with_f.size();
+  bid.assign(count.size(), -1);
+  key_of.clear();
+  key_of.reserve(nbt);
+  const int64_t per = nbt / 8, rem = nbt % 8;
+  int64_t fi = 0, gi = 0;
+  for (int x = 0; x < 8; ++x) {
+    const int64_t size = per + (x < rem ? 1 : 0);
+    const int64_t fend = std::min<int64_t>(nwf * (x + 1) / 8, fi + size);
+    int64_t k = 0;
+    for (; fi < fend; ++fi, ++k) key_of.push_back(with_f[fi]);
+    for (; k < size && gi < (int64_t)without_f.size(); ++gi, ++k) key_of.push_back(without_f[gi]);
+    for (; k < size; ++fi, ++k) key_of.push_back(with_f[fi]);  // only if the others ran out
+  }
+  for (size_t b = 0; b < key_of.size(); ++b) bid[key_of[b]] = (int32_t)b;
+  return nwf;
+}
+}  // namespace sbm
+
 static void build_bricks(sbm_ctx *c, const std::vector<int32_t> &id, int64_t lx, int64_t ly, int64_t lz) {
   const int d = c->dim, p = c->p;
   int BX, BY, BZ;
@@ -568,30 +339,11 @@ static void build_bricks(sbm_ctx *c, const std::vector<int32_t> &id, int64_t lx,
   // order (neighbouring bricks share an L2).
   std::vector<int32_t> fcount(count.size(), 0);
   for (int64_t f = 0; f < c->n_sbm; ++f) ++fcount[bkey[c->faces[3 * f]]];
-  std::vector<int64_t> with_f, without_f;
-  for (size_t k = 0; k < count.size(); ++k)
-    if (count[k] > 0) (fcount[k] > 0 ? with_f : without_f).push_back((int64_t)k);
-  const int64_t nbt = (int64_t)(with_f.size() + without_f.size());
-  const int64_t nwf = (int64_t)with_f.size();
-  std::vector<int32_t> bid(count.size(), -1);
+  std::vector<int32_t> bid;
   std::vector<int64_t> key_of;
-  key_of.reserve(nbt);
-  {
-    const int64_t per = nbt / 8, rem = nbt % 8;
-    int64_t fi = 0, gi = 0;
-    for (int x = 0; x < 8; ++x) {
-      const int64_t size = per + (x < rem ? 1 : 0);
-      const int64_t fend = std::min<int64_t>(nwf * (x + 1) / 8, fi + size);
-      int64_t k = 0;
-      for (; fi < fend; ++fi, ++k) key_of.push_back(with_f[fi]);
-      for (; k < size && gi < (int64_t)without_f.size(); ++gi, ++k) key_of.push_back(without_f[gi]);
-      for (; k < size; ++fi, ++k) key_of.push_back(with_f[fi]);  // only if the others ran out
-    }
-  }
+  c->n_bricks_faces = order_bricks(count, fcount, key_of, bid);
   const int32_t nb = (int32_t)key_of.size();
-  for (int32_t b = 0; b < nb; ++b) bid[key_of[b]] = b;
   c->n_bricks = nb;
-  c->n_bricks_faces = nwf;
   auto cell_loc = [&](int64_t r, int64_t key) {
     const int32_t *cc = &c->cells[r * d];
     const int64_t bx = key % nbx, by = (key / nbx) % nby, bz = key / (nbx * nby);
@@ -747,8 +499,9 @@ void free_workspace(sbm_ctx *c);  // solver.hip
 }
 
 // Host part of the setup; separate so that tests can exercise it without a device.
-static sbm_status host_setup(sbm_ctx *c, const sbm_mesh *mesh, const sbm_levelset *ls, int p, int disc,
-                             const sbm_options *opts) {
+// Validation and the per-operator parameters (mesh, penalties, level set, 1D rules).
+static sbm_status prepare(sbm_ctx *c, const sbm_mesh *mesh, const sbm_levelset *ls, int p, int disc,
+                          const sbm_options *opts) {
   if (!mesh || !ls) {
     set_error("sbm_setup: NULL mesh or level set");
     return SBM_EINVAL;
@@ -866,10 +619,21 @@ static sbm_status host_setup(sbm_ctx *c, const sbm_mesh *mesh, const sbm_levelse
       return SBM_EINVAL;
   }
   c->rules = make_rules(p);
-  const Rules1D &R = c->rules;
   const int n1 = p + 1;
   c->nb = (d == 3) ? n1 * n1 * n1 : n1 * n1;
   c->nq_face = (d == 3) ? n1 * n1 : n1;
+  return SBM_OK;
+}
+
+// Geometry and numbering on the host: active cells, faces, closest points, DoF numbering and
+// (CG) the brick layout.  Used for user level sets (SBM_LS_CALLBACK), for host-only handles and
+// when SBM_SETUP_HOST_BUILD asks for it; the analytic kinds are built on the device otherwise
+// (setup_gpu.hip), with identical results.
+static sbm_status host_geometry(sbm_ctx *c) {
+  const int d = c->dim, p = c->p, disc = c->disc;
+  const LevelSet &L = c->ls;
+  const Rules1D &R = c->rules;
+  const int n1 = p + 1;
   const int np = c->nq_face;  // runs per cell = face points
 
   // ---- vertex values and active cells (phi < 0 at all 2^d vertices) ----
@@ -1048,8 +812,22 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
     return SBM_ENOMEM;
   }
   sbm_status st;
+  const int flags = opts ? opts->flags : 0;
+  const bool on_device = !(flags & (SBM_SETUP_HOST_ONLY | SBM_SETUP_HOST_BUILD)) && ls &&
+                         ls->kind != SBM_LS_CALLBACK;
   try {
-    st = host_setup(c, mesh, ls, p, disc, opts);
+    st = prepare(c, mesh, ls, p, disc, opts);
+    if (st == SBM_OK && on_device) {
+      st = sbm::device_setup(c);
+      if (st == SBM_OK) {
+        *out = c;
+        return SBM_OK;
+      }
+      free_device(c);
+      delete c;
+      return st;
+    }
+    if (st == SBM_OK) st = host_geometry(c);
   } catch (const std::bad_alloc &) {
     set_error("sbm_setup: out of host memory");
     st = SBM_ENOMEM;
@@ -1062,7 +840,7 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
     delete c;
     return st;
   }
-  if (opts && (opts->flags & SBM_SETUP_HOST_ONLY)) {
+  if (flags & SBM_SETUP_HOST_ONLY) {
     c->host_only = true;
     *out = c;
     return SBM_OK;
