@@ -144,20 +144,11 @@ def configs_section(torch, sbm, inputs, steps, graph_batch):
     return out
 
 
-TAYLOR_SOLVES = [
-    # (name, workload, overrides, max_it): shifted GMRES(64) to 1e-10, default extension vs E_1
-    ("sphere3d_q2_n32", "sphere3d_q4", {"p": 2, "n": 32}, 1500),
-    ("sphere3d_q4", "sphere3d_q4", {}, 600),
-    ("torus3d_dg_q3", "torus3d_dg", {}, 1000),
-]
-
-
 def taylor_section(torch, sbm, inputs, op, vecs, steps, graph_batch):
     """The truncated Taylor extension E_m (sbm_set_extension_order) on the headline operator:
-    apply time for m = 1 and m = p against the default extension (FP64 and FP32), then
-    shifted GMRES(64) solves with E_1 against the default (status, iterations, residual
-    reached, seconds)."""
-    out = {"workload": "sphere3d_q4", "apply": {}, "solves": []}
+    apply time for m = 1 and m = p against the default extension (FP64 and FP32); its solves
+    are in the solve section."""
+    out = {"workload": "sphere3d_q4", "apply": {}}
     for m in (None, 1, op.p):
         op.set_extension_order(m)
         rec = {}
@@ -170,24 +161,6 @@ def taylor_section(torch, sbm, inputs, op, vecs, steps, graph_batch):
         print(f"# taylor apply m={m}: f64 {rec['f64']['ms_per_apply']:.4f} ms, f32 {rec['f32']['ms_per_apply']:.4f} ms",
               file=sys.stderr, flush=True)
     op.set_extension_order(None)
-    for name, wname, over, max_it in TAYLOR_SOLVES:
-        w = inputs.workload(wname, **over)
-        sop = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"])
-        u_fn, f_fn = inputs.manufactured(w["d"])
-        cq, bp = sop.rhs_points()
-        b = torch.empty(sop.n_dofs, dtype=torch.float64, device="cuda")
-        sop.rhs(f_fn(cq.reshape(-1, w["d"])), u_fn(bp.reshape(-1, w["d"])), b)
-        rec = {"case": name, "n_dofs": sop.n_dofs, "max_it": max_it}
-        for m in (None, 1):
-            sop.set_extension_order(m)
-            x = torch.zeros_like(b)
-            info = sop.solve(b, x, rel_tol=1e-10, max_it=max_it, mode="gmres", restart=64)
-            rec["default" if m is None else f"m{m}"] = {
-                "status": sbm.status_name(info["status"]), "krylov_its": info["inner_its"],
-                "rel_residual": info["rel_residual"], "seconds": info["seconds"]}
-        print(f"# taylor solve {name}: {rec}", file=sys.stderr, flush=True)
-        out["solves"].append(rec)
-        sop.close()
     return out
 
 
@@ -231,43 +204,59 @@ def cpu_baseline(w, budget_s=12.0):
 
 
 SOLVE_CASES = [
-    # (name, workload, overrides, shift_scale, (FP64 mode, mixed modes...), max_it)
-    ("disk2d_q2", "disk2d_q2", {}, 1.0, ("gmres", "gmres_ir"), 8000),
-    ("sphere3d_q1_n64", "sphere3d_q4", {"p": 1}, 1.0, ("gmres", "gmres_ir"), 4000),
-    # the symmetric limit of the 3D Q4 workload (shift 0): CG applies, full size
-    ("sphere3d_q4_unshifted", "sphere3d_q4", {}, 0.0, ("cg", "cg_ir", "cg_rr"), 4000),
-    # the shifted 3D Q4 workload: restarted GMRES stagnates (indefinite operator); reported
-    ("sphere3d_q4", "sphere3d_q4", {}, 1.0, ("gmres", "gmres_ir"), 300),
+    # (name, workload, overrides, shift_scale, extension order, modes, max_it)
+    # converging shifted cases (GMRES(64) in FP64 vs FP32 GMRES in FP64 refinement)
+    ("disk2d_q2", "disk2d_q2", {}, 1.0, None, ("gmres", "gmres_ir"), 8000),
+    ("sphere3d_q1_n64", "sphere3d_q4", {"p": 1}, 1.0, None, ("gmres", "gmres_ir"), 4000),
+    # the 3D workloads with the method's extension: restarted GMRES stagnates (the operator is
+    # near-singular and indefinite); the residual reached is reported
+    ("sphere3d_q4", "sphere3d_q4", {}, 1.0, None, ("gmres", "gmres_ir"), 300),
+    ("torus3d_dg_q3", "torus3d_dg", {}, 1.0, None, ("gmres", "gmres_ir"), 300),
+    ("spheres3d_q6", "spheres3d_q6", {}, 1.0, None, ("gmres", "gmres_ir"), 300),
+    # the same with the first-order extension E_1
+    ("sphere3d_q2_n32_E1", "sphere3d_q4", {"p": 2, "n": 32}, 1.0, 1, ("gmres", "gmres_ir"), 1500),
+    ("sphere3d_q4_E1", "sphere3d_q4", {}, 1.0, 1, ("gmres", "gmres_ir"), 600),
+    ("torus3d_dg_q3_E1", "torus3d_dg", {}, 1.0, 1, ("gmres", "gmres_ir"), 600),
+    ("spheres3d_q6_E1", "spheres3d_q6", {}, 1.0, 1, ("gmres", "gmres_ir"), 600),
+    # the symmetric limit (shift 0) of the 3D CG workloads at full size: CG converges
+    ("sphere3d_q4_unshifted", "sphere3d_q4", {}, 0.0, None, ("cg", "cg_ir", "cg_rr"), 4000),
+    ("spheres3d_q6_unshifted", "spheres3d_q6", {}, 0.0, None, ("cg", "cg_ir", "cg_rr"), 4000),
 ]
 
 
 def solve_section(torch, sbm, inputs):
-    """FP64 Krylov vs FP64 refinement around the same Krylov method in FP32, to 1e-10: GMRES(64)
-    for the shifted (nonsymmetric) operators, CG for the symmetric limit."""
+    """FP64 Krylov vs FP64 refinement around the same Krylov method in FP32, to 1e-10 relative
+    residual: GMRES(64) for the shifted (nonsymmetric) operators, CG for the symmetric limit.
+    Per run: status, time, iterations, the FP64 residual reached and the L2 error of the
+    solution against the manufactured solution (sbm_l2_error)."""
     out = []
-    for name, wname, over, shift, modes, max_it in SOLVE_CASES:
+    for name, wname, over, shift, order, modes, max_it in SOLVE_CASES:
         w = inputs.workload(wname, **over)
         op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"],
-                          shift_scale=shift)
+                          shift_scale=shift, taylor_order=order)
         u_fn, f_fn = inputs.manufactured(w["d"])
         cq, bp = op.rhs_points()
+        ustar = u_fn(cq.reshape(-1, w["d"]))
         b = torch.empty(op.n_dofs, dtype=torch.float64, device="cuda")
         op.rhs(f_fn(cq.reshape(-1, w["d"])), u_fn(bp.reshape(-1, w["d"])), b)
-        rec = {"case": name, "n_dofs": op.n_dofs, "shift_scale": shift}
+        rec = {"case": name, "n_dofs": op.n_dofs, "p": w["p"], "disc": w["disc"], "shift_scale": shift,
+               "extension": "full" if order is None else f"E_{order}", "max_it": max_it}
         for mode in modes:
             x = torch.zeros_like(b)
             info = op.solve(b, x, rel_tol=1e-10, max_it=max_it, mode=mode, restart=64)
             rec[mode] = {"status": sbm.status_name(info["status"]), "seconds": info["seconds"],
                          "krylov_its": info["inner_its"], "refinements": info["outer_its"],
                          "applies_f64": info["applies_f64"], "applies_f32": info["applies_f32"],
-                         "rel_residual_f64": info["rel_residual"]}
-            print(f"solve {name} {mode}: {rec[mode]}", file=sys.stderr, flush=True)
+                         "rel_residual_f64": info["rel_residual"], "l2_error": op.l2_error(x, ustar)}
+            print(f"# solve {name} {mode}: {rec[mode]}", file=sys.stderr, flush=True)
         g = rec[modes[0]]
         for mode in modes[1:]:
             if g["status"] == "SBM_OK" and rec[mode]["status"] == "SBM_OK":
-                rec[f"{mode}_speedup"] = g["seconds"] / rec[mode]["seconds"]
+                rec[f"{mode}_speedup_vs_{modes[0]}"] = g["seconds"] / rec[mode]["seconds"]
         out.append(rec)
         op.close()
+        del b
+        torch.cuda.empty_cache()
     return out
 
 
@@ -329,7 +318,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' applies")
-    ap.add_argument("--solve", action="store_true", help="also time the FP64 and FP32+IR solves")
+    ap.add_argument("--no-solve", action="store_true", help="skip the FP64 vs FP32+refinement solves")
     ap.add_argument("--no-taylor", action="store_true", help="skip the truncated-Taylor extension section")
     ap.add_argument("--profile-run", action="store_true", help="few eager applies + copies (counter runs)")
     ap.add_argument("--profile-order", type=int, default=None,
@@ -420,12 +409,16 @@ def main():
                  "brick_kernel_frac": res["f32"]["b_brick"] / res["f32"]["t_brick"] / 1e9 / HBM_PEAK_GBS},
         "setup_s": t_setup,
     }
+    # setup again on a warm process (the first one also loads the library's kernels)
+    t0 = time.perf_counter()
+    sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"]).close()
+    out["setup_warm_s"] = time.perf_counter() - t0
     if not args.no_taylor:
         out["taylor_extension"] = taylor_section(torch, sbm, inputs, op, {"f64": (u64, v64), "f32": (u32, v32)},
                                                  min(args.steps, 200), gb)
     if not args.no_configs:
         out["other_configs"] = configs_section(torch, sbm, inputs, min(args.steps, 200), gb)
-    if args.solve:
+    if not args.no_solve:
         out["solve"] = solve_section(torch, sbm, inputs)
     if args.serve > 0:
         out["serving"] = serve_section(args.serve, args.serve_max_it, args.serve_rate, slots=12, budget_gb=96.0)

@@ -237,6 +237,14 @@ sbm_status sbm_rhs_points(sbm_handle h, double *cell_qp, double *bdry_pts);
  */
 sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double *b, void *stream);
 
+/*
+ * sbm_l2_error -- the L2 error ||u_h - u*|| on the surrogate domain of the FP64 device vector x
+ * (the error measure of App. A), by each cell's (p+1)^d-point Gauss rule: u* is given at the
+ * cell_qp points of sbm_rhs_points (host array, n_cells x (p+1)^d, evaluated by the caller).
+ * Synchronous (copies x to the host).  Errors: EINVAL (NULL argument, host-only handle), EHIP.
+ */
+sbm_status sbm_l2_error(sbm_handle h, const double *x, const double *ustar_qp, double *err);
+
 /* Solver selection for sbm_solve. */
 enum {
   SBM_SOLVE_GMRES_F64 = 0,  /* restarted GMRES(m) in FP64 */

@@ -929,6 +929,63 @@ using namespace sbm;
 
 extern "C" {
 
+sbm_status sbm_l2_error(sbm_handle h, const double *x, const double *ustar_qp, double *err) {
+  if (!h || !ustar_qp || !err || (h->n_dofs > 0 && !x) || h->host_only) {
+    set_error("sbm_l2_error: NULL argument or host-only handle");
+    return SBM_EINVAL;
+  }
+  *err = 0.0;
+  const int d = h->dim, n1 = h->n1, nb = h->nb, np = h->nq_face;
+  const Rules1D &R = h->rules;
+  const int64_t nc = h->n_cells;
+  if (nc == 0) return SBM_OK;
+  std::vector<double> xh(h->n_dofs);
+  SBM_HIP_CHECK(hipMemcpy(xh.data(), x, sizeof(double) * h->n_dofs, hipMemcpyDeviceToHost));
+  // per cell: u_K at the GLL nodes -> values at the (p+1)^d Gauss points (N along each axis),
+  // then sum_q W_q h^d (u_h - u*)^2; partial sums per cell, added in cell order
+  std::vector<double> part(nc);
+  auto cells = [&](int64_t r0, int64_t r1) {
+    std::vector<double> A(nb), B(nb);
+    for (int64_t r = r0; r < r1; ++r) {
+      for (int i = 0; i < nb; ++i)
+        A[i] = xh[(h->disc == SBM_CG) ? (int64_t)h->runs[r * np + i / n1] + i % n1 : r * nb + i];
+      double *src = A.data(), *dst = B.data();
+      int st = 1;
+      for (int m = 0; m < d; ++m) {
+        for (int idx = 0; idx < nb; ++idx) {
+          const int q = (idx / st) % n1, base = idx - q * st;
+          double acc = 0.0;
+          for (int j = 0; j < n1; ++j) acc += R.N[q * n1 + j] * src[base + j * st];
+          dst[idx] = acc;
+        }
+        std::swap(src, dst);
+        st *= n1;
+      }
+      double s = 0.0;
+      for (int q = 0; q < nb; ++q) {
+        const int qk[3] = {q % n1, (q / n1) % n1, q / (n1 * n1)};
+        double w = 1.0;
+        for (int m = 0; m < d; ++m) w *= R.w[qk[m]] * h->h;
+        const double e = src[q] - ustar_qp[r * nb + q];
+        s += w * e * e;
+      }
+      part[r] = s;
+    }
+  };
+  const int64_t nt = std::max<int64_t>(1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 16, nc / 1024}));
+  if (nt <= 1) {
+    cells(0, nc);
+  } else {
+    std::vector<std::thread> pool;
+    for (int64_t t = 0; t < nt; ++t) pool.emplace_back([&, t] { cells(nc * t / nt, nc * (t + 1) / nt); });
+    for (auto &th : pool) th.join();
+  }
+  double tot = 0.0;
+  for (int64_t r = 0; r < nc; ++r) tot += part[r];
+  *err = std::sqrt(tot);
+  return SBM_OK;
+}
+
 sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double *b, void *stream) {
   if (!h || !f_qp || !b || (h->n_sbm > 0 && !g_bp) || h->host_only) {
     set_error("sbm_rhs: NULL argument or host-only handle");

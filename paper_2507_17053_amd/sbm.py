@@ -86,6 +86,7 @@ _lib.sbm_rhs.argtypes = [_P, _P, _P, _P, _P]
 _lib.sbm_solve.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                            _P, ctypes.POINTER(SolveInfo)]
 _lib.sbm_diagonal.argtypes = [_P, _P, ctypes.c_int, _P]
+_lib.sbm_l2_error.argtypes = [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]
 _lib.sbm_set_extension_order.argtypes = [_P, ctypes.c_int]
 _lib.sbm_footprint_estimate.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                         ctypes.c_int64]
@@ -98,7 +99,7 @@ _lib.sbm_layout_stats.argtypes = [_P, _I64P, _I64P, _I64P]
 EXPORTED = ["sbm_setup", "sbm_info", "sbm_destroy", "sbm_last_error", "sbm_apply", "sbm_apply_noalloc",
             "sbm_apply_parts",
             "sbm_apply_batch", "sbm_layout_stats",
-            "sbm_dof_points", "sbm_rhs_points", "sbm_rhs", "sbm_solve", "sbm_diagonal",
+            "sbm_dof_points", "sbm_rhs_points", "sbm_rhs", "sbm_l2_error", "sbm_solve", "sbm_diagonal",
             "sbm_footprint_estimate", "sbm_export_cells", "sbm_export_sbm_faces", "sbm_export_face_xi",
             "sbm_export_cell_dofs"]
 
@@ -300,6 +301,16 @@ class Operator:
         f_qp = np.ascontiguousarray(f_qp, dtype=np.float64)
         g_bp = np.ascontiguousarray(g_bp, dtype=np.float64)
         _check(_lib.sbm_rhs(self._h, _hptr(f_qp), _hptr(g_bp), _dptr(out), _stream_ptr(stream)), "sbm_rhs")
+
+    def l2_error(self, x, ustar_qp):
+        """sbm_l2_error: ||u_h - u*|| for the FP64 device vector x, u* given at the cell Gauss
+        points of rhs_points() (array n_cells x (p+1)^d)."""
+        u = np.ascontiguousarray(ustar_qp, dtype=np.float64).reshape(-1)
+        if u.size != self.n_cells * self.nb:
+            raise ValueError("ustar_qp must have n_cells x (p+1)^d entries")
+        out = ctypes.c_double()
+        _check(_lib.sbm_l2_error(self._h, _dptr(x), _hptr(u), ctypes.byref(out)), "sbm_l2_error")
+        return out.value
 
     def solve(self, b, x, rel_tol=1e-10, max_it=10000, mode="gmres", restart=50, jacobi=False, stream=None):
         """sbm_solve: A x = b to rel_tol from the initial x (FP64 device tensors of n_dofs).

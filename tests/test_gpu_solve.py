@@ -258,3 +258,68 @@ def test_long_restart_at_size_matches_torch_gmres(mode):
         assert abs(rel - rel_ref) <= 1e-6 * rel_ref, (rel, rel_ref)
     else:
         assert rel <= max(2 * rel_ref, 1e-5), (rel, rel_ref)
+
+
+@pytest.mark.parametrize("d,n,ls,p,disc", [(2, 12, DISK, 3, "cg"), (3, 6, inputs.sphere((0, 0, 0), 0.75), 2, "dg"),
+                                           (3, 8, inputs.sphere_union(1), 4, "cg")])
+def test_l2_error_matches_oracle_exactly_for_polynomials(d, n, ls, p, disc):
+    """sbm_l2_error against the oracle's L2 error: with u* a random polynomial of degree p in
+    each coordinate and any u_h, (u_h - u*)^2 has degree 2p per coordinate, so both Gauss rules
+    ((p+1)^d points in the library, (p+3)^d in the oracle) integrate it exactly."""
+    ref = O.setup(d, n, -1.0, 1.0, ls, p, disc=disc)
+    op = sbm.Operator(d, n, -1.0, 1.0, ls, p, disc=disc)
+    rng = np.random.default_rng(4)
+    coef = rng.uniform(-1, 1, [p + 1] * d)
+
+    def ustar(X):
+        out = np.zeros(X.shape[0])
+        for idx in np.ndindex(*coef.shape):
+            term = np.full(X.shape[0], coef[idx])
+            for k in range(d):
+                term = term * X[:, k] ** idx[k]
+            out += term
+        return out
+
+    x = inputs.uniform_vector(op.n_dofs, seed=3)
+    cq, _ = op.rhs_points()
+    e = op.l2_error(torch.from_numpy(x).cuda(), ustar(cq.reshape(-1, d)))
+    e_ref = O.l2_error(ref, x, ustar)
+    assert abs(e - e_ref) <= 1e-12 * e_ref, (e, e_ref)
+    # the interpolant of u* itself has zero error
+    xi = O.interpolate(ref, ustar)
+    assert op.l2_error(torch.from_numpy(xi).cuda(), ustar(cq.reshape(-1, d))) <= 1e-12 * np.abs(xi).max()
+
+
+# downsized versions of the 3D workloads (the largest the oracle's direct solver takes)
+DOWNSIZED = [
+    ("sphere-q4 (64^3 workload at 8^3)", 3, 8, inputs.sphere((0, 0, 0), 0.75), 4, "cg", None),
+    ("spheres-q6 (48^3 workload at 12^3)", 3, 12, inputs.sphere_union(1), 6, "cg", None),
+    ("torus-dg-q3 (32^3 workload at 12^3)", 3, 12, inputs.torus(0.6, 0.25), 3, "dg", None),
+    ("sphere-q4 E_1", 3, 8, inputs.sphere((0, 0, 0), 0.75), 4, "cg", 1),
+    ("sphere-q2 E_1", 3, 12, inputs.sphere((0, 0, 0), 0.75), 2, "cg", 1),
+]
+
+
+@pytest.mark.parametrize("name,d,n,ls,p,disc,m", DOWNSIZED, ids=[c[0] for c in DOWNSIZED])
+def test_downsized_workload_solves_against_oracle_direct_solution(name, d, n, ls, p, disc, m):
+    """FP64 GMRES(64) and FP32 GMRES in FP64 refinement, 2,000 iterations at most, on downsized
+    versions of the 3D workloads, against the oracle's sparse direct solution of the same system:
+    the solver's residual report equals the residual computed with the oracle's matrix, and
+    ||x - x_oracle|| / ||x_oracle|| is printed (it is small only where the solve converged)."""
+    ref = O.setup(d, n, -1.0, 1.0, ls, p, disc=disc, taylor_order=m)
+    op = sbm.Operator(d, n, -1.0, 1.0, ls, p, disc=disc, taylor_order=m)
+    b, bref = _rhs(ref, op)
+    A = O.assemble(ref)
+    xd = O.solve_direct(A, bref)
+    for mode in ("gmres", "gmres_ir"):
+        x = torch.zeros_like(b)
+        info = op.solve(b, x, rel_tol=1e-10, max_it=2000, mode=mode, restart=64)
+        xs = x.cpu().numpy()
+        res = np.linalg.norm(bref - A @ xs) / np.linalg.norm(bref)
+        err = np.linalg.norm(xs - xd) / np.linalg.norm(xd)
+        print(f"  {name} n_dofs={op.n_dofs} {mode}: status {sbm.status_name(info['status'])} its "
+              f"{info['inner_its']} residual {info['rel_residual']:.2e} (oracle {res:.2e}) "
+              f"|x - x_oracle|/|x_oracle| {err:.2e}", flush=True)
+        assert abs(res - info["rel_residual"]) <= 1e-6 * res + 1e-13
+        if info["status"] == sbm.SBM_OK:
+            assert res <= 2e-10
