@@ -293,20 +293,23 @@ def serve_section(n_req, max_it, rate, slots, budget_gb):
             "closed_loop_first_order_extension": dict(first, krylov_cap=10 * max_it)}
 
 
-def profile_run(torch, sbm, inputs, n=5, order=None):
-    """A few eager FP64 applies and plain device copies of n_dofs doubles, for counter runs
-    (order: extension order set on the operator first; None keeps the full extension)."""
-    w = inputs.workload("sphere3d_q4")
+def profile_run(torch, sbm, inputs, n=5, order=None, prec="f64", workload="sphere3d_q4"):
+    """A few eager applies and plain device copies of the vector, for counter runs (order:
+    extension order set on the operator first; None keeps the full extension; prec: f64 or
+    f32)."""
+    w = inputs.workload(workload)
     op = sbm.Operator(w["d"], w["n"], w["lo"], w["hi"], w["levelset"], w["p"], disc=w["disc"], taylor_order=order)
     u = torch.from_numpy(inputs.uniform_vector(op.n_dofs, seed=0)).to("cuda")
+    if prec == "f32":
+        u = u.float()
     v = torch.empty_like(u)
     for _ in range(n):
         op.apply(u, v)
     for _ in range(n):
         v.copy_(u)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_run": True, "n_dofs": op.n_dofs, "copy_bytes_each_way": 8 * op.n_dofs,
-                      "taylor_order": order}))
+    print(json.dumps({"profile_run": True, "workload": workload, "n_dofs": op.n_dofs, "prec": prec,
+                      "copy_bytes_each_way": u.element_size() * op.n_dofs, "taylor_order": order}))
 
 
 def main():
@@ -323,6 +326,7 @@ def main():
     ap.add_argument("--profile-run", action="store_true", help="few eager applies + copies (counter runs)")
     ap.add_argument("--profile-order", type=int, default=None,
                     help="with --profile-run: extension order of the operator (default: full extension)")
+    ap.add_argument("--profile-prec", default="f64", choices=("f64", "f32"), help="with --profile-run")
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-max-it", type=int, default=100)
     ap.add_argument("--serve-rate", type=float, default=0.0,
@@ -337,7 +341,7 @@ def main():
     from paper_2507_17053_amd import inputs, sbm
 
     if args.profile_run:
-        profile_run(torch, sbm, inputs, order=args.profile_order)
+        profile_run(torch, sbm, inputs, order=args.profile_order, prec=args.profile_prec, workload=args.workload)
         return
 
     w = inputs.workload(args.workload)

@@ -467,12 +467,12 @@ struct BrickCfg {
   static constexpr int EPC0 = (sizeof(T) == 8 && D == 3 && P == 4) ? 4 : EPB;
   static constexpr int EPC = EPC0 < EPB ? EPC0 : EPB;
   static constexpr int NTILE = EPC < NG ? EPC + 1 : NG;  // tile pairs
-  // LDS in doubles: the lattice accumulator (FP64 in both precisions: the cell and face rows
-  // are summed into it in FP64), then either the two sweep arrays of
-  // the full path (in FP64 the first one is the accumulator itself) or the per-cell tiles.
-  static constexpr int TAIL_SWEEP = NL;  // FP64: LB; FP32: LA and LB
-  static constexpr int TAIL_CELLS = (2 * NTILE * NB * (int)sizeof(T) + 7) / 8;
-  static constexpr int SMEM_D = NL + (TAIL_SWEEP > TAIL_CELLS ? TAIL_SWEEP : TAIL_CELLS);
+  // LDS in elements of T: the lattice accumulator (the cell and face rows are summed into it in
+  // the apply's precision, in a fixed order), then either the second sweep array of the full
+  // path (the first one is the accumulator itself) or the per-cell tiles.
+  static constexpr int TAIL_SWEEP = NL;
+  static constexpr int TAIL_CELLS = 2 * NTILE * NB;
+  static constexpr int SMEM = NL + (TAIL_SWEEP > TAIL_CELLS ? TAIL_SWEEP : TAIL_CELLS);
 };
 
 // Lattice-line segments of a full brick.  A line of B cells has B p + 1 nodes; the segment of
@@ -506,9 +506,9 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
   constexpr int BX = C::BX, BY = C::BY, BZ = C::BZ, LX = C::LX, LY = C::LY, LZ = C::LZ;
   constexpr int NL = C::NL, NROWS = C::NROWS;
   static_assert(LX <= 32, "row masks hold 32 points");
-  __shared__ double smem_d[C::SMEM_D];
-  double *acc = smem_d;                       // the brick lattice (both paths), FP64
-  T *const tail = (T *)(smem_d + NL);         // per-cell tiles, or the FP32 sweep arrays
+  __shared__ T smem[C::SMEM];
+  T *const acc = smem;             // the brick lattice (both paths)
+  T *const tail = smem + NL;       // per-cell tiles, or the second sweep array
   const int brick = xcd_block();
   const int tid = threadIdx.x;
   constexpr int nthr = C::NT;  // the launch uses exactly NT threads
@@ -534,10 +534,10 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     // the Kronecker sum of the 1D operators assembled along each direction; sweep the
     // brick lattice line by line (a = M u, b = K u along the last axis, then c = M a,
     // e = K a + M b, then h (K c + M e)), in place in LDS. ----
-    // sweep arrays: FP64 a/c in the accumulator itself (the last sweep writes in place),
-    // FP32 both in the tail (the last sweep writes the accumulator)
-    T *const LA = (sizeof(T) == sizeof(double)) ? (T *)smem_d : tail;
-    T *const LB = (sizeof(T) == sizeof(double)) ? tail : tail + NL;
+    // sweep arrays: a/c in the accumulator itself (the last sweep writes in place), b/e in the
+    // tail
+    T *const LA = acc;
+    T *const LB = tail;
     // last axis (z in 3D, y in 2D): a = M u, b = K u, gathered from u (every point of a full
     // brick is a DoF: id = row base + x)
     {
@@ -641,14 +641,14 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
         yo[0] += from_prev_lane<G>(yo[P], j);
         if (live) {
 #pragma unroll
-          for (int i = 0; i < P; ++i) acc[o + i] = (double)yo[i];
-          if (j == BX - 1) acc[o + P] = (double)yo[P];
+          for (int i = 0; i < P; ++i) acc[o + i] = yo[i];
+          if (j == BX - 1) acc[o + P] = yo[P];
         }
       }
     }
     __syncthreads();
   } else {
-    for (int i = tid; i < NL; i += nthr) acc[i] = 0.0;
+    for (int i = tid; i < NL; i += nthr) acc[i] = T(0);
     __syncthreads();
   }
 
@@ -682,7 +682,7 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
       for (int k = 0; k < nslot; ++k) {
         if (le == k) {
 #pragma unroll
-          for (int i = 0; i < N1; ++i) acc[loc + run_off + i] += (double)out[i];
+          for (int i = 0; i < N1; ++i) acc[loc + run_off + i] += out[i];
         }
         __syncthreads();
       }
@@ -717,7 +717,7 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
       for (int k = 0; k < nslot; ++k) {
         if (fact && le == k) {
 #pragma unroll
-          for (int ia = 0; ia < N1; ++ia) acc[node + ia * Sa] += (double)row[ia];
+          for (int ia = 0; ia < N1; ++ia) acc[node + ia * Sa] += row[ia];
         }
         __syncthreads();
       }
@@ -746,7 +746,7 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     const int plane = (x == 0 ? 1 : 0) | (y == 0 ? 2 : 0) | ((D == 3 && z == 0) ? 4 : 0);
     T *dst = inner ? v + s_base[row] + __popc(gm & below)
                    : halo + (int64_t)plane * nhalo + s_hbase[row] + __popc(hgm & below);
-    const T val = (T)acc[ptc];
+    const T val = acc[ptc];
     if (pt < NL && ((bm >> x) & 1u)) *dst = val;
   }
 }
@@ -972,10 +972,13 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
 // sums are added in slab order, as in sbm_face_eval; the face-node phases (normal
 // derivative, Gauss interpolation, integration) run in every slab with identical results;
 // slab 0 stores the face's (Rv, Rg) as sbm_face_kernel does.  For p <= 5 ((p+1)^3 <= 256).
+// face_runs != nullptr (CG): the cell's values are gathered through its x-run bases
+// (face_runs[f][t] is the first DoF of run t); otherwise (DG) the cell block is contiguous.
 template <typename T, int N1, int EPB>
 __global__ __launch_bounds__(256) void sbm_face_slab_kernel(int n_faces, const int32_t *__restrict__ face_cell,
                                                             const int32_t *__restrict__ face_code,
                                                             const double *__restrict__ face_xi,
+                                                            const int32_t *__restrict__ face_runs,
                                                             const T *__restrict__ u, T *__restrict__ fbuf,
                                                             KTab<T, N1> tab, KScal sc) {
   constexpr int D = 3, NP = N1 * N1, NB = NP * N1;
@@ -992,8 +995,11 @@ __global__ __launch_bounds__(256) void sbm_face_slab_kernel(int n_faces, const i
 #pragma unroll
   for (int k = 0; k < D; ++k) xp[k] = act ? face_xi[((int64_t)f * NP + t) * D + k] : 0.0;
   const FaceAxes<D, N1> fa(act ? face_code[f] : 0);
-  const int64_t base = (int64_t)(act ? face_cell[f] : 0) * NB;
-  if (act) su[r] = u[base + r];
+  if (act) {
+    const int64_t at = face_runs ? (int64_t)face_runs[(int64_t)f * NP + r / N1] + r % N1
+                                 : (int64_t)face_cell[f] * NB + r;
+    su[r] = u[at];
+  }
   __syncthreads();
   const T h = T(sc.h), sig = T(sc.sigma_gamma);
   const T sh = (fa.s ? T(1) : T(-1)) / h;
@@ -1341,6 +1347,8 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
       T *halo = (T *)scr.halo;
       T *fbuf = (T *)scr.fbuf;
       if (nf > 0 && (parts & SBM_PART_SBM_FACES) && !(parts & SBM_PART_REUSE_FACES)) {
+        // (the one-thread-per-(point, slab) layout of the DG faces measured 21.7 against
+        // 11.6 us here at 3D p = 4: the pair layout reads each cell value once for two points)
         constexpr int EF = epb<T, D, N1, 2, 0>();
         hipLaunchKernelGGL((sbm_face_cg_kernel<T, D, N1, EF>), dim3((nf + EF - 1) / EF), dim3(EF * NP), 0, s, nf,
                            c->d_face_code, c->d_face_runs, c->d_face_xi, u, fbuf, tab, sc);
@@ -1362,10 +1370,11 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
         constexpr int NB = Shape<D, N1>::NB, E = 256 / NB, E1 = (64 / NB < 1) ? 1 : 64 / NB;
         if ((nf + E - 1) / E >= two_per_cu())
           hipLaunchKernelGGL((sbm_face_slab_kernel<T, N1, E>), dim3((nf + E - 1) / E), dim3(E * NB), 0, s, nf,
-                             c->d_face_cell, c->d_face_code, c->d_face_xi, u, fbuf, tab, sc);
+                             c->d_face_cell, c->d_face_code, c->d_face_xi, (const int32_t *)nullptr, u, fbuf, tab, sc);
         else
           hipLaunchKernelGGL((sbm_face_slab_kernel<T, N1, E1>), dim3((nf + E1 - 1) / E1), dim3(E1 * NB), 0, s,
-                             nf, c->d_face_cell, c->d_face_code, c->d_face_xi, u, fbuf, tab, sc);
+                             nf, c->d_face_cell, c->d_face_code, c->d_face_xi, (const int32_t *)nullptr, u, fbuf, tab,
+                             sc);
       } else {
         constexpr int E = epb<T, D, N1, 1, 0>(), E1 = epb_one_wave<T, D, N1, 1>();
         if ((nf + E - 1) / E >= two_per_cu())
