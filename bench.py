@@ -260,37 +260,59 @@ def solve_section(torch, sbm, inputs):
     return out
 
 
-def serve_section(n_req, max_it, rate, slots, budget_gb):
+def serve_section(n_req, max_it, rate, slots, budget_gb, deadline_s):
     """Request stream (p in 2..6, 16^3..64^3 cells, ellipsoid or 8-ball union, CG or SIPG,
     FP32 GMRES inside FP64 refinement to 1e-10 with an iteration cap).  First closed loop (all
     requests queued at t = 0) for the capacity mu in solves/s, then open loop with Poisson
     arrivals at 0.7 mu (rate > 0 overrides the open-loop rate); then the same requests in closed
-    loop with the first-order extension E_1 and a 10x iteration cap."""
+    loop with the first-order extension E_1 and a 10x iteration cap.  Each run admits requests
+    for at most deadline_s seconds (the prefix served is reported)."""
     from paper_2507_17053_amd import inputs
     from paper_2507_17053_amd.serving import Server
 
     def one(reqs, time_scale, cap=max_it):
         srv = Server(budget_bytes=int(budget_gb * (1 << 30)), slots=slots, mode="gmres_ir", rel_tol=1e-10,
                      max_it=cap, restart=32)
-        s = srv.run(reqs, time_scale=time_scale)
+        s = srv.run(reqs, time_scale=time_scale, deadline_s=deadline_s)
         res = list(s["results"].values())
         rr = sorted(r["info"].get("rel_residual", float("nan")) for r in res)
+        conv = [r for r in res if r["error"] is None and r["info"].get("status") == 0]
         return {"requests": s["requests"], "served": s["served"], "converged_to_1e-10": s["converged"],
-                "errors": s["errors"], "solves_per_s": s["solves_per_s"], "latency_p50_s": s["latency_p50_s"],
-                "latency_p99_s": s["latency_p99_s"], "median_rel_residual": rr[len(rr) // 2] if rr else None,
-                "total_dofs": int(sum(r["info"].get("n_dofs", 0) for r in res))}
+                "errors": s["errors"], "solves_per_s": s["solves_per_s"],
+                "converged_solves_per_s": s["converged_solves_per_s"],
+                "latency_p50_s": s["latency_p50_s"], "latency_p99_s": s["latency_p99_s"],
+                "converged_latency_p50_s": s["converged_latency_p50_s"],
+                "converged_latency_p99_s": s["converged_latency_p99_s"],
+                "median_rel_residual": rr[len(rr) // 2] if rr else None,
+                "converged_by_kind": {k: sum(1 for r in conv if f"{r['info'].get('disc', '')}" == k) for k in ("cg", "dg")},
+                "total_dofs": int(sum(r["info"].get("n_dofs", 0) for r in res)), "wall_s": s["wall_s"]}
 
     closed = one(inputs.serving_requests(n_req, seed=2, rate=1.0), 0.0)
     mu = closed["solves_per_s"]
     lam = rate if rate > 0 else 0.7 * mu
     opened = one(inputs.serving_requests(n_req, seed=2, rate=lam), 1.0)
-    # the same requests with the first-order extension E_1 (Krylov methods converge on it),
-    # closed loop with a 10x larger iteration cap
+    # the same requests with the first-order extension E_1, closed loop, 10x iteration cap
     first = one([dict(r, taylor_order=1) for r in inputs.serving_requests(n_req, seed=2, rate=1.0)], 0.0,
                 cap=10 * max_it)
     return {"closed_loop": closed, "open_loop": dict(opened, arrival_rate_per_s=lam), "slots": slots,
-            "hbm_budget_GB": budget_gb, "krylov_cap": max_it,
+            "hbm_budget_GB": budget_gb, "krylov_cap": max_it, "admission_deadline_s": deadline_s,
             "closed_loop_first_order_extension": dict(first, krylov_cap=10 * max_it)}
+
+
+def serve_in_child(args):
+    """The serving section in a child process (its worker threads, allocations and teardowns are
+    isolated from the measurement above: whatever happens there, this run still prints its
+    line); returns the child's JSON, or the child's exit status and the tail of its output."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--serve-only", "--serve", str(args.serve),
+           "--serve-max-it", str(args.serve_max_it), "--serve-rate", str(args.serve_rate),
+           "--serve-deadline", str(args.serve_deadline)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=max(120.0, 8 * args.serve_deadline + 120.0))
+    lines = [ln for ln in r.stdout.strip().splitlines() if ln.startswith("{")]
+    if r.returncode == 0 and lines:
+        return json.loads(lines[-1])
+    return {"error": f"serving process exited with status {r.returncode}",
+            "stderr_tail": r.stderr[-2000:], "stdout_tail": r.stdout[-500:]}
 
 
 def profile_run(torch, sbm, inputs, n=5, order=None, prec="f64", workload="sphere3d_q4"):
@@ -327,7 +349,12 @@ def main():
     ap.add_argument("--profile-order", type=int, default=None,
                     help="with --profile-run: extension order of the operator (default: full extension)")
     ap.add_argument("--profile-prec", default="f64", choices=("f64", "f32"), help="with --profile-run")
-    ap.add_argument("--serve", type=int, default=24, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve", type=int, default=512, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve-deadline", type=float, default=20.0,
+                    help="seconds during which each serving run admits requests")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving section and print its JSON (used by the main run, which "
+                         "runs the serving section in a child process)")
     ap.add_argument("--serve-max-it", type=int, default=100)
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="open-loop arrival rate (default: 0.7 of the closed-loop capacity)")
@@ -335,6 +362,12 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU: the library has no multi-GPU path; use --gpus 1"}))
         sys.exit(2)
+
+    if args.serve_only:
+        import torch  # noqa: F401  (the library runs on torch's HIP runtime)
+        print(json.dumps(serve_section(args.serve, args.serve_max_it, args.serve_rate, slots=12, budget_gb=96.0,
+                                       deadline_s=args.serve_deadline)), flush=True)
+        return
 
     import torch
 
@@ -425,7 +458,7 @@ def main():
     if not args.no_solve:
         out["solve"] = solve_section(torch, sbm, inputs)
     if args.serve > 0:
-        out["serving"] = serve_section(args.serve, args.serve_max_it, args.serve_rate, slots=12, budget_gb=96.0)
+        out["serving"] = serve_in_child(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

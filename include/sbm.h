@@ -104,10 +104,13 @@ typedef struct {
                               SBM_SETUP_HOST_BUILD: build the geometry, numbering and layout on
                               host threads and upload them (the default for the analytic
                               level-set kinds builds them with device kernels; results are
-                              identical; user level sets are always built on the host) */
+                              identical; user level sets are always built on the host);
+                              SBM_SETUP_NO_GRAPHS: sbm_solve launches every Arnoldi step's
+                              kernels one by one instead of replaying them from graphs captured
+                              in the second restart cycle (the results are identical) */
 } sbm_options;
 
-enum { SBM_SETUP_HOST_ONLY = 1, SBM_SETUP_HOST_BUILD = 2 };
+enum { SBM_SETUP_HOST_ONLY = 1, SBM_SETUP_HOST_BUILD = 2, SBM_SETUP_NO_GRAPHS = 4 };
 
 /*
  * sbm_setup -- build one operator (Sec. 3.4 data structures, Sec. 4.4 initialisation).
@@ -130,7 +133,10 @@ sbm_status sbm_setup(const sbm_mesh *mesh, const sbm_levelset *ls, int p, int di
 sbm_status sbm_info(sbm_handle h, int64_t *n_dofs, int64_t *n_cells, int64_t *n_sbm_faces,
                     int64_t *n_interior_faces, size_t *device_bytes);
 
-/* Releases every resource of h (NULL is ignored).  Synchronises the device first. */
+/* Releases every resource of h (NULL is ignored).  Waits for the handle's last asynchronous
+ * work (apply, diagonal) to finish, then returns its device memory to the library's pool
+ * stream-ordered: nothing else on the device is waited for, so other handles' work in flight
+ * continues.  Work on h enqueued on a stream after that last call must not exist. */
 void sbm_destroy(sbm_handle h);
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -201,9 +207,9 @@ sbm_status sbm_apply_parts(sbm_handle h, const void *u, void *v, int prec, int p
  * cell's polynomial evaluated at the shifted point (Sec. 3.3, Alg. 3).  m >= 0: the
  * expansion kept to total order m, E_m u(x~) = sum over |alpha| <= m of
  * D^alpha u_K(x~) d^alpha / alpha! (m = 1: value plus gradient; m >= dim * p equals the
- * default up to rounding).  With m >= 0 the surrogate faces run in a separate kernel that adds
- * its rows with atomics (results reproducible to rounding, not bitwise), and sbm_apply_parts
- * returns SBM_EUNSUPPORTED.  Does not touch the device; not synchronised with work already
+ * default up to rounding).  With m >= 0 the surrogate faces run in a separate kernel whose
+ * per-face results the cell kernels add in their fixed order (bitwise reproducible, as the
+ * default), and sbm_apply_parts returns SBM_EUNSUPPORTED.  Does not touch the device; not synchronised with work already
  * enqueued on h (call it between, not during, applies).  Errors: EINVAL (NULL handle).
  */
 sbm_status sbm_set_extension_order(sbm_handle h, int m);
@@ -280,7 +286,11 @@ typedef struct {
  * max_it bounds the total Krylov iterations.  jacobi != 0 right-preconditions with the
  * inverse of the operator's diagonal.  The Krylov workspace (GMRES: m + 1 basis vectors per
  * precision used) is allocated on the first solve and kept with the handle; solves on one
- * handle must not overlap.  Synchronous (returns after the work on stream has finished).
+ * handle must not overlap.  The solve runs on a stream of the workspace, after the work
+ * already enqueued on stream; from the second GMRES restart cycle on, each run of Arnoldi
+ * steps between residual checks is replayed from a graph captured at its first use (kept with
+ * the workspace; SBM_SETUP_NO_GRAPHS disables this).  Synchronous (returns after the solve's
+ * work has finished).
  * Errors: EINVAL, ENOMEM, ENOCONV (info->rel_residual holds what was reached), EHIP.
  */
 sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, int max_it,

@@ -84,5 +84,6 @@ extern "C" sbm_status sbm_apply_noalloc(sbm_handle h, const void *u, void *v, in
   scr.halo = base;
   scr.fbuf = (unsigned char *)base + (halo_bytes + 255) / 256 * 256;
   SBM_HIP_CHECK(sbm::launch_operator(h, u, v, prec, SBM_PART_ALL, (hipStream_t)stream, &scr));
+  sbm::note_work(h, (hipStream_t)stream);
   return SBM_OK;
 }

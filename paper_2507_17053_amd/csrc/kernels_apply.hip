@@ -1365,7 +1365,7 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
     // surrogate faces first (their (Rv, Rg) go to fbuf), then the cell kernel writes every
     // cell's block once: cell term, interior faces and the surrogate faces' rows in face order
     T *fbuf = (T *)scr.fbuf;
-    if (nf > 0 && (parts & SBM_PART_SBM_FACES)) {
+    if (nf > 0 && (parts & SBM_PART_SBM_FACES) && !(parts & SBM_PART_REUSE_FACES)) {
       if constexpr (D == 3 && Shape<D, N1>::NB <= 256) {
         constexpr int NB = Shape<D, N1>::NB, E = 256 / NB, E1 = (64 / NB < 1) ? 1 : 64 / NB;
         if ((nf + E - 1) / E >= two_per_cu())

@@ -107,20 +107,21 @@ constexpr int taylor_slabs() {
 // then its slab's share of E_m u (the cell values contracted axis by axis with the order sum
 // kept <= m) and of the normal derivative at x~_q; the slab shares are added in slab order.
 // Phase 2, one thread per face node: Rv = sum_q psi(x~_q) w_q (sigma E_m u - dn u) and
-// Rg = -sum_q psi(x~_q) w_q E_m u (2s-1)/h over the tangential basis.  Phase 3, one thread
-// per local row: Rv on the face's own nodes plus Rg times the normal derivative of the row's
-// 1D function.  FP64 inside; the 1D tables are staged in LDS.  JN: Taylor orders carried per
-// axis (p+1, or 2 for a launch with m <= 1).
+// Rg = -sum_q psi(x~_q) w_q E_m u (2s-1)/h over the tangential basis, stored per face node in
+// fbuf (fbuf[f][0][t], fbuf[f][1][t]); the cell kernels add the face's rows (Rv on the face's
+// own nodes plus Rg times the normal derivative of the row's 1D function) in a fixed order, as
+// for the full extension.  FP64 inside; the 1D tables are staged in LDS.  JN: Taylor orders
+// carried per axis (p+1, or 2 for a launch with m <= 1).
 template <typename T, int D, int N1, int JN>
 __global__ __launch_bounds__(kTaylorThreads) void sbm_face_taylor_kernel(
     int n_faces, int disc_dg, int m, const int32_t *__restrict__ face_cell, const int32_t *__restrict__ face_code,
-    const double *__restrict__ face_xi, const int32_t *__restrict__ runs, const T *__restrict__ u, T *__restrict__ v,
-    TaylorTab tt, double h, double sigma) {
-  constexpr int NP = D == 3 ? N1 * N1 : N1, NB = NP * N1, P = N1 - 1, S = taylor_slabs<D, N1>();
+    const double *__restrict__ face_xi, const int32_t *__restrict__ runs, const T *__restrict__ u,
+    T *__restrict__ fbuf, TaylorTab tt, double h, double sigma) {
+  constexpr int NP = D == 3 ? N1 * N1 : N1, NB = NP * N1, S = taylor_slabs<D, N1>();
   __shared__ double su[NB];
   __shared__ double sN[N1 * N1], sDs[N1], sw[N1];
   __shared__ double pe[S][NP], pd[S][NP];  // slab shares of E_m u and of the normal derivative
-  __shared__ double sA[NP], sB[NP], sRv[NP], sRg[NP];
+  __shared__ double sA[NP], sB[NP];
   const int f = blockIdx.x;
   if (f >= n_faces) return;
   const int cell = face_cell[f], code = face_code[f], a = code >> 1, s = code & 1;
@@ -243,17 +244,8 @@ __global__ __launch_bounds__(kTaylorThreads) void sbm_face_taylor_kernel(
       rv += tang * sA[q];
       rg += tang * sB[q];
     }
-    sRv[t] = rv;
-    sRg[t] = rg;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < NB; i += blockDim.x) {
-    const int ik[3] = {i % N1, (i / N1) % N1, D == 3 ? i / (N1 * N1) : 0};
-    const int ia = a == 0 ? ik[0] : (a == 1 ? ik[1] : ik[2]);
-    const int ib = tb == 0 ? ik[0] : ik[1];
-    const int node = ib + (D == 3 ? N1 * ik[tc] : 0);
-    const double row = (ia == s * P ? sRv[node] : 0.0) + sDs[ia] * sRg[node];
-    unsafeAtomicAdd(v + local_dof<D, N1>(disc_dg, runs, cell, i), (T)row);
+    fbuf[(int64_t)f * 2 * NP + t] = (T)rv;
+    fbuf[(int64_t)f * 2 * NP + NP + t] = (T)rg;
   }
 }
 
@@ -319,7 +311,7 @@ __global__ __launch_bounds__(kTaylorThreads) void diag_taylor_kernel(
 }
 
 template <typename T, int D, int N1>
-hipError_t taylor_faces(const sbm_ctx *c, const T *u, T *v, hipStream_t s) {
+hipError_t taylor_faces(const sbm_ctx *c, const T *u, T *fbuf, hipStream_t s) {
   const int nf = (int)c->n_sbm;
   if (nf == 0) return hipSuccess;
   // one thread per (face point, slab) in the first phase (at least one wavefront)
@@ -328,11 +320,11 @@ hipError_t taylor_faces(const sbm_ctx *c, const T *u, T *v, hipStream_t s) {
   // orders 0 and 1 only for m <= 1 (the first-order extension), all p+1 otherwise
   if (c->taylor_m <= 1)
     hipLaunchKernelGGL((sbm_face_taylor_kernel<T, D, N1, 2>), dim3(nf), dim3(NT), 0, s, nf, c->disc == SBM_DG,
-                       c->taylor_m, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, v,
+                       c->taylor_m, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, fbuf,
                        make_taylor_tab(c->rules), c->h, c->sigma_gamma);
   else
     hipLaunchKernelGGL((sbm_face_taylor_kernel<T, D, N1, N1>), dim3(nf), dim3(NT), 0, s, nf, c->disc == SBM_DG,
-                       c->taylor_m, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, v,
+                       c->taylor_m, c->d_face_cell, c->d_face_code, c->d_face_xi, c->d_runs, u, fbuf,
                        make_taylor_tab(c->rules), c->h, c->sigma_gamma);
   return hipGetLastError();
 }
@@ -378,13 +370,16 @@ hipError_t taylor_run(const sbm_ctx *c, const void *u, void *v, void *diag, hipS
 hipError_t launch_operator(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s,
                            const Scratch *scr) {
   if (c->taylor_m < 0 || !(parts & SBM_PART_SBM_FACES)) return launch_apply(c, u, v, prec, parts, s, scr);
-  // the cell term (DG: with the interior faces) overwrites v; the surrogate faces add into it
-  const int rest = parts & ~(SBM_PART_SBM_FACES | SBM_PART_REUSE_FACES);
-  if (rest & SBM_PART_CELLS) {
-    hipError_t e = launch_apply(c, u, v, prec, rest, s, scr);
+  // the truncated surrogate-face term leaves (Rv, Rg) per face node in the face-result scratch;
+  // the cell launches then take them as computed face results (SBM_PART_REUSE_FACES) and add the
+  // rows in their fixed order
+  void *fbuf = (scr && scr->fbuf) ? scr->fbuf : c->d_fbuf;
+  if (c->n_sbm > 0) {
+    const hipError_t e = prec == SBM_F64 ? taylor_run<double>(c, u, fbuf, nullptr, s)
+                                         : taylor_run<float>(c, u, fbuf, nullptr, s);
     if (e != hipSuccess) return e;
   }
-  return prec == SBM_F64 ? taylor_run<double>(c, u, v, nullptr, s) : taylor_run<float>(c, u, v, nullptr, s);
+  return launch_apply(c, u, v, prec, parts | SBM_PART_REUSE_FACES, s, scr);
 }
 
 hipError_t launch_operator_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s) {

@@ -85,6 +85,7 @@ struct sbm_ctx {
   double h = 1.0;
   double gamma = 10.0, gamma_dg = 10.0, shift_scale = 1.0;
   int taylor_m = -1;  // surrogate-face extension: < 0 full (point value at the shifted point), else E_m
+  bool solver_graphs = true;  // the solver replays its Arnoldi steps from captured graphs
   double sigma_gamma = 0.0, sigma_f = 0.0;
   int64_t n_cells = 0, n_dofs = 0, n_sbm = 0, n_int = 0;
   int nq_face = 1;   // (p+1)^(d-1)
@@ -133,6 +134,9 @@ struct sbm_ctx {
   size_t device_bytes = 0;
   bool host_only = false;
   sbm::Workspace *ws = nullptr;
+  // completion of the handle's last stream-ordered work (recorded by the asynchronous entry
+  // points); sbm_destroy waits for it instead of for the whole device
+  hipEvent_t last_work = nullptr;
 };
 
 namespace sbm {
@@ -169,6 +173,17 @@ int64_t order_bricks(const std::vector<int32_t> &count, const std::vector<int32_
 // the geometry, the DoF numbering and the brick layout with kernels, fills the handle's arena
 // and the host copies (cells, faces, shifted and true points, runs).
 sbm_status device_setup(sbm_ctx *c);
+// Device memory of handles and workspaces: a released block goes to a per-device cache
+// (bounded, 16 GB) and is handed to the next allocation that fits, so releasing memory does not
+// synchronise the device (hipFree does); only what exceeds the cache is freed.  The caller of
+// dev_free must have finished all device work on the block.  lib_stream: a library stream of
+// the current device (default priority) for the library's own uploads.
+hipStream_t lib_stream();
+hipError_t dev_alloc(void **p, size_t bytes);
+void dev_free(void *p);
+// Record the completion of the work just enqueued on stream for handle c (skipped while the
+// stream is being captured into a graph).
+void note_work(sbm_ctx *c, hipStream_t stream);
 // Device bytes of the handle's solver workspace (0 before the first solve).
 size_t workspace_bytes(const sbm_ctx *c);
 // Vector kernels (vec.hip)

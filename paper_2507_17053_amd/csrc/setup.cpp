@@ -8,6 +8,8 @@
 #include <limits>
 #include <functional>
 #include <new>
+#include <map>
+#include <mutex>
 #include <thread>
 
 #include "sbm_internal.h"
@@ -16,6 +18,99 @@ namespace sbm {
 
 static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+constexpr int kMaxDev = 64;
+std::mutex g_lib_mu;
+hipStream_t g_lib_stream[kMaxDev] = {};
+// Released device blocks kept for reuse, per device: (bytes, pointer), at most kCacheBytes in
+// total per device; a request takes the smallest cached block that fits and is at most twice
+// its size.
+constexpr size_t kCacheBytes = (size_t)16 << 30;
+std::mutex g_cache_mu;
+std::multimap<size_t, void *> g_cache[kMaxDev];
+size_t g_cached[kMaxDev] = {};
+std::map<void *, std::pair<int, size_t>> g_live;  // block -> (device, bytes)
+}  // namespace
+
+hipStream_t lib_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
+  std::lock_guard<std::mutex> lock(g_lib_mu);
+  if (!g_lib_stream[dev]) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    g_lib_stream[dev] = s;
+  }
+  return g_lib_stream[dev];
+}
+
+hipError_t dev_alloc(void **p, size_t bytes) {
+  *p = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto it = g_cache[dev].lower_bound(bytes);
+    if (it != g_cache[dev].end() && it->first <= 2 * bytes) {
+      *p = it->second;
+      g_cached[dev] -= it->first;
+      g_live[*p] = {dev, it->first};
+      g_cache[dev].erase(it);
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    // release the cache of this device and try once more
+    std::vector<void *> drop;
+    {
+      std::lock_guard<std::mutex> lock(g_cache_mu);
+      for (auto &kv : g_cache[dev]) drop.push_back(kv.second);
+      g_cache[dev].clear();
+      g_cached[dev] = 0;
+    }
+    if (drop.empty()) return e;
+    for (void *q : drop) (void)hipFree(q);
+    (void)hipGetLastError();
+    e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return e;
+  }
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  g_live[*p] = {dev, bytes};
+  return hipSuccess;
+}
+
+void dev_free(void *p) {
+  if (!p) return;
+  std::pair<int, size_t> info{-1, 0};
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto it = g_live.find(p);
+    if (it != g_live.end()) {
+      info = it->second;
+      g_live.erase(it);
+      if (g_cached[info.first] + info.second <= kCacheBytes) {
+        g_cache[info.first].emplace(info.second, p);
+        g_cached[info.first] += info.second;
+        return;
+      }
+    }
+  }
+  (void)hipFree(p);  // beyond the cache (this synchronises the device)
+}
+
+void note_work(sbm_ctx *c, hipStream_t stream) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  if (!c->last_work && hipEventCreateWithFlags(&c->last_work, hipEventDisableTiming) != hipSuccess) {
+    c->last_work = nullptr;
+    return;
+  }
+  (void)hipEventRecord(c->last_work, stream);
+}
 
 // ---------------------------------------------------------------------------------------
 // 1D rules on [0,1] (Sec. 3.1): GLL nodes for the basis, Gauss points for quadrature.
@@ -252,24 +347,24 @@ struct ArenaPlan {
     for (const Item &it : items) *total += aligned(it.bytes);
     *arena = nullptr;
     if (*total == 0) return hipSuccess;
-    hipError_t e = hipMalloc(arena, *total);
+    hipError_t e = dev_alloc(arena, *total);
     if (e != hipSuccess) return e;
     size_t off = 0;
     for (const Item &it : items) {
       char *p = static_cast<char *>(*arena) + off;
       it.set(p);
       if (it.src) {
-        e = hipMemcpy(p, it.src, it.bytes, hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(p, it.src, it.bytes, hipMemcpyHostToDevice, lib_stream());
         if (e != hipSuccess) return e;
       }
       off += aligned(it.bytes);
     }
-    return hipSuccess;
+    return hipStreamSynchronize(lib_stream());
   }
 };
 
 static void free_device(sbm_ctx *c) {
-  if (c->d_arena) (void)hipFree(c->d_arena);
+  if (c->d_arena) dev_free(c->d_arena);
   c->d_arena = nullptr;
   c->d_runs = c->d_nbr = c->d_face_cell = c->d_face_code = nullptr;
   c->d_face_xi = nullptr;
@@ -545,6 +640,7 @@ static sbm_status prepare(sbm_ctx *c, const sbm_mesh *mesh, const sbm_levelset *
   c->gamma = (opts && opts->penalty_gamma > 0) ? opts->penalty_gamma : 10.0;
   c->gamma_dg = (opts && opts->dg_penalty_gamma > 0) ? opts->dg_penalty_gamma : 10.0;
   c->shift_scale = opts ? opts->shift_scale : 1.0;
+  c->solver_graphs = !(opts && (opts->flags & SBM_SETUP_NO_GRAPHS));
   c->sigma_gamma = c->gamma * p * p / c->h;
   c->sigma_f = c->gamma_dg * p * p / c->h;
 
@@ -912,7 +1008,13 @@ sbm_status sbm_info(sbm_handle h, int64_t *n_dofs, int64_t *n_cells, int64_t *n_
 
 void sbm_destroy(sbm_handle h) {
   if (!h) return;
-  if (!h->host_only) (void)hipDeviceSynchronize();
+  // wait for the handle's last asynchronous work only (its memory returns to the pool
+  // stream-ordered; nothing else on the device is waited for)
+  if (h->last_work) {
+    (void)hipEventSynchronize(h->last_work);
+    (void)hipEventDestroy(h->last_work);
+    h->last_work = nullptr;
+  }
   sbm::free_workspace(h);
   free_device(h);
   delete h;
@@ -941,6 +1043,7 @@ sbm_status sbm_apply(sbm_handle h, const void *u, void *v, int prec, void *strea
     return SBM_EINVAL;
   }
   SBM_HIP_CHECK(launch_operator(h, u, v, prec, SBM_PART_ALL, (hipStream_t)stream));
+  note_work(h, (hipStream_t)stream);
   return SBM_OK;
 }
 
@@ -957,6 +1060,7 @@ sbm_status sbm_apply_parts(sbm_handle h, const void *u, void *v, int prec, int p
   }
   if (h->n_dofs == 0) return SBM_OK;
   SBM_HIP_CHECK(launch_apply(h, u, v, prec, parts, (hipStream_t)stream));
+  note_work(h, (hipStream_t)stream);
   return SBM_OK;
 }
 

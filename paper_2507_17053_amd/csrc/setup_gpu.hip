@@ -441,7 +441,7 @@ struct Carve {
   hipError_t commit(void **arena) {
     *arena = nullptr;
     if (off == 0) return hipSuccess;
-    hipError_t e = hipMalloc(arena, off);
+    hipError_t e = dev_alloc(arena, off);
     if (e != hipSuccess) return e;
     for (auto &it : items) *it.first = (char *)*arena + it.second;
     return hipSuccess;
@@ -713,6 +713,7 @@ sbm_status device_setup_impl(sbm_ctx *c, Temps &tmp) {
     if (ne > 0) DS_CHECK(hipMemcpyAsync(c->d_nbr, nbr_t, sizeof(int32_t) * ne, hipMemcpyDeviceToDevice, s), "copy");
     if (nf > 0) {
       // DG face arrays in host order: cell rank and code from the face list, xi as projected
+      // (the host vectors are read by the copies before the synchronisation below)
       std::vector<int32_t> hf(3 * nf);
       DS_CHECK(hipMemcpyAsync(hf.data(), faces, sizeof(int32_t) * 3 * nf, hipMemcpyDeviceToHost, s), "download");
       DS_CHECK(hipStreamSynchronize(s), "synchronise");
@@ -724,6 +725,7 @@ sbm_status device_setup_impl(sbm_ctx *c, Temps &tmp) {
       DS_CHECK(hipMemcpyAsync(c->d_face_cell, fcell.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, s), "upload");
       DS_CHECK(hipMemcpyAsync(c->d_face_code, fcode.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, s), "upload");
       DS_CHECK(hipMemcpyAsync(c->d_face_xi, xi_h, sizeof(double) * nf * g.np * d, hipMemcpyDeviceToDevice, s), "copy");
+      DS_CHECK(hipStreamSynchronize(s), "synchronise");
     }
   }
 

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <thread>
 #include <type_traits>
 #include <vector>
@@ -586,6 +587,14 @@ struct Workspace {
   unsigned *ticket = nullptr; // block counter of the single-pass reductions (0 between launches)
   void *arena = nullptr;      // the allocation holding all of the above
   size_t bytes = 0;           // device bytes held: the arena plus the Jacobi diagonals
+  // the solver runs on a stream of its own (after the caller's stream, by an event), so that
+  // its Arnoldi steps can be captured into graphs and replayed; one graph per run of steps
+  // j..j1 of a restart cycle (key: precision, j, j1, preconditioner, extension order), made in
+  // the second cycle of a solve and replayed in every later one
+  hipStream_t stream = nullptr;
+  hipEvent_t ready = nullptr;
+  std::map<uint64_t, hipGraphExec_t> graphs;
+  bool graphs_off = false;    // a capture failed: steps are launched one by one
   bool have_diag = false;
   // grid of each Gram-Schmidt kernel: as many blocks as fit on the device at once (no partial
   // last round), index [FP32][log2(CPW) - 1, 4 for the kernel of more than 64 columns][MODE]
@@ -597,10 +606,14 @@ size_t workspace_bytes(const sbm_ctx *c) { return c->ws ? c->ws->bytes : 0; }
 void free_workspace(sbm_ctx *c) {
   Workspace *ws = c->ws;
   if (!ws) return;
-  // one allocation for the vectors and scalars (hipFree synchronises the device); the Jacobi
-  // diagonals are allocated on their first use
-  for (void *p : {ws->arena, (void *)ws->dinv, (void *)ws->dinv32})
-    if (p) (void)hipFree(p);
+  // one allocation for the vectors and scalars; the Jacobi diagonals are allocated on their
+  // first use; all from the device pool, released stream-ordered
+  if (ws->stream) (void)hipStreamSynchronize(ws->stream);
+  for (auto &g : ws->graphs) (void)hipGraphExecDestroy(g.second);
+  ws->graphs.clear();
+  for (void *p : {ws->arena, (void *)ws->dinv, (void *)ws->dinv32}) dev_free(p);
+  if (ws->ready) (void)hipEventDestroy(ws->ready);
+  if (ws->stream) (void)hipStreamDestroy(ws->stream);
   delete ws;
   c->ws = nullptr;
 }
@@ -643,11 +656,15 @@ static hipError_t ensure_workspace(sbm_ctx *c, int m, bool need32) {
     piece(ws->z32, sizeof(float) * n);
     piece(ws->r32, sizeof(float) * n);
   }
-  hipError_t e = hipMalloc(&ws->arena, off);
+  hipError_t e = dev_alloc(&ws->arena, off);
   if (e != hipSuccess) return e;
   ws->bytes = off;
+  e = hipStreamCreateWithFlags(&ws->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->ready, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
   for (auto &set : parts) set(static_cast<char *>(ws->arena));
-  return hipMemset(ws->ticket, 0, sizeof(unsigned));
+  e = hipMemsetAsync(ws->ticket, 0, sizeof(unsigned), lib_stream());
+  return e == hipSuccess ? hipStreamSynchronize(lib_stream()) : e;
 }
 
 // device dot products: out[i] = V_i . w for i < ncol (out on the device)
@@ -781,7 +798,7 @@ static sbm_status gmres_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *V, T *v
   if (grid[0][0] == 0) gs_grid_caps<T>(grid);
   *its = 0;
   double beta = 0.0;
-  while (true) {
+  for (int cycle = 0;; ++cycle) {
     // r = rhs - A x  -> V_0
     SBM_HIP_CHECK(launch_operator(c, x, w, prec, SBM_PART_ALL, s));
     ++*applies;
@@ -798,7 +815,37 @@ static sbm_status gmres_run(sbm_ctx *c, int prec, const T *rhs, T *x, T *V, T *v
     bool stop = false;
     while (j < m && *its < max_it && !stop) {
       const int j1 = std::min({m, j + check, j + (max_it - *its)});
-      const sbm_status st = arnoldi_steps<T>(c, prec, V, vc, w, z, dinv, m, j, j1, s);
+      // a run of steps of the regular length, from the second cycle on: its graph (captured at
+      // its first use, then replayed); otherwise the steps are launched one by one
+      const bool use_graph = cycle > 0 && c->solver_graphs && !ws->graphs_off && j1 == std::min(m, j + check);
+      sbm_status st = SBM_OK;
+      if (use_graph) {
+        const uint64_t key = ((uint64_t)(sizeof(T) == 4) << 62) | ((uint64_t)(dinv != nullptr) << 61) |
+                             ((uint64_t)(c->taylor_m + 1) << 40) | ((uint64_t)m << 20) | ((uint64_t)j << 10) |
+                             (uint64_t)j1;
+        auto it = ws->graphs.find(key);
+        if (it == ws->graphs.end()) {
+          hipGraph_t g = nullptr;
+          hipGraphExec_t ge = nullptr;
+          bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+          if (ok) {
+            st = arnoldi_steps<T>(c, prec, V, vc, w, z, dinv, m, j, j1, s);
+            ok = hipStreamEndCapture(s, &g) == hipSuccess && st == SBM_OK && g;
+            if (ok) ok = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+          }
+          if (!ok) {
+            (void)hipGetLastError();
+            ws->graphs_off = true;  // launch one by one from now on
+            st = arnoldi_steps<T>(c, prec, V, vc, w, z, dinv, m, j, j1, s);
+          } else {
+            it = ws->graphs.emplace(key, ge).first;
+          }
+        }
+        if (it != ws->graphs.end()) SBM_HIP_CHECK(hipGraphLaunch(it->second, s));
+      } else {
+        st = arnoldi_steps<T>(c, prec, V, vc, w, z, dinv, m, j, j1, s);
+      }
       if (st != SBM_OK) return st;
       *applies += j1 - j;
       SBM_HIP_CHECK(hipMemcpyAsync(rh.data(), dres + j, sizeof(double) * (j1 - j), hipMemcpyDeviceToHost, s));
@@ -926,6 +973,154 @@ static sbm_status cg_rr_run(sbm_ctx *c, const double *b, double *x, double tol_a
 }  // namespace sbm
 
 using namespace sbm;
+
+static sbm_status solve_on(sbm_handle h, const double *b, double *x, double rel_tol, int max_it, int mode, int m,
+                           int jacobi, hipStream_t s, sbm_solve_info *info,
+                           std::chrono::steady_clock::time_point t0) {
+  Workspace *ws = h->ws;
+  const int64_t n = h->n_dofs;
+  const int nb = nblocks(n);
+  // Jacobi: inverse diagonal
+  const double *dinv = nullptr;
+  const float *dinv32 = nullptr;
+  if (jacobi) {
+    if (!ws->dinv) {
+      if (dev_alloc((void **)&ws->dinv, sizeof(double) * n) != hipSuccess) {
+        set_error("sbm_solve: out of device memory");
+        return SBM_ENOMEM;
+      }
+      ws->bytes += sizeof(double) * n;
+    }
+    sbm_status st = sbm_diagonal(h, ws->dinv, SBM_F64, s);
+    if (st != SBM_OK) {
+      info->status = st;
+      return st;
+    }
+    hipLaunchKernelGGL(invert_kernel, dim3(nb), dim3(kThreads), 0, s, ws->dinv, n);
+    dinv = ws->dinv;
+    if (mode == SBM_SOLVE_GMRES_IR) {
+      if (!ws->dinv32) {
+        if (dev_alloc((void **)&ws->dinv32, sizeof(float) * n) != hipSuccess) {
+          set_error("sbm_solve: out of device memory");
+          return SBM_ENOMEM;
+        }
+        ws->bytes += sizeof(float) * n;
+      }
+      hipLaunchKernelGGL(cast_f64_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->dinv, ws->dinv32, n);
+      dinv32 = ws->dinv32;
+    }
+  }
+  // ||b||
+  SBM_HIP_CHECK(multidot<double>(b, n, 1, b, n, ws->partial, ws->h, s));
+  double bn2 = 0.0;
+  SBM_HIP_CHECK(hipMemcpyAsync(&bn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
+  SBM_HIP_CHECK(hipStreamSynchronize(s));
+  const double bnorm = std::sqrt(bn2);
+  const double tol_abs = rel_tol * (bnorm > 0 ? bnorm : 1.0);
+  sbm_status st = SBM_OK;
+  double res = 0.0;
+  if (mode == SBM_SOLVE_GMRES_F64) {
+    int its = 0, applies = 0;
+    st = gmres_run<double>(h, SBM_F64, b, x, ws->V, ws->vc, ws->w, ws->z, dinv, m, tol_abs, max_it, s, &its,
+                           &applies, &res);
+    info->inner_its = its;
+    info->outer_its = (its + m - 1) / m;
+    info->applies_f64 = applies;
+  } else if (mode == SBM_SOLVE_GMRES_IR) {
+    // FP64 refinement: r = b - A x (FP64), c ~= A32^-1 (r / |r|) by FP32 GMRES, x += |r| c
+    int total_its = 0;
+    for (int outer = 0;; ++outer) {
+      SBM_HIP_CHECK(launch_operator(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
+      ++info->applies_f64;
+      hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
+      SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));
+      double rn2 = 0.0;
+      SBM_HIP_CHECK(hipMemcpyAsync(&rn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
+      SBM_HIP_CHECK(hipStreamSynchronize(s));
+      res = std::sqrt(rn2);
+      info->outer_its = outer;
+      if (!(res > tol_abs) || total_its >= max_it || !std::isfinite(res)) break;
+      // keep |r|^2 on the device for the scaling kernels (slot m+1 of h is GMRES scratch)
+      SBM_HIP_CHECK(hipMemcpyAsync(ws->y + (m + 1), ws->h, sizeof(double), hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(to_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->r, ws->y + (m + 1), ws->r32, n);
+      hipLaunchKernelGGL(fill_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, n);
+      int its = 0, applies = 0;
+      double inner_res = 0.0;
+      // inner solve of A32 c = r / |r| (unit right-hand side) to what the remaining reduction
+      // needs, max(1e-6, tol / (2 |r|)) (FP32 reaches about 1e-6), at most 4 restart cycles
+      const double inner_tol = std::max(1e-6, 0.5 * tol_abs / res);
+      (void)gmres_run<float>(h, SBM_F32, ws->r32, ws->c32, ws->V32, ws->vc32, ws->w32, ws->z32, dinv32, m,
+                             inner_tol, std::min(4 * m, max_it - total_its), s, &its, &applies, &inner_res);
+      total_its += its;
+      info->applies_f32 += applies;
+      hipLaunchKernelGGL(add_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, ws->y + (m + 1), x, n);
+      if (its == 0) break;
+    }
+    info->inner_its = total_its;
+  } else if (mode == SBM_SOLVE_CG_F64) {
+    // CG (symmetric operators only)
+    int its = 0, applies = 0;
+    st = cg_run<double>(h, SBM_F64, b, x, ws->r, ws->z, ws->t, tol_abs, max_it, s, &its, &applies, &res);
+    info->inner_its = its;
+    info->outer_its = 1;
+    info->applies_f64 = applies;
+  } else if (mode == SBM_SOLVE_CG_RR) {
+    int its = 0, reps = 0, a64 = 0, a32 = 0;
+    st = cg_rr_run(h, b, x, tol_abs, max_it, s, &its, &reps, &a64, &a32, &res);
+    info->inner_its = its;
+    info->outer_its = reps;
+    info->applies_f64 = a64;
+    info->applies_f32 = a32;
+  } else {
+    // FP64 refinement around FP32 CG: r = b - A x and |r| in FP64, c ~= A32^-1 (r / |r|) by
+    // FP32 CG, x += |r| c in FP64.  The inner tolerance is what the remaining reduction needs
+    // (half of tol / |r|), but not below 1e-6 (FP32): every restart of CG discards its Krylov
+    // space, so each inner solve should do as much of the work as FP32 allows.
+    int total_its = 0;
+    for (int outer = 0;; ++outer) {
+      SBM_HIP_CHECK(launch_operator(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
+      ++info->applies_f64;
+      hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
+      SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));  // |r|^2 stays in h[0]
+      double rn2 = 0.0;
+      SBM_HIP_CHECK(hipMemcpyAsync(&rn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
+      SBM_HIP_CHECK(hipStreamSynchronize(s));
+      res = std::sqrt(rn2);
+      info->outer_its = outer;
+      if (!(res > tol_abs) || total_its >= max_it || !std::isfinite(res)) break;
+      hipLaunchKernelGGL(to_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->r, ws->h, ws->r32, n);
+      hipLaunchKernelGGL(fill_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, n);
+      int its = 0, applies = 0;
+      double inner_res = 0.0;
+      const double inner_tol = std::max(1e-6, 0.5 * tol_abs / res);
+      const sbm_status ist = cg_run<float>(h, SBM_F32, ws->r32, ws->c32, ws->w32, ws->z32, ws->V32, inner_tol,
+                                           max_it - total_its, s, &its, &applies, &inner_res);
+      if (ist != SBM_OK) {
+        info->status = ist;
+        return ist;
+      }
+      total_its += its;
+      info->applies_f32 += applies;
+      hipLaunchKernelGGL(add_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, ws->h, x, n);
+      if (its == 0) break;
+    }
+    info->inner_its = total_its;
+  }
+  // final true residual in FP64
+  SBM_HIP_CHECK(launch_operator(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
+  ++info->applies_f64;
+  hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
+  SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));
+  double rn2 = 0.0;
+  SBM_HIP_CHECK(hipMemcpyAsync(&rn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
+  SBM_HIP_CHECK(hipStreamSynchronize(s));
+  info->rel_residual = std::sqrt(rn2) / (bnorm > 0 ? bnorm : 1.0);
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st == SBM_OK && !(info->rel_residual <= rel_tol)) st = SBM_ENOCONV;
+  if (st == SBM_ENOCONV) set_error("sbm_solve: tolerance not reached within max_it");
+  info->status = st;
+  return st;
+}
 
 extern "C" {
 
@@ -1117,6 +1312,7 @@ sbm_status sbm_diagonal(sbm_handle h, void *diag, int prec, void *stream) {
     return SBM_EUNSUPPORTED;
   }
   SBM_HIP_CHECK(e);
+  note_work(h, (hipStream_t)stream);
   return SBM_OK;
 }
 
@@ -1137,7 +1333,6 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
     info->status = SBM_OK;
     return SBM_OK;
   }
-  hipStream_t s = (hipStream_t)stream;
   const bool cg = mode == SBM_SOLVE_CG_F64 || mode == SBM_SOLVE_CG_IR || mode == SBM_SOLVE_CG_RR;
   // CG needs no Krylov basis: one spare column of it serves as a work vector
   const int m = cg ? 1 : (restart > 0 ? std::min(restart, kMaxRestart) : 50);
@@ -1149,147 +1344,18 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
     return SBM_ENOMEM;
   }
   Workspace *ws = h->ws;
-  const int64_t n = h->n_dofs;
-  const int nb = nblocks(n);
-  // Jacobi: inverse diagonal
-  const double *dinv = nullptr;
-  const float *dinv32 = nullptr;
-  if (jacobi) {
-    if (!ws->dinv) {
-      if (hipMalloc(&ws->dinv, sizeof(double) * n) != hipSuccess) {
-        set_error("sbm_solve: out of device memory");
-        return SBM_ENOMEM;
-      }
-      ws->bytes += sizeof(double) * n;
-    }
-    sbm_status st = sbm_diagonal(h, ws->dinv, SBM_F64, stream);
-    if (st != SBM_OK) {
-      info->status = st;
-      return st;
-    }
-    hipLaunchKernelGGL(invert_kernel, dim3(nb), dim3(kThreads), 0, s, ws->dinv, n);
-    dinv = ws->dinv;
-    if (mode == SBM_SOLVE_GMRES_IR) {
-      if (!ws->dinv32) {
-        if (hipMalloc(&ws->dinv32, sizeof(float) * n) != hipSuccess) {
-          set_error("sbm_solve: out of device memory");
-          return SBM_ENOMEM;
-        }
-        ws->bytes += sizeof(float) * n;
-      }
-      hipLaunchKernelGGL(cast_f64_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->dinv, ws->dinv32, n);
-      dinv32 = ws->dinv32;
-    }
+  // everything below runs on the workspace's stream, after the work already on the caller's
+  // stream; the call returns when it has finished (so later work on the caller's stream sees x)
+  SBM_HIP_CHECK(hipEventRecord(ws->ready, (hipStream_t)stream));
+  SBM_HIP_CHECK(hipStreamWaitEvent(ws->stream, ws->ready, 0));
+  hipStream_t s = ws->stream;
+  const sbm_status st = solve_on(h, b, x, rel_tol, max_it, mode, m, jacobi, s, info, t0);
+  const hipError_t se = hipStreamSynchronize(s);
+  if (st == SBM_OK && se != hipSuccess) {
+    set_error(std::string("sbm_solve: ") + hipGetErrorString(se));
+    info->status = SBM_EHIP;
+    return SBM_EHIP;
   }
-  // ||b||
-  SBM_HIP_CHECK(multidot<double>(b, n, 1, b, n, ws->partial, ws->h, s));
-  double bn2 = 0.0;
-  SBM_HIP_CHECK(hipMemcpyAsync(&bn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
-  SBM_HIP_CHECK(hipStreamSynchronize(s));
-  const double bnorm = std::sqrt(bn2);
-  const double tol_abs = rel_tol * (bnorm > 0 ? bnorm : 1.0);
-  sbm_status st = SBM_OK;
-  double res = 0.0;
-  if (mode == SBM_SOLVE_GMRES_F64) {
-    int its = 0, applies = 0;
-    st = gmres_run<double>(h, SBM_F64, b, x, ws->V, ws->vc, ws->w, ws->z, dinv, m, tol_abs, max_it, s, &its,
-                           &applies, &res);
-    info->inner_its = its;
-    info->outer_its = (its + m - 1) / m;
-    info->applies_f64 = applies;
-  } else if (mode == SBM_SOLVE_GMRES_IR) {
-    // FP64 refinement: r = b - A x (FP64), c ~= A32^-1 (r / |r|) by FP32 GMRES, x += |r| c
-    int total_its = 0;
-    for (int outer = 0;; ++outer) {
-      SBM_HIP_CHECK(launch_operator(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
-      ++info->applies_f64;
-      hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
-      SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));
-      double rn2 = 0.0;
-      SBM_HIP_CHECK(hipMemcpyAsync(&rn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
-      SBM_HIP_CHECK(hipStreamSynchronize(s));
-      res = std::sqrt(rn2);
-      info->outer_its = outer;
-      if (!(res > tol_abs) || total_its >= max_it || !std::isfinite(res)) break;
-      // keep |r|^2 on the device for the scaling kernels (slot m+1 of h is GMRES scratch)
-      SBM_HIP_CHECK(hipMemcpyAsync(ws->y + (m + 1), ws->h, sizeof(double), hipMemcpyDeviceToDevice, s));
-      hipLaunchKernelGGL(to_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->r, ws->y + (m + 1), ws->r32, n);
-      hipLaunchKernelGGL(fill_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, n);
-      int its = 0, applies = 0;
-      double inner_res = 0.0;
-      // inner solve of A32 c = r / |r| (unit right-hand side) to what the remaining reduction
-      // needs, max(1e-6, tol / (2 |r|)) (FP32 reaches about 1e-6), at most 4 restart cycles
-      const double inner_tol = std::max(1e-6, 0.5 * tol_abs / res);
-      (void)gmres_run<float>(h, SBM_F32, ws->r32, ws->c32, ws->V32, ws->vc32, ws->w32, ws->z32, dinv32, m,
-                             inner_tol, std::min(4 * m, max_it - total_its), s, &its, &applies, &inner_res);
-      total_its += its;
-      info->applies_f32 += applies;
-      hipLaunchKernelGGL(add_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, ws->y + (m + 1), x, n);
-      if (its == 0) break;
-    }
-    info->inner_its = total_its;
-  } else if (mode == SBM_SOLVE_CG_F64) {
-    // CG (symmetric operators only)
-    int its = 0, applies = 0;
-    st = cg_run<double>(h, SBM_F64, b, x, ws->r, ws->z, ws->t, tol_abs, max_it, s, &its, &applies, &res);
-    info->inner_its = its;
-    info->outer_its = 1;
-    info->applies_f64 = applies;
-  } else if (mode == SBM_SOLVE_CG_RR) {
-    int its = 0, reps = 0, a64 = 0, a32 = 0;
-    st = cg_rr_run(h, b, x, tol_abs, max_it, s, &its, &reps, &a64, &a32, &res);
-    info->inner_its = its;
-    info->outer_its = reps;
-    info->applies_f64 = a64;
-    info->applies_f32 = a32;
-  } else {
-    // FP64 refinement around FP32 CG: r = b - A x and |r| in FP64, c ~= A32^-1 (r / |r|) by
-    // FP32 CG, x += |r| c in FP64.  The inner tolerance is what the remaining reduction needs
-    // (half of tol / |r|), but not below 1e-6 (FP32): every restart of CG discards its Krylov
-    // space, so each inner solve should do as much of the work as FP32 allows.
-    int total_its = 0;
-    for (int outer = 0;; ++outer) {
-      SBM_HIP_CHECK(launch_operator(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
-      ++info->applies_f64;
-      hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
-      SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));  // |r|^2 stays in h[0]
-      double rn2 = 0.0;
-      SBM_HIP_CHECK(hipMemcpyAsync(&rn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
-      SBM_HIP_CHECK(hipStreamSynchronize(s));
-      res = std::sqrt(rn2);
-      info->outer_its = outer;
-      if (!(res > tol_abs) || total_its >= max_it || !std::isfinite(res)) break;
-      hipLaunchKernelGGL(to_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->r, ws->h, ws->r32, n);
-      hipLaunchKernelGGL(fill_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, n);
-      int its = 0, applies = 0;
-      double inner_res = 0.0;
-      const double inner_tol = std::max(1e-6, 0.5 * tol_abs / res);
-      const sbm_status ist = cg_run<float>(h, SBM_F32, ws->r32, ws->c32, ws->w32, ws->z32, ws->V32, inner_tol,
-                                           max_it - total_its, s, &its, &applies, &inner_res);
-      if (ist != SBM_OK) {
-        info->status = ist;
-        return ist;
-      }
-      total_its += its;
-      info->applies_f32 += applies;
-      hipLaunchKernelGGL(add_f32_kernel, dim3(nb), dim3(kThreads), 0, s, ws->c32, ws->h, x, n);
-      if (its == 0) break;
-    }
-    info->inner_its = total_its;
-  }
-  // final true residual in FP64
-  SBM_HIP_CHECK(launch_operator(h, x, ws->t, SBM_F64, SBM_PART_ALL, s));
-  ++info->applies_f64;
-  hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(kThreads), 0, s, b, ws->t, ws->r, n);
-  SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));
-  double rn2 = 0.0;
-  SBM_HIP_CHECK(hipMemcpyAsync(&rn2, ws->h, sizeof(double), hipMemcpyDeviceToHost, s));
-  SBM_HIP_CHECK(hipStreamSynchronize(s));
-  info->rel_residual = std::sqrt(rn2) / (bnorm > 0 ? bnorm : 1.0);
-  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (st == SBM_OK && !(info->rel_residual <= rel_tol)) st = SBM_ENOCONV;
-  if (st == SBM_ENOCONV) set_error("sbm_solve: tolerance not reached within max_it");
-  info->status = st;
   return st;
 }
 

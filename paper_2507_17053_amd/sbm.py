@@ -199,7 +199,7 @@ class Operator:
     """One SBM operator (sbm_setup handle)."""
 
     def __init__(self, d, n, lo, hi, levelset, p, disc="cg", gamma=10.0, gamma_dg=10.0, shift_scale=1.0,
-                 host_only=False, taylor_order=None, host_build=False):
+                 host_only=False, taylor_order=None, host_build=False, solver_graphs=True):
         """taylor_order: None for the full extension (point value at the shifted point), m >= 0
         for the Taylor expansion kept to total order m (sbm_set_extension_order).  host_build:
         build the setup data on host threads (SBM_SETUP_HOST_BUILD) instead of the device."""
@@ -207,7 +207,8 @@ class Operator:
         keep = []
         m = _mesh(d, n, lo, hi)
         ls = _levelset(levelset, keep)
-        opt = _Options(gamma, gamma_dg, shift_scale, (1 if host_only else 0) | (2 if host_build else 0))
+        opt = _Options(gamma, gamma_dg, shift_scale,
+                       (1 if host_only else 0) | (2 if host_build else 0) | (0 if solver_graphs else 4))
         h = _P()
         _check(_lib.sbm_setup(ctypes.byref(m), ctypes.byref(ls), int(p), SBM_CG if disc == "cg" else SBM_DG,
                               ctypes.byref(opt), ctypes.byref(h)), "sbm_setup")

@@ -139,12 +139,14 @@ class Server:
     """Runs a request stream on the GPU through the library (see module docstring)."""
 
     def __init__(self, budget_bytes, slots=4, mode="gmres_ir", rel_tol=1e-10, max_it=400, restart=32,
-                 taylor_order=None, jacobi=False):
+                 taylor_order=None, jacobi=False, solver_graphs=False):
         """taylor_order: extension of the surrogate-face term for requests that do not name one
         (None: the full extension; m >= 0: the Taylor expansion kept to order m)."""
         self.sched = Scheduler(budget_bytes, slots)
         self.mode, self.rel_tol, self.max_it, self.restart = mode, rel_tol, max_it, restart
         self.jacobi = bool(jacobi)
+        # the solver's graph capture stays off in the slots (see the serving notes of the design)
+        self.solver_graphs = bool(solver_graphs)
         self.taylor_order = taylor_order
         self.lock = threading.Lock()
         self.done = threading.Condition(self.lock)
@@ -169,7 +171,7 @@ class Server:
 
         from . import inputs, sbm
         op = sbm.Operator(req["d"], req["n"], req["lo"], req["hi"], req["levelset"], req["p"], disc=req["disc"],
-                          taylor_order=req.get("taylor_order", self.taylor_order))
+                          taylor_order=req.get("taylor_order", self.taylor_order), solver_graphs=self.solver_graphs)
         try:
             u_fn, f_fn = inputs.manufactured(req["d"])
             cq, bp = op.rhs_points()
@@ -182,13 +184,16 @@ class Server:
                 info["device_bytes"] = op.device_bytes
                 xh = x.cpu().numpy() if stream is None else _to_host(x, stream)
             info["n_dofs"] = op.n_dofs
+            info["disc"], info["p"] = req["disc"], req["p"]
             return xh, info
         finally:
             op.close()
 
-    def run(self, requests, time_scale=1.0, keep_solutions=False):
+    def run(self, requests, time_scale=1.0, keep_solutions=False, deadline_s=None):
         """Serve `requests` (dicts with 'id' and 'arrival' seconds).  Arrival times are
-        scaled by time_scale (0 = all present at t=0, closed loop).  Returns a summary."""
+        scaled by time_scale (0 = all present at t=0, closed loop).  deadline_s: no request is
+        admitted after this many seconds (the ones admitted finish; the rest are reported as
+        not served).  Returns a summary."""
         import torch
 
         reqs = {r["id"]: r for r in requests}
@@ -220,6 +225,12 @@ class Server:
         with self.lock:
             while not self.sched.idle():
                 now = time.perf_counter() - t0
+                if deadline_s is not None and now > deadline_s:
+                    self.sched.pending.clear()  # stop admitting; wait for the admitted ones
+                    if self.sched.idle():
+                        break
+                    self.done.wait(timeout=0.05)
+                    continue
                 for rid, req in self.sched.admit(now):
                     si = free_streams.pop()
                     th = threading.Thread(target=worker, args=(rid, req, si), daemon=True)
@@ -234,13 +245,16 @@ class Server:
         wall = time.perf_counter() - t0
         lat = [r["latency"] for r in self.results.values() if r["error"] is None]
         ok = [r for r in self.results.values() if r["error"] is None and r["info"].get("status") == 0]
+        lat_ok = [r["latency"] for r in ok]
         first_arrival = min((r["arrival"] for r in self.results.values()), default=0.0)
         last_end = max((r["end"] for r in self.results.values()), default=0.0)
+        span = max(1e-9, last_end - first_arrival)
         return {
             "requests": len(requests), "served": len(self.results), "rejected": list(self.sched.rejected),
             "converged": len(ok), "errors": sum(1 for r in self.results.values() if r["error"]),
-            "solves_per_s": len(self.results) / max(1e-9, last_end - first_arrival),
+            "solves_per_s": len(self.results) / span, "converged_solves_per_s": len(ok) / span,
             "latency_p50_s": percentile(lat, 50), "latency_p99_s": percentile(lat, 99),
+            "converged_latency_p50_s": percentile(lat_ok, 50), "converged_latency_p99_s": percentile(lat_ok, 99),
             "wall_s": wall, "results": self.results,
         }
 

@@ -323,3 +323,43 @@ def test_downsized_workload_solves_against_oracle_direct_solution(name, d, n, ls
         assert abs(res - info["rel_residual"]) <= 1e-6 * res + 1e-13
         if info["status"] == sbm.SBM_OK:
             assert res <= 2e-10
+
+
+GRAPH_CASES = {
+    "disk-cg-q2": ((2, 16, -1.0, 1.0, DISK, 2), "cg", None, 16),
+    "sphere-dg-q2": ((3, 6, -1.0, 1.0, inputs.sphere((0, 0, 0), 0.75), 2), "dg", None, 4),
+    "disk-cg-q2-E1": ((2, 16, -1.0, 1.0, DISK, 2), "cg", 1, 16),
+}
+
+
+def _graph_pair(case):
+    args, disc, order, restart = GRAPH_CASES[case]
+    g_op = sbm.Operator(*args, disc=disc, taylor_order=order)
+    e_op = sbm.Operator(*args, disc=disc, taylor_order=order, solver_graphs=False)
+    ref = O.setup(*args, disc=disc, taylor_order=order)
+    b, _ = _rhs(ref, e_op)
+    return g_op, e_op, b, restart
+
+
+@pytest.mark.parametrize("mode", ["gmres", "gmres_ir"])
+@pytest.mark.parametrize("case", list(GRAPH_CASES))
+def test_graph_replayed_solves_equal_step_by_step_solves(case, mode):
+    """From the second restart cycle on, sbm_solve replays its runs of Arnoldi steps from graphs
+    captured at their first use.  Every solve on the graph-replaying handle (three in a row, with
+    eager applies and synchronisation between them, so later solves replay graphs made by earlier
+    ones) equals the solve on a handle that launches every step one by one, bit for bit (the
+    applies of both extensions are deterministic)."""
+    g_op, e_op, b, restart = _graph_pair(case)
+    xe = torch.zeros_like(b)
+    ie = e_op.solve(b, xe, rel_tol=1e-10, max_it=600, mode=mode, restart=restart)
+    assert ie["inner_its"] > 2 * restart, ie  # several restart cycles (converged or not)
+    scratch = torch.empty_like(b)
+    for rep in range(3):
+        xg = torch.zeros_like(b)
+        ig = g_op.solve(b, xg, rel_tol=1e-10, max_it=600, mode=mode, restart=restart)
+        assert ig["inner_its"] == ie["inner_its"] and ig["status"] == ie["status"], (rep, ig, ie)
+        assert torch.equal(xg, xe), rep
+        g_op.apply(xg, scratch)  # eager work between the solves
+        torch.cuda.synchronize()
+    g_op.close()
+    e_op.close()
