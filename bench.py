@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SBM apply DoF/s + % HBM roofline (FP64 vs FP32), 3D p=4; solves/s, p99 latency"
 HBM_PEAK_GBS = 8000.0
+VEC_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 
 
 def algorithmic_bytes(op, s, what):
@@ -51,18 +52,48 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per brick-kernel launch from the committed FETCH_SIZE / WRITE_SIZE summary,
-    only if it was taken on the current kernel source (else None)."""
-    p = os.path.join(ROOT, "profiles", "brick_kernel_sphere3d_q4_traffic.md")
+def _profile_record(name):
+    """The machine-readable line of a committed counter summary, only if it was taken on the
+    current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     for line in open(p):
         if line.startswith("machine-readable:"):
             rec = json.loads(line.split(":", 1)[1])
             if rec.get("kernel_src") == kernel_source_hash():
-                return rec.get("traffic_bytes_per_launch")
+                return rec
     return None
+
+
+def measured_traffic(key="traffic_bytes_per_launch"):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters) from
+    the committed apply-kernel traffic summary: key names the brick kernel or the whole apply."""
+    rec = _profile_record("apply_kernels_sphere3d_q4_traffic.md")
+    return None if rec is None else rec.get(key)
+
+
+def flop_rates(t_kernels, t_apply):
+    """FP64/FP32 vector FLOP rates of the apply kernels: FLOPs per launch from the committed
+    VALU counter summary over the kernel times measured in this run (t_kernels: name -> s)."""
+    rec = _profile_record("apply_kernels_sphere3d_q4_valu.md")
+    if rec is None:
+        return None
+    out = {}
+    for name, t in t_kernels.items():
+        fl = rec["flop_per_launch"].get(name)
+        if fl is None or not t:
+            continue
+        peak = VEC_PEAK_TFLOPS["f64" if "double" in name else "f32"]
+        rate = fl / t / 1e12
+        out[name] = {"gflop_per_launch": fl / 1e9, "tflops": rate, "peak_tflops": peak, "frac": rate / peak}
+    for prec, t in t_apply.items():
+        tn = "double" if prec == "f64" else "float"
+        fl = sum(v for k, v in rec["flop_per_launch"].items() if f"<{tn}," in k)
+        rate = fl / t / 1e12
+        out[f"apply_{prec}"] = {"gflop_per_apply": fl / 1e9, "tflops": rate, "peak_tflops": VEC_PEAK_TFLOPS[prec],
+                                "frac": rate / VEC_PEAK_TFLOPS[prec]}
+    return out
 
 
 def time_launches(torch, fn, k, graph_batch=20):
@@ -430,7 +461,21 @@ def main():
                      "achieved": brick_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": brick_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel_ms": r["t_brick"] * 1e3,
-                     "algorithmic_bytes_per_launch": r["b_brick"], "kernel_src": kernel_source_hash()},
+                     "algorithmic_bytes_per_launch": r["b_brick"], "kernel_src": kernel_source_hash(),
+                     # the whole apply (surrogate faces, bricks, boundary sums) against the same peak
+                     "apply_achieved": apply_gbs, "apply_frac": apply_gbs / HBM_PEAK_GBS,
+                     "apply_traffic": measured_traffic("apply_traffic_bytes_f64")},
+        "apply_roofline": {"bound": "hbm", "achieved": apply_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": apply_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("apply_traffic_bytes_f64"),
+                           "algorithmic_bytes_per_apply": r["b_apply"], "ms": r["t_apply"] * 1e3,
+                           "fp32": {"achieved": res["f32"]["b_apply"] / res["f32"]["t_apply"] / 1e9,
+                                    "frac": res["f32"]["b_apply"] / res["f32"]["t_apply"] / 1e9 / HBM_PEAK_GBS,
+                                    "traffic": measured_traffic("apply_traffic_bytes_f32"),
+                                    "algorithmic_bytes_per_apply": res["f32"]["b_apply"]}},
+        "flop_rates": flop_rates({"brick_kernel<double, 3, 5>": r["t_brick"],
+                                  "brick_kernel<float, 3, 5>": res["f32"]["t_brick"]},
+                                 {"f64": r["t_apply"], "f32": res["f32"]["t_apply"]})
+        if (op.d, op.p, op.disc) == (3, 4, "cg") else None,
         "apply_effective_GBs": apply_gbs,
         "apply_hbm_frac": apply_gbs / HBM_PEAK_GBS,
         "apply_algorithmic_bytes": r["b_apply"],
