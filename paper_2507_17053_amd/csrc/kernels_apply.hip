@@ -176,7 +176,7 @@ struct EOAcc {
 
 template <typename T, int D, int N1>
 __device__ __forceinline__ void kron_cell(const KTab<T, N1> &tab, int t, const T (&x)[N1], T *A, T *B, T scale,
-                                          T (&out)[N1]) {
+                                          T (&out)[N1], bool on = true) {
   constexpr int NP = Shape<D, N1>::NP;
   {
     // last axis: a = M x, b = K x
@@ -187,10 +187,12 @@ __device__ __forceinline__ void kron_cell(const KTab<T, N1> &tab, int t, const T
     T a[N1], b[N1];
     eo_combine<T, N1>(ya.ye, ya.yo, T(1), a);
     eo_combine<T, N1>(yb.ye, yb.yo, T(1), b);
+    if (on) {
 #pragma unroll
-    for (int i = 0; i < N1; ++i) {
-      A[t + NP * i] = a[i];
-      B[t + NP * i] = b[i];
+      for (int i = 0; i < N1; ++i) {
+        A[t + NP * i] = a[i];
+        B[t + NP * i] = b[i];
+      }
     }
   }
   __syncthreads();
@@ -212,10 +214,12 @@ __device__ __forceinline__ void kron_cell(const KTab<T, N1> &tab, int t, const T
     T c[N1], e[N1];
     eo_combine<T, N1>(yc.ye, yc.yo, T(1), c);
     eo_combine<T, N1>(ye.ye, ye.yo, T(1), e);
+    if (on) {
 #pragma unroll
-    for (int i = 0; i < N1; ++i) {
-      A[ix + N1 * i + NP * iz] = c[i];
-      B[ix + N1 * i + NP * iz] = e[i];
+      for (int i = 0; i < N1; ++i) {
+        A[ix + N1 * i + NP * iz] = c[i];
+        B[ix + N1 * i + NP * iz] = e[i];
+      }
     }
     __syncthreads();
   }
@@ -233,10 +237,11 @@ __device__ __forceinline__ void kron_cell(const KTab<T, N1> &tab, int t, const T
   eo_combine<T, N1>(yo.ye, yo.yo, scale, out);
 }
 
-// Thread t's input pencil (see kron_cell) gathered through the x-run bases of a CG cell.
+// Thread t's input pencil (see kron_cell) gathered through the x-run bases of a CG cell
+// (cell_runs: the cell's (p+1)^(d-1) run bases, in LDS or in global memory).
 template <typename T, int D, int N1>
-__device__ __forceinline__ void gather_pencil(const int32_t *__restrict__ cell_runs, const T *__restrict__ u,
-                                              int t, bool act, T (&x)[N1]) {
+__device__ __forceinline__ void gather_pencil(const int32_t *cell_runs, const T *__restrict__ u, int t, bool act,
+                                              T (&x)[N1]) {
   const int i0 = (D == 3) ? t % N1 : t;
   const int r0 = (D == 3) ? t / N1 : 0;
 #pragma unroll
@@ -461,17 +466,22 @@ struct BrickCfg {
   static constexpr int EPB = EPB0 < 1 ? 1 : EPB0;   // faces per batch (and thread groups with NP threads)
   static constexpr int NG = (NT + NP - 1) / NP;      // thread groups (the last may be partial)
   // cells per batch of the per-cell path: each has two tiles of NB values; the groups beyond
-  // share one more pair of tiles (they only take part in the barriers).  In FP64 at 3D p=4 the
-  // batch is cut to 4 cells so that the tiles fit in the sweep arrays' space: 6 instead of 5
-  // workgroups per CU.
+  // only take part in the barriers.  In FP64 at 3D p=4 the batch is cut to 4 cells so that the
+  // tiles and the staged run bases fit in the sweep arrays' space.
   static constexpr int EPC0 = (sizeof(T) == 8 && D == 3 && P == 4) ? 4 : EPB;
   static constexpr int EPC = EPC0 < EPB ? EPC0 : EPB;
-  static constexpr int NTILE = EPC < NG ? EPC + 1 : NG;  // tile pairs
+  static constexpr int NTILE = EPC;  // tile pairs (the other groups store nothing)
   // LDS in elements of T: the lattice accumulator (the cell and face rows are summed into it in
   // the apply's precision, in a fixed order), then either the second sweep array of the full
   // path (the first one is the accumulator itself) or the per-cell tiles.
+  static constexpr int MAXC = BX * BY * BZ;  // cells of a full brick
   static constexpr int TAIL_SWEEP = NL;
-  static constexpr int TAIL_CELLS = 2 * NTILE * NB;
+  // per-cell path: the tiles, then (where they are small: p >= 4 in 3D) the brick's run
+  // bases and cell offsets (int32), staged in one round trip instead of read per batch
+  static constexpr int RUNS_B = (MAXC * NP + MAXC) * 4;
+  static constexpr bool STAGE_RUNS = RUNS_B <= 2560;
+  static constexpr int RUNS_T = STAGE_RUNS ? (RUNS_B + (int)sizeof(T) - 1) / (int)sizeof(T) : 0;
+  static constexpr int TAIL_CELLS = 2 * NTILE * NB + RUNS_T;
   static constexpr int SMEM = NL + (TAIL_SWEEP > TAIL_CELLS ? TAIL_SWEEP : TAIL_CELLS);
 };
 
@@ -517,15 +527,39 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
   // lattice offset of thread t's x-run inside a cell tile
   const int run_off = (D == 3) ? (t % N1) * LX + (t / N1) * LX * LY : t * LX;
   const int c0 = br.cell_off[brick], c1 = br.cell_off[brick + 1];
-  const bool full = (c1 - c0) == BX * BY * BZ;
-  // the brick's row descriptors, staged once: every later lattice access indexes them
+  const int f0 = br.face_off[brick], f1e = br.face_off[brick + 1];
+  const bool full = (c1 - c0) == C::MAXC;
+  // Everything that does not depend on u is fetched in one round trip at the start: the
+  // brick's row descriptors (every later lattice access indexes them), for a partial brick
+  // its cells' run bases and lattice offsets, and the first batch of surrogate-face results
+  // (held in registers through the cell phase).
   __shared__ int32_t s_base[NROWS], s_hbase[NROWS];
   __shared__ uint32_t s_gmask[NROWS], s_bmask[NROWS];
+  // (the partial brick's run bases and cell offsets sit behind the per-cell tiles)
+  int32_t *const s_runs = reinterpret_cast<int32_t *>(tail + 2 * C::NTILE * NB);
+  int32_t *const s_loc = s_runs + C::MAXC * NP;
   for (int r = tid; r < NROWS; r += nthr) {
     s_base[r] = br.row_base[rb + r];
     s_hbase[r] = br.row_hbase[rb + r];
     s_gmask[r] = br.row_gmask[rb + r];
     s_bmask[r] = br.row_bmask[rb + r];
+  }
+  if (C::STAGE_RUNS && !full && (parts & SBM_PART_CELLS)) {
+    for (int i = tid; i < (c1 - c0) * NP; i += nthr) s_runs[i] = br.runs[(int64_t)c0 * NP + i];
+    for (int i = tid; i < c1 - c0; i += nthr) s_loc[i] = br.cell_loc[c0 + i];
+  }
+  // a cell's run bases and lattice offset (by the cell's rank inside the brick)
+  const int32_t *const runs_of = C::STAGE_RUNS ? s_runs : br.runs + (int64_t)c0 * NP;
+  const int32_t *const loc_of = C::STAGE_RUNS ? s_loc : br.cell_loc + c0;
+  const bool do_faces = (parts & SBM_PART_SBM_FACES) != 0;
+  int fcode = 0, floc = 0;
+  T fRv = T(0), fRg = T(0);
+  if (do_faces && le < EPB && f0 + le < f1e) {
+    const int f = f0 + le;
+    fcode = br.face_code[f];
+    floc = br.face_loc[f];
+    fRv = fbuf[(int64_t)f * 2 * NP + t];
+    fRg = fbuf[(int64_t)f * 2 * NP + NP + t];
   }
   __syncthreads();
 
@@ -543,18 +577,30 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     {
       constexpr int NC = (D == 3) ? BZ : BY, G = LaneGroup<NC>::G;
       constexpr int NLINE = (D == 3) ? LX * LY : LX;
-      for (int q = tid; q < NLINE * G; q += nthr) {
+      // every thread's segments are loaded before any is swept: one round trip to memory
+      constexpr int NQ = (NLINE * G + nthr - 1) / nthr;
+      T xus[NQ][N1];
+#pragma unroll
+      for (int r = 0; r < NQ; ++r) {
+        const int q = tid + r * nthr;
         const int j = q % G, line = q / G;
         const int x = line % LX, y = (D == 3) ? line / LX : 0;
-        const bool live = j < NC;
-        T xu[N1], ya[N1], yb[N1];
+        const bool live = q < NLINE * G && j < NC;
 #pragma unroll
         for (int i = 0; i < N1; ++i) {
           const int row = (D == 3) ? y + LY * (j * P + i) : (j * P + i);
-          xu[i] = live ? u[s_base[row] + x] : T(0);
+          xus[r][i] = live ? u[s_base[live ? row : 0] + x] : T(0);
         }
+      }
+#pragma unroll
+      for (int r = 0; r < NQ; ++r) {
+        const int q = tid + r * nthr;
+        const int j = q % G, line = q / G;
+        const int x = line % LX, y = (D == 3) ? line / LX : 0;
+        const bool live = q < NLINE * G && j < NC;
+        T ya[N1], yb[N1];
         {
-          const EvenOdd<T, N1> ex(xu);
+          const EvenOdd<T, N1> ex(xus[r]);
           EOAcc<T, N1> aa, ab;
           eo_acc<T, N1>(tab.EM, tab.OM, ex, aa.ye, aa.yo);
           eo_acc<T, N1>(tab.EK, tab.OK, ex, ab.ye, ab.yo);
@@ -656,24 +702,24 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     // ---- partial brick: cell by cell (EPC cells per batch; the other thread groups only
     // take part in the barriers) ----
     constexpr int EPC = C::EPC, NTILE = C::NTILE;
-    const int tl = le < EPC ? le : NTILE - 1;  // groups beyond EPC share the last tile pair
-    T *A = tail + tl * NB, *B = tail + NTILE * NB + tl * NB;
     const bool grp = le < EPC;
+    const int tl = grp ? le : 0;  // groups beyond EPC only take part in the barriers
+    T *A = tail + tl * NB, *B = tail + NTILE * NB + tl * NB;
     // software pipeline: the pencils of batch b+1 are in flight while batch b computes
     T x[N1];
     {
       const bool act = grp && c0 + le < c1;
-      gather_pencil<T, D, N1>(br.runs + (int64_t)(act ? c0 + le : 0) * NP, u, t, act, x);
+      gather_pencil<T, D, N1>(runs_of + (act ? le : 0) * NP, u, t, act, x);
     }
     for (int b = c0; b < c1; b += EPC) {
       const int idx = b + le;
       const bool act = grp && idx < c1;
-      const int loc = act ? br.cell_loc[idx] : 0;
+      const int loc = act ? loc_of[idx - c0] : 0;
       const int idn = idx + EPC;
       const bool actn = grp && idn < c1;
       T xn[N1], out[N1];
-      gather_pencil<T, D, N1>(br.runs + (int64_t)(actn ? idn : 0) * NP, u, t, actn, xn);
-      kron_cell<T, D, N1>(tab, t, x, A, B, scale, out);
+      gather_pencil<T, D, N1>(runs_of + (actn ? idn - c0 : 0) * NP, u, t, actn, xn);
+      kron_cell<T, D, N1>(tab, t, x, A, B, scale, out, grp);
 #pragma unroll
       for (int i = 0; i < N1; ++i) x[i] = xn[i];
       // the batch's cells add their rows in slot order (a cell's runs are disjoint), so every
@@ -688,20 +734,30 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
       }
     }
   }
-  if (parts & SBM_PART_SBM_FACES) {
+  if (do_faces) {
     // ---- the brick's surrogate faces: sbm_face_cg_kernel left (Rv, Rg) per face node in
-    // fbuf; expand them into the (p+1)^d local rows and add those into the lattice ----
-    const int f0 = br.face_off[brick], f1e = br.face_off[brick + 1];
+    // fbuf; expand them into the (p+1)^d local rows and add those into the lattice.  The
+    // batch's data is in registers (the first batch since the start); the next batch's is
+    // fetched while this one merges. ----
     constexpr int SL1 = LX, SL2 = LX * LY;  // lattice strides of axes 1 and 2
     for (int b = f0; b < f1e; b += EPB) {
       const int f = b + le;
       const bool fact = le < EPB && f < f1e;
+      const int fn = f + EPB;
+      int ncode = 0, nloc = 0;
+      T nRv = T(0), nRg = T(0);
+      if (le < EPB && fn < f1e) {
+        ncode = br.face_code[fn];
+        nloc = br.face_loc[fn];
+        nRv = fbuf[(int64_t)fn * 2 * NP + t];
+        nRg = fbuf[(int64_t)fn * 2 * NP + NP + t];
+      }
       int node = 0, Sa = 0;
       T row[N1];
       if (fact) {
-        const FaceAxes<D, N1> fa(br.face_code[f]);
-        const int loc = br.face_loc[f];
-        const T Rv = fbuf[(int64_t)f * 2 * NP + t], Rg = fbuf[(int64_t)f * 2 * NP + NP + t];
+        const FaceAxes<D, N1> fa(fcode);
+        const int loc = floc;
+        const T Rv = fRv, Rg = fRg;
         const int a = fa.a;
         const int jb = (D == 3) ? t % N1 : t, jc = (D == 3) ? t / N1 : 0;
         // normal axis a; tangential axes in increasing order (b < c), as in FaceAxes
@@ -721,6 +777,10 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
         }
         __syncthreads();
       }
+      fcode = ncode;
+      floc = nloc;
+      fRv = nRv;
+      fRg = nRg;
     }
   }
   __syncthreads();
