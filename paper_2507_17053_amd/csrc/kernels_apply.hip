@@ -481,7 +481,9 @@ struct BrickCfg {
   static constexpr int RUNS_B = (MAXC * NP + MAXC) * 4;
   static constexpr bool STAGE_RUNS = RUNS_B <= 2560;
   static constexpr int RUNS_T = STAGE_RUNS ? (RUNS_B + (int)sizeof(T) - 1) / (int)sizeof(T) : 0;
-  static constexpr int TAIL_CELLS = 2 * NTILE * NB + RUNS_T;
+  // ... then the partial brick's row masks (a full brick's are all ones)
+  static constexpr int MASK_T = (2 * NROWS * 4 + (int)sizeof(T) - 1) / (int)sizeof(T);
+  static constexpr int TAIL_CELLS = 2 * NTILE * NB + RUNS_T + MASK_T;
   static constexpr int SMEM = NL + (TAIL_SWEEP > TAIL_CELLS ? TAIL_SWEEP : TAIL_CELLS);
 };
 
@@ -534,15 +536,20 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
   // its cells' run bases and lattice offsets, and the first batch of surrogate-face results
   // (held in registers through the cell phase).
   __shared__ int32_t s_base[NROWS], s_hbase[NROWS];
-  __shared__ uint32_t s_gmask[NROWS], s_bmask[NROWS];
-  // (the partial brick's run bases and cell offsets sit behind the per-cell tiles)
+  // (the partial brick's run bases, cell offsets and row masks sit behind the per-cell tiles;
+  // a full brick's rows are all DoFs, all touched by its cells: masks of all ones, not stored,
+  // which keeps the static LDS small enough for one more workgroup per CU)
   int32_t *const s_runs = reinterpret_cast<int32_t *>(tail + 2 * C::NTILE * NB);
   int32_t *const s_loc = s_runs + C::MAXC * NP;
+  uint32_t *const s_gmask = reinterpret_cast<uint32_t *>(tail + 2 * C::NTILE * NB + C::RUNS_T);
+  uint32_t *const s_bmask = s_gmask + NROWS;
   for (int r = tid; r < NROWS; r += nthr) {
     s_base[r] = br.row_base[rb + r];
     s_hbase[r] = br.row_hbase[rb + r];
-    s_gmask[r] = br.row_gmask[rb + r];
-    s_bmask[r] = br.row_bmask[rb + r];
+    if (!full) {
+      s_gmask[r] = br.row_gmask[rb + r];
+      s_bmask[r] = br.row_bmask[rb + r];
+    }
   }
   if (C::STAGE_RUNS && !full && (parts & SBM_PART_CELLS)) {
     for (int i = tid; i < (c1 - c0) * NP; i += nthr) s_runs[i] = br.runs[(int64_t)c0 * NP + i];
@@ -797,7 +804,8 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     const int pt = tid + k * C::NT;
     const int ptc = pt < NL ? pt : 0;
     const int x = ptc % LX, row = ptc / LX;
-    const uint32_t bm = s_bmask[row], gm = s_gmask[row];
+    constexpr uint32_t ALL = (LX == 32) ? 0xffffffffu : ((1u << LX) - 1u);
+    const uint32_t bm = full ? ALL : s_bmask[row], gm = full ? ALL : s_gmask[row];
     const uint32_t below = (1u << x) - 1u;
     const int y = row % LY, z = row / LY;
     const bool brow = y == 0 || y == LY - 1 || (D == 3 && (z == 0 || z == LZ - 1));
