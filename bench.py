@@ -136,6 +136,8 @@ OTHER_CONFIGS = [
     # (label, workload, overrides)
     ("torus3d_dg_q3", "torus3d_dg", {}),
     ("torus3d_dg_q5", "torus3d_dg", {"p": 5}),
+    # DG at a size that fills the device (about 0.36M cells)
+    ("torus3d_dg_q3_n80", "torus3d_dg", {"n": 80}),
     ("spheres3d_q6", "spheres3d_q6", {}),
     # working set (vectors alone 229 MB in FP64) above the 256 MB last-level cache together
     ("sphere3d_q4_n128", "sphere3d_q4", {"n": 128}),
