@@ -1,6 +1,6 @@
-// Vector kernels used around the operator: fill, precision casts, fused axpy forms and
-// deterministic two-pass reductions (block partial sums, then one block sums them in a
-// fixed order).
+// Vector fill (x = val in FP64 or FP32), used by the solver to clear its vectors.  The other
+// vector operations of the solvers (casts, fused updates, reductions) live in solver.hip,
+// fused into the kernels that need them.
 #include "sbm_internal.h"
 
 namespace sbm {
