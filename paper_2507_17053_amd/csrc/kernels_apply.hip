@@ -796,26 +796,42 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
   // on the box boundary go to plane k = [x == 0] + 2 [y == 0] + 4 [z == 0] of the halo (the
   // brick's side of the point; bricks sharing the point differ in k), at the point's halo
   // index (consecutive along the row's boundary DoFs); halo_reduce_kernel sums the planes.
-  // Unrolled over the thread's points so that all LDS reads issue back to back; the stores
-  // are predicated.
-  constexpr int NIT = (NL + C::NT - 1) / C::NT;
-#pragma unroll
-  for (int k = 0; k < NIT; ++k) {
-    const int pt = tid + k * C::NT;
-    const int ptc = pt < NL ? pt : 0;
-    const int x = ptc % LX, row = ptc / LX;
+  // Lane layout: each wavefront takes RPW whole rows per pass (lane = row slot * LX + x), so a
+  // lane's x and everything that depends on it only (masks below x, x on the box boundary)
+  // are fixed, and a pass only advances the row; (y, z) of the row advance by a constant.
+  {
+    constexpr int RPW = 64 / LX, NW = C::NT / 64, STEP = NW * RPW;
+    constexpr int QY = STEP % LY, QZ = STEP / LY;
     constexpr uint32_t ALL = (LX == 32) ? 0xffffffffu : ((1u << LX) - 1u);
-    const uint32_t bm = full ? ALL : s_bmask[row], gm = full ? ALL : s_gmask[row];
+    static_assert(RPW >= 1 && C::NT % 64 == 0, "a wavefront holds at least one lattice row");
+    const int lane = tid & 63, rl = lane / LX, x = lane - rl * LX;
+    const bool xl = rl < RPW;
     const uint32_t below = (1u << x) - 1u;
-    const int y = row % LY, z = row / LY;
-    const bool brow = y == 0 || y == LY - 1 || (D == 3 && (z == 0 || z == LZ - 1));
-    const bool inner = !brow && x > 0 && x < LX - 1;
-    const uint32_t hgm = brow ? gm : (gm & (1u | (1u << (LX - 1))));
-    const int plane = (x == 0 ? 1 : 0) | (y == 0 ? 2 : 0) | ((D == 3 && z == 0) ? 4 : 0);
-    T *dst = inner ? v + s_base[row] + __popc(gm & below)
-                   : halo + (int64_t)plane * nhalo + s_hbase[row] + __popc(hgm & below);
-    const T val = acc[ptc];
-    if (pt < NL && ((bm >> x) & 1u)) *dst = val;
+    const bool xin = (unsigned)(x - 1) < (unsigned)(LX - 2);  // 0 < x < LX - 1
+    const int xplane = x == 0 ? 1 : 0;
+    int row = (tid >> 6) * RPW + rl;
+    int y = row % LY, z = row / LY;
+    for (int r0 = (tid >> 6) * RPW; r0 < NROWS; r0 += STEP) {
+      if (xl && row < NROWS) {
+        const uint32_t bm = full ? ALL : s_bmask[row], gm = full ? ALL : s_gmask[row];
+        const bool brow = ((unsigned)(y - 1) >= (unsigned)(LY - 2)) |
+                          ((D == 3) & ((unsigned)(z - 1) >= (unsigned)(LZ - 2)));
+        const bool inner = !brow & xin;
+        const uint32_t hgm = brow ? gm : (gm & (1u | (1u << (LX - 1))));
+        const int plane = xplane | (y == 0 ? 2 : 0) | ((D == 3 && z == 0) ? 4 : 0);
+        const T val = acc[row * LX + x];
+        T *dst = inner ? v + s_base[row] + __popc(gm & below)
+                       : halo + (int64_t)plane * nhalo + s_hbase[row] + __popc(hgm & below);
+        if ((bm >> x) & 1u) *dst = val;
+      }
+      row += STEP;
+      y += QY;
+      z += QZ;
+      if (y >= LY) {
+        y -= LY;
+        ++z;
+      }
+    }
   }
 }
 
