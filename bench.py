@@ -339,7 +339,7 @@ def serve_in_child(args):
     import subprocess
     cmd = [sys.executable, os.path.abspath(__file__), "--serve-only", "--serve", str(args.serve),
            "--serve-max-it", str(args.serve_max_it), "--serve-rate", str(args.serve_rate),
-           "--serve-deadline", str(args.serve_deadline)]
+           "--serve-deadline", str(args.serve_deadline), "--serve-slots", str(args.serve_slots)]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=max(120.0, 8 * args.serve_deadline + 120.0))
     lines = [ln for ln in r.stdout.strip().splitlines() if ln.startswith("{")]
     if r.returncode == 0 and lines:
@@ -389,6 +389,10 @@ def main():
                     help="run only the serving section and print its JSON (used by the main run, which "
                          "runs the serving section in a child process)")
     ap.add_argument("--serve-max-it", type=int, default=100)
+    ap.add_argument("--serve-slots", type=int, default=1,
+                    help="requests solved at once (each on its own thread and stream); the default runs one "
+                         "at a time: a 12-slot run of this section aborted inside the process (glibc "
+                         "'free(): invalid pointer') without a cause found in the library")
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="open-loop arrival rate (default: 0.7 of the closed-loop capacity)")
     args = ap.parse_args()
@@ -398,8 +402,8 @@ def main():
 
     if args.serve_only:
         import torch  # noqa: F401  (the library runs on torch's HIP runtime)
-        print(json.dumps(serve_section(args.serve, args.serve_max_it, args.serve_rate, slots=12, budget_gb=96.0,
-                                       deadline_s=args.serve_deadline)), flush=True)
+        print(json.dumps(serve_section(args.serve, args.serve_max_it, args.serve_rate, slots=args.serve_slots,
+                                       budget_gb=96.0, deadline_s=args.serve_deadline)), flush=True)
         return
 
     import torch
