@@ -799,8 +799,10 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
   // Lane layout: each wavefront takes RPW whole rows per pass (lane = row slot * LX + x), so a
   // lane's x and everything that depends on it only (masks below x, x on the box boundary)
   // are fixed, and a pass only advances the row; (y, z) of the row advance by a constant.
+  // The passes are unrolled, every LDS read first, so that one wait covers them all.
   {
     constexpr int RPW = 64 / LX, NW = C::NT / 64, STEP = NW * RPW;
+    constexpr int NPASS = (NROWS + STEP - 1) / STEP;
     constexpr int QY = STEP % LY, QZ = STEP / LY;
     constexpr uint32_t ALL = (LX == 32) ? 0xffffffffu : ((1u << LX) - 1u);
     static_assert(RPW >= 1 && C::NT % 64 == 0, "a wavefront holds at least one lattice row");
@@ -809,27 +811,42 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
     const uint32_t below = (1u << x) - 1u;
     const bool xin = (unsigned)(x - 1) < (unsigned)(LX - 2);  // 0 < x < LX - 1
     const int xplane = x == 0 ? 1 : 0;
-    int row = (tid >> 6) * RPW + rl;
-    int y = row % LY, z = row / LY;
-    for (int r0 = (tid >> 6) * RPW; r0 < NROWS; r0 += STEP) {
-      if (xl && row < NROWS) {
-        const uint32_t bm = full ? ALL : s_bmask[row], gm = full ? ALL : s_gmask[row];
+    const int row0 = (tid >> 6) * RPW + rl;
+    int y = row0 % LY, z = row0 / LY;
+    constexpr int CH = NPASS < 9 ? NPASS : 9;  // passes per group (bounds the registers held)
+#pragma unroll
+    for (int k0 = 0; k0 < NPASS; k0 += CH) {
+      T val[CH];
+      int base[CH], hb[CH];
+      uint32_t gmk[CH], bmk[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int row = row0 + (k0 + k) * STEP;
+        const bool on = xl && k0 + k < NPASS && row < NROWS;
+        const int rc = on ? row : 0;
+        val[k] = acc[rc * LX + x];
+        base[k] = s_base[rc];
+        hb[k] = s_hbase[rc];
+        gmk[k] = full ? ALL : s_gmask[rc];
+        bmk[k] = (full || !on) ? (on ? ALL : 0u) : s_bmask[rc];
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const uint32_t gm = gmk[k];
         const bool brow = ((unsigned)(y - 1) >= (unsigned)(LY - 2)) |
                           ((D == 3) & ((unsigned)(z - 1) >= (unsigned)(LZ - 2)));
         const bool inner = !brow & xin;
         const uint32_t hgm = brow ? gm : (gm & (1u | (1u << (LX - 1))));
         const int plane = xplane | (y == 0 ? 2 : 0) | ((D == 3 && z == 0) ? 4 : 0);
-        const T val = acc[row * LX + x];
-        T *dst = inner ? v + s_base[row] + __popc(gm & below)
-                       : halo + (int64_t)plane * nhalo + s_hbase[row] + __popc(hgm & below);
-        if ((bm >> x) & 1u) *dst = val;
-      }
-      row += STEP;
-      y += QY;
-      z += QZ;
-      if (y >= LY) {
-        y -= LY;
-        ++z;
+        T *dst = inner ? v + base[k] + __popc(gm & below)
+                       : halo + (int64_t)plane * nhalo + hb[k] + __popc(hgm & below);
+        if ((bmk[k] >> x) & 1u) *dst = val[k];
+        y += QY;
+        z += QZ;
+        if (y >= LY) {
+          y -= LY;
+          ++z;
+        }
       }
     }
   }
