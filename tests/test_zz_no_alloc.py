@@ -1,8 +1,8 @@
 """sbm_apply_noalloc (the apply for callers that cannot allocate) against sbm_apply, through
 the C ABI: the same operator with the scratch taken from the library's static device array.
-With the default extension every sum is taken in a fixed order, so the two agree bit for bit;
-with a truncated extension (atomics in its face kernel) to the parity bar's rounding level.
-Two calls in a row on the shared array, the second with a smaller operator and input."""
+Every sum of the apply (default or truncated extension) is taken in an order fixed by the
+setup, so the two agree bit for bit.  Two calls in a row on the shared array, the second with a
+smaller operator and input."""
 
 import numpy as np
 import pytest
@@ -43,11 +43,10 @@ def test_noalloc_equals_apply_twice_second_smaller(dtype):
 def test_noalloc_truncated_extension_matches_apply(dtype):
     op = sbm.Operator(3, 16, -1.0, 1.0, inputs.sphere((0, 0, 0), 0.75), 3, taylor_order=1)
     small = sbm.Operator(2, 16, -1.0, 1.0, inputs.sphere((0.05, -0.03), 0.7), 2, taylor_order=1)
-    tol = 1e-13 if dtype == torch.float64 else 1e-6
     for o, seed in ((op, 0), (small, 1)):
         out, ref = _pair(o, seed, dtype)
-        err = (torch.linalg.norm((out - ref).double()) / torch.linalg.norm(ref.double())).item()
-        assert err <= tol, err
+        assert torch.isfinite(out).all()
+        assert torch.equal(out, ref), (o.n_dofs, (out - ref).abs().max().item())
     op.close()
     small.close()
 
