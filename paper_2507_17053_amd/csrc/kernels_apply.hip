@@ -7,6 +7,8 @@
 //                   surrogate-boundary faces (Alg. 3); points strictly inside the brick are
 //                   then stored to v directly, points on the brick's boundary (shared with
 //                   neighbouring bricks) go to halo slots that halo_reduce_kernel sums.
+//   sbm_face_cg_kernel  CG surrogate-boundary faces (Alg. 3), before the bricks: (Rv, Rg)
+//                   per face node, which the brick holding the face's cell expands and merges.
 //   sbm_face_kernel DG surrogate-boundary faces (Alg. 3): (Rv, Rg) per face node.
 //   dg_cell_kernel  DG: Laplace cell term plus the SIPG terms of the cell's interior faces,
 //                   evaluated cell by cell (Alg. 2 split per side), plus the rows of the

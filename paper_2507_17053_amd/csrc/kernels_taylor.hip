@@ -9,10 +9,11 @@
 // in reference coordinates of the face's own cell (D_x^alpha d^alpha = D_xi^alpha delta^alpha,
 // delta = xi - xi~).  m = 1 is the value-plus-gradient form; m >= d p is the full extension.
 //
-// Only the surrogate-face term changes: with an order set on a handle, the apply runs the cell
-// term (and the DG interior faces) through the default kernels with the surrogate faces left
-// out, then adds the faces' rows from sbm_face_taylor_kernel.  The diagonal is the default one
-// plus a correction of its surrogate-face term.
+// Only the surrogate-face term changes: with an order set on a handle, sbm_face_taylor_kernel
+// leaves each face's (Rv, Rg) per face node in the handle's face buffer, and the default cell
+// kernels (brick kernel for CG, cell kernel for DG) then expand and merge them in face order,
+// exactly as for the full extension.  The diagonal is the default one plus a correction of its
+// surrogate-face term.
 #include "sbm_internal.h"
 
 namespace sbm {
