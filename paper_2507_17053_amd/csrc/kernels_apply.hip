@@ -178,9 +178,11 @@ struct EOAcc {
 
 template <typename T, int D, int N1>
 __device__ __forceinline__ void kron_cell(const KTab<T, N1> &tab, int t, const T (&x)[N1], T *A, T *B, T scale,
-                                          T (&out)[N1], bool on = true) {
+                                          T (&out)[N1], bool on = true, bool work = true) {
+  // on = false: compute but store nothing; work = false: only take part in the barriers (out
+  // is left as it was)
   constexpr int NP = Shape<D, N1>::NP;
-  {
+  if (work) {
     // last axis: a = M x, b = K x
     const EvenOdd<T, N1> ex(x);
     EOAcc<T, N1> ya, yb;
@@ -202,41 +204,47 @@ __device__ __forceinline__ void kron_cell(const KTab<T, N1> &tab, int t, const T
     // pencils along axis 1; c = M a, e = K a + M b
     const int ix = t % N1, iz = t / N1;
     T a[N1], b[N1];
+    if (work) {
 #pragma unroll
-    for (int j = 0; j < N1; ++j) {
-      a[j] = A[ix + N1 * j + NP * iz];
-      b[j] = B[ix + N1 * j + NP * iz];
+      for (int j = 0; j < N1; ++j) {
+        a[j] = A[ix + N1 * j + NP * iz];
+        b[j] = B[ix + N1 * j + NP * iz];
+      }
     }
     __syncthreads();
-    const EvenOdd<T, N1> ea(a), eb(b);
-    EOAcc<T, N1> yc, ye;
-    eo_acc<T, N1>(tab.EM, tab.OM, ea, yc.ye, yc.yo);
-    eo_acc<T, N1>(tab.EK, tab.OK, ea, ye.ye, ye.yo);
-    eo_acc<T, N1>(tab.EM, tab.OM, eb, ye.ye, ye.yo);
-    T c[N1], e[N1];
-    eo_combine<T, N1>(yc.ye, yc.yo, T(1), c);
-    eo_combine<T, N1>(ye.ye, ye.yo, T(1), e);
-    if (on) {
+    if (work) {
+      const EvenOdd<T, N1> ea(a), eb(b);
+      EOAcc<T, N1> yc, ye;
+      eo_acc<T, N1>(tab.EM, tab.OM, ea, yc.ye, yc.yo);
+      eo_acc<T, N1>(tab.EK, tab.OK, ea, ye.ye, ye.yo);
+      eo_acc<T, N1>(tab.EM, tab.OM, eb, ye.ye, ye.yo);
+      T c[N1], e[N1];
+      eo_combine<T, N1>(yc.ye, yc.yo, T(1), c);
+      eo_combine<T, N1>(ye.ye, ye.yo, T(1), e);
+      if (on) {
 #pragma unroll
-      for (int i = 0; i < N1; ++i) {
-        A[ix + N1 * i + NP * iz] = c[i];
-        B[ix + N1 * i + NP * iz] = e[i];
+        for (int i = 0; i < N1; ++i) {
+          A[ix + N1 * i + NP * iz] = c[i];
+          B[ix + N1 * i + NP * iz] = e[i];
+        }
       }
     }
     __syncthreads();
   }
-  // pencils along axis 0 (thread t = run index); out = K c + M e
-  T c[N1], e[N1];
+  if (work) {
+    // pencils along axis 0 (thread t = run index); out = K c + M e
+    T c[N1], e[N1];
 #pragma unroll
-  for (int j = 0; j < N1; ++j) {
-    c[j] = A[j + N1 * t];
-    e[j] = B[j + N1 * t];
+    for (int j = 0; j < N1; ++j) {
+      c[j] = A[j + N1 * t];
+      e[j] = B[j + N1 * t];
+    }
+    const EvenOdd<T, N1> ec(c), ee(e);
+    EOAcc<T, N1> yo;
+    eo_acc<T, N1>(tab.EK, tab.OK, ec, yo.ye, yo.yo);
+    eo_acc<T, N1>(tab.EM, tab.OM, ee, yo.ye, yo.yo);
+    eo_combine<T, N1>(yo.ye, yo.yo, scale, out);
   }
-  const EvenOdd<T, N1> ec(c), ee(e);
-  EOAcc<T, N1> yo;
-  eo_acc<T, N1>(tab.EK, tab.OK, ec, yo.ye, yo.yo);
-  eo_acc<T, N1>(tab.EM, tab.OM, ee, yo.ye, yo.yo);
-  eo_combine<T, N1>(yo.ye, yo.yo, scale, out);
 }
 
 // Thread t's input pencil (see kron_cell) gathered through the x-run bases of a CG cell
@@ -1299,7 +1307,7 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
                                                       int parts) {
   constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, P = N1 - 1, NF = 2 * D, TPC = NF * NP;
   __shared__ T su_all[EPB * NB];           // own tile
-  __shared__ T sab_all[(2 * EPB + 2) * NB];  // cell-term tiles (A, B) per cell + one shared scratch pair
+  __shared__ T sab_all[2 * EPB * NB];        // cell-term tiles (A, B) per cell
   __shared__ T sn_all[EPB * NF * NB];      // neighbour tiles, one per face
   __shared__ T sw_all[EPB * NB];           // cell term
   __shared__ T f_all[EPB * NF * 6 * NP];   // per face: f1..f4 scratch, Rv, Rg
@@ -1308,8 +1316,6 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
   const int cell = xcd_block() * EPB + le;
   const bool act = cell < n_cells;
   T *su = su_all + le * NB, *sw = sw_all + le * NB;
-  T *A = (g == 0) ? sab_all + 2 * le * NB : sab_all + 2 * EPB * NB;
-  T *B = A + NB;
   T *An = sn_all + (le * NF + g) * NB;
   T *fw = f_all + (le * NF + g) * 6 * NP;
   T *f1 = fw, *f2 = fw + NP, *f3 = fw + 2 * NP, *f4 = fw + 3 * NP, *fRv = fw + 4 * NP, *fRg = fw + 5 * NP;
@@ -1373,15 +1379,20 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
       fRg[t] = T(0);
     }
   }
-  // ---- cell term (group 0; the other groups on the shared scratch tiles) ----
+  // ---- cell term: the block's first EPB * NP threads, NP per cell (whole wavefronts beyond
+  // them only take part in the barriers) ----
   {
+    const int lc = threadIdx.x / NP, tc = threadIdx.x - lc * NP;
+    const bool work = lc < EPB;
+    const int lw = work ? lc : 0;
+    T *A = sab_all + 2 * lw * NB, *B = A + NB;
     T x[N1], out[N1];
 #pragma unroll
-    for (int k = 0; k < N1; ++k) x[k] = su[t + NP * k];
-    kron_cell<T, D, N1>(tab, t, x, A, B, scale, out);
-    if (g == 0) {
+    for (int k = 0; k < N1; ++k) x[k] = work ? su_all[lw * NB + tc + NP * k] : T(0);
+    kron_cell<T, D, N1>(tab, tc, x, A, B, scale, out, true, work);
+    if (work) {
 #pragma unroll
-      for (int i = 0; i < N1; ++i) sw[N1 * t + i] = use_int ? out[i] : T(0);
+      for (int i = 0; i < N1; ++i) sw_all[lw * NB + N1 * tc + i] = use_int ? out[i] : T(0);
     }
   }
   __syncthreads();
