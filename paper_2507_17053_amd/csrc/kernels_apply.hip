@@ -736,7 +736,7 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
       const bool actn = grp && idn < c1;
       T xn[N1], out[N1];
       gather_pencil<T, D, N1>(runs_of + (actn ? idn - c0 : 0) * NP, u, t, actn, xn);
-      kron_cell<T, D, N1>(tab, t, x, A, B, scale, out, grp);
+      kron_cell<T, D, N1>(tab, t, x, A, B, scale, out, grp, grp);
 #pragma unroll
       for (int i = 0; i < N1; ++i) x[i] = xn[i];
       // the batch's cells add their rows in slot order (a cell's runs are disjoint), so every
