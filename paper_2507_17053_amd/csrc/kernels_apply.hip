@@ -1284,8 +1284,8 @@ __global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int
 }
 
 // Thread layout: 2d groups of NP threads per cell, group g evaluates interior face g (code
-// 2 axis + side) with its own neighbour tile and scratch, all faces at once; group 0 also
-// forms the cell term (the other groups pass its barriers on a shared scratch pair of tiles).
+// 2 axis + side) with its own neighbour tile and scratch, all faces at once; then the block's
+// first EPB NP threads form the cells' terms (NP per cell; the rest only pass the barriers).
 // Then every row of the cell adds the cell term and the faces' rows in face order (the order
 // of a face-by-face loop); a face without a neighbour contributes the surrogate face's rows.
 template <typename T, int D, int N1>
@@ -1296,7 +1296,7 @@ constexpr int dg_cells_per_block(bool one_wave) {
   constexpr int per_cell = ((4 + 2 * D) * NB + 2 * D * 6 * NP) * (int)sizeof(T);
   int e = (one_wave ? 64 : 256) / TPC;
   if (e < 1) e = 1;
-  while (e > 1 && e * per_cell + 2 * NB * (int)sizeof(T) > 60000) --e;
+  while (e > 1 && e * per_cell > 60000) --e;
   return e;
 }
 
