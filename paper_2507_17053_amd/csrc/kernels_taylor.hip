@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kTaylorThreads) void sbm_face_taylor_kernel(
   }
   __syncthreads();
   // tangential axes of the face, lower one first (face point q = qb + N1 qc)
-  const int tb = a == 0 ? 1 : 0, tc = a == 2 ? 1 : 2;
+  const int tb = a == 0 ? 1 : 0;  // (the upper tangential axis is the remaining one)
   for (int t = threadIdx.x; t < NP * S; t += blockDim.x) {
     const int q = t % NP, slab = t / NP;
     const int qb = q % N1, qc = D == 3 ? q / N1 : 0;

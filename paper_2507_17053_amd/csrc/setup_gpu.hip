@@ -364,7 +364,7 @@ __global__ void halo_rows_kernel(Geo g, Bricks bk, int64_t nbricks, const int32_
       if (!((hgm >> x) & 1u)) continue;
       const int32_t h = hidx(x);
       // every boundary DoF of the row is a halo DoF, numbered consecutively along the row
-      if (h < 0 || h != hb + __popc(hgm & ((1u << x) - 1u))) atomicOr(bad, 2);
+      if (h < 0 || h != hb + (int32_t)__popc(hgm & ((1u << x) - 1u))) atomicOr(bad, 2);
       if ((hm >> x) & 1u) {
         const int k = (x == 0 ? 1 : 0) | (y == 0 ? 2 : 0) | ((g.d == 3 && z == 0) ? 4 : 0);
         if (h >= 0) atomicOr(&hmask32[h], 1u << k);
@@ -574,7 +574,7 @@ sbm_status device_setup_impl(sbm_ctx *c, Temps &tmp) {
                        xtrue, bad);
 
   // ---- CG bricks ----
-  int32_t *d_bid = nullptr, *d_cell_off = nullptr, *d_face_off = nullptr;
+  int32_t *d_bid = nullptr;
   int64_t *d_key_of = nullptr;
   int32_t *hflag = nullptr, *hpre = nullptr;
   if (cg) {
