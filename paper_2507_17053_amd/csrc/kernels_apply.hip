@@ -476,9 +476,9 @@ struct BrickCfg {
   static constexpr int EPB = EPB0 < 1 ? 1 : EPB0;   // faces per batch (and thread groups with NP threads)
   static constexpr int NG = (NT + NP - 1) / NP;      // thread groups (the last may be partial)
   // cells per batch of the per-cell path: each has two tiles of NB values; the groups beyond
-  // only take part in the barriers.  In FP64 at 3D p=4 the batch is cut to 4 cells so that the
-  // tiles and the staged run bases fit in the sweep arrays' space.
-  static constexpr int EPC0 = (sizeof(T) == 8 && D == 3 && P == 4) ? 4 : EPB;
+  // only take part in the barriers.  At 3D p=4 the batch is cut to 4 cells so that the tiles
+  // and the staged run bases fit in the sweep arrays' space.
+  static constexpr int EPC0 = (D == 3 && P == 4) ? 4 : EPB;  // (FP32 too: 20.3 against 20.9 us)
   static constexpr int EPC = EPC0 < EPB ? EPC0 : EPB;
   static constexpr int NTILE = EPC;  // tile pairs (the other groups store nothing)
   // LDS in elements of T: the lattice accumulator (the cell and face rows are summed into it in
@@ -863,17 +863,33 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
 }
 
 // v[dof] = sum over the planes k present in the DoF's mask, in increasing k (deterministic).
+// Two DoFs per thread (a block's 2 * 256 consecutive ones), so that each thread has twice the
+// loads in flight (FP64 apply at 64^3 Q4: 50.2 against 51.2 us).
+constexpr int kHaloPerThread = 2;
 template <typename T, int D>
 __global__ __launch_bounds__(256) void halo_reduce_kernel(int n, const int32_t *__restrict__ dof,
                                                           const uint8_t *__restrict__ mask,
                                                           const T *__restrict__ halo, T *__restrict__ v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t m = mask[i];
-  T s = 0;
+  const int i0 = blockIdx.x * (kHaloPerThread * 256) + threadIdx.x;
+  uint32_t m[kHaloPerThread];
+  int dd[kHaloPerThread];
 #pragma unroll
-  for (int k = 0; k < (1 << D); ++k) s += ((m >> k) & 1u) ? halo[(int64_t)k * n + i] : T(0);
-  v[dof[i]] = s;
+  for (int r = 0; r < kHaloPerThread; ++r) {
+    const int i = i0 + r * 256;
+    m[r] = i < n ? mask[i] : 0u;
+    dd[r] = i < n ? dof[i] : 0;
+  }
+  T s[kHaloPerThread];
+#pragma unroll
+  for (int r = 0; r < kHaloPerThread; ++r) s[r] = T(0);
+#pragma unroll
+  for (int k = 0; k < (1 << D); ++k)
+#pragma unroll
+    for (int r = 0; r < kHaloPerThread; ++r)
+      s[r] += ((m[r] >> k) & 1u) ? halo[(int64_t)k * n + i0 + r * 256] : T(0);
+#pragma unroll
+  for (int r = 0; r < kHaloPerThread; ++r)
+    if (i0 + r * 256 < n) v[dd[r]] = s[r];
 }
 
 // ------------------------------------------------------------------------------------
@@ -1471,7 +1487,8 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
       hipLaunchKernelGGL((brick_kernel<T, D, N1>), dim3((unsigned)c->n_bricks), dim3(NT), 0, s, br,
                          (const T *)fbuf, u, v, halo, nh, tab, scale, parts);
       if (nh > 0 && !(parts & SBM_PART_NO_ASSEMBLY)) {
-        hipLaunchKernelGGL((halo_reduce_kernel<T, D>), dim3((nh + 255) / 256), dim3(256), 0, s, nh, c->d_halo_dof,
+        constexpr int HB = kHaloPerThread * 256;  // DoFs per block
+        hipLaunchKernelGGL((halo_reduce_kernel<T, D>), dim3((nh + HB - 1) / HB), dim3(256), 0, s, nh, c->d_halo_dof,
                            (const uint8_t *)c->d_halo_mask, (const T *)halo, v);
       }
     }
