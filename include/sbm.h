@@ -215,11 +215,37 @@ sbm_status sbm_apply_parts(sbm_handle h, const void *u, void *v, int prec, int p
 sbm_status sbm_set_extension_order(sbm_handle h, int m);
 
 /*
- * sbm_apply_batch -- n independent applies v_i = A_i u_i, enqueued in order on one stream
- * (the kernels of each operator as sbm_apply launches them).  Same argument rules as
- * sbm_apply for every i; stops at the first failing entry and returns its status.
- * Asynchronous.
+ * Batched applies (serving: many operators' applies in few launches; the matrix-free apply
+ * of Sec. 3, Alg. 1-3, per operator).  A batch is n independent applies v_i = A_i u_i in one
+ * precision.  The operators that share a kernel instantiation (discretisation, dimension,
+ * degree) form a group, and each group runs as one launch per stage across all its operators
+ * (surrogate faces; cells or bricks; brick-boundary sums), every workgroup finding its
+ * operator in a table in device memory.  Each v_i is bitwise the result of sbm_apply(h_i,
+ * u_i, v_i).  Operators with a truncated extension (sbm_set_extension_order) have their
+ * surrogate faces computed one by one, their other stages in the group launches.
+ *
+ * Argument rules (every i): as sbm_apply, and further: a handle appears at most once (its
+ * scratch serves one apply at a time), no v_i equals another v_j or any u_j (vectors of a
+ * batch must not overlap), all handles on the current device.  Errors: EINVAL (any rule
+ * broken, NULL arrays with n > 0), EHIP.
+ *
+ * sbm_batch_create -- validate and prepare (host tables, one device allocation holding them,
+ *   uploaded before returning).  graph != 0: the first sbm_batch_run captures the batch's
+ *   launches into a HIP graph (on the stream given to it, which must not be the legacy
+ *   default stream; otherwise, or if capture fails, launches are issued directly) and every
+ *   later run replays it.  The handles and vectors must stay valid until sbm_batch_destroy;
+ *   changing a handle's extension order after creation is not seen by the batch.
+ * sbm_batch_run -- enqueue the batch on stream (asynchronous).  A batch is not to be run from
+ *   two threads at once, nor concurrently with other work on its handles.
+ * sbm_batch_destroy -- waits for the batch's last run, then releases it (NULL: no-op).
+ * sbm_apply_batch -- one-shot form: create (no graph), run on stream, release the tables once
+ *   the run has completed (without waiting for it).  n = 0: no-op.
  */
+typedef struct sbm_batch_s *sbm_batch;
+sbm_status sbm_batch_create(int n, const sbm_handle *hs, const void *const *u, void *const *v, int prec,
+                            int graph, sbm_batch *out);
+sbm_status sbm_batch_run(sbm_batch b, void *stream);
+sbm_status sbm_batch_destroy(sbm_batch b);
 sbm_status sbm_apply_batch(int n, const sbm_handle *hs, const void *const *u, void *const *v,
                            int prec, void *stream);
 

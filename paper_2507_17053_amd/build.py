@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libsbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["setup.cpp", "kernels_apply.hip", "kernels_taylor.hip", "vec.hip", "solver.hip",
-           "apply_noalloc.hip", "setup_gpu.hip"]
+           "apply_noalloc.hip", "setup_gpu.hip", "batch.cpp"]
 # per-file flags: the device setup evaluates the level sets with the same floating-point
 # operations as the host build (no multiply-add contraction), so both agree bit for bit
 EXTRA = {"setup_gpu.hip": ["-ffp-contract=off"], "setup.cpp": ["-ffp-contract=off"]}

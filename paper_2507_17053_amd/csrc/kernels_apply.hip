@@ -29,6 +29,10 @@
 //   M_ij = sum_q w_q l_i(g_q) l_j(g_q),   K_ij = sum_q w_q l'_i(g_q) l'_j(g_q)
 // (exact with p+1 Gauss points), A_K = h^(d-2) sum_k M x .. K(axis k) .. x M.  In 3D this
 // is 7 one-dimensional sweeps instead of the 12 of the gradient form.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+
 #include "sbm_internal.h"
 
 namespace sbm {
@@ -520,9 +524,9 @@ struct LaneGroup {
 };
 
 template <typename T, int D, int N1>
-__global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
-    BrickArgs br, const T *__restrict__ fbuf, const T *__restrict__ u, T *__restrict__ v, T *__restrict__ halo,
-    int nhalo, KTab<T, N1> tab, T scale, int parts) {
+__device__ __forceinline__ void brick_body(const int blk, BrickArgs br, const T *__restrict__ fbuf,
+                                           const T *__restrict__ u, T *__restrict__ v, T *__restrict__ halo,
+                                           int nhalo, KTab<T, N1> tab, T scale, int parts) {
   using C = BrickCfg<T, D, N1>;
   constexpr int P = C::P, NP = C::NP, NB = C::NB, EPB = C::EPB;
   constexpr int BX = C::BX, BY = C::BY, BZ = C::BZ, LX = C::LX, LY = C::LY, LZ = C::LZ;
@@ -531,7 +535,7 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
   __shared__ T smem[C::SMEM];
   T *const acc = smem;             // the brick lattice (both paths)
   T *const tail = smem + NL;       // per-cell tiles, or the second sweep array
-  const int brick = xcd_block();
+  const int brick = blk;
   const int tid = threadIdx.x;
   constexpr int nthr = C::NT;  // the launch uses exactly NT threads
   const int le = tid / NP, t = tid - le * NP;
@@ -862,15 +866,22 @@ __global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
   }
 }
 
+template <typename T, int D, int N1>
+__global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_kernel(
+    BrickArgs br, const T *__restrict__ fbuf, const T *__restrict__ u, T *__restrict__ v, T *__restrict__ halo,
+    int nhalo, KTab<T, N1> tab, T scale, int parts) {
+  brick_body<T, D, N1>(xcd_block(), br, fbuf, u, v, halo, nhalo, tab, scale, parts);
+}
+
 // v[dof] = sum over the planes k present in the DoF's mask, in increasing k (deterministic).
 // Two DoFs per thread (a block's 2 * 256 consecutive ones), so that each thread has twice the
 // loads in flight (FP64 apply at 64^3 Q4: 50.2 against 51.2 us).
 constexpr int kHaloPerThread = 2;
 template <typename T, int D>
-__global__ __launch_bounds__(256) void halo_reduce_kernel(int n, const int32_t *__restrict__ dof,
+__device__ __forceinline__ void halo_reduce_body(const int blk, int n, const int32_t *__restrict__ dof,
                                                           const uint8_t *__restrict__ mask,
                                                           const T *__restrict__ halo, T *__restrict__ v) {
-  const int i0 = blockIdx.x * (kHaloPerThread * 256) + threadIdx.x;
+  const int i0 = blk * (kHaloPerThread * 256) + threadIdx.x;
   uint32_t m[kHaloPerThread];
   int dd[kHaloPerThread];
 #pragma unroll
@@ -892,6 +903,13 @@ __global__ __launch_bounds__(256) void halo_reduce_kernel(int n, const int32_t *
     if (i0 + r * 256 < n) v[dd[r]] = s[r];
 }
 
+template <typename T, int D>
+__global__ __launch_bounds__(256) void halo_reduce_kernel(int n, const int32_t *__restrict__ dof,
+                                                          const uint8_t *__restrict__ mask,
+                                                          const T *__restrict__ halo, T *__restrict__ v) {
+  halo_reduce_body<T, D>(blockIdx.x, n, dof, mask, halo, v);
+}
+
 // ------------------------------------------------------------------------------------
 // CG surrogate-boundary faces (Alg. 3), EPB faces per workgroup, faces in brick order.
 // Output per face: Rv and Rg at its NP face nodes (fbuf[f][0][t], fbuf[f][1][t]);
@@ -902,8 +920,7 @@ __global__ __launch_bounds__(256) void halo_reduce_kernel(int n, const int32_t *
 // (p+1)^d values once for both points.
 // ------------------------------------------------------------------------------------
 template <typename T, int D, int N1, int EPB>
-// (at least 4 waves per SIMD: keeps the scheduler from holding the whole tile in registers)
-__global__ __launch_bounds__(256, 4) void sbm_face_cg_kernel(int n_faces, const int32_t *__restrict__ face_code,
+__device__ __forceinline__ void sbm_face_cg_body(const int blk, int n_faces, const int32_t *__restrict__ face_code,
                                                           const int32_t *__restrict__ face_runs,
                                                           const double *__restrict__ face_xi,
                                                           const T *__restrict__ u, T *__restrict__ fbuf,
@@ -912,7 +929,7 @@ __global__ __launch_bounds__(256, 4) void sbm_face_cg_kernel(int n_faces, const 
   __shared__ T su_all[EPB * NB];
   __shared__ T fw_all[6 * EPB * NP];  // per face: g, sweep, E u, integrands v / dn v, scratch
   const int tid = threadIdx.x;
-  const int f0 = xcd_block() * EPB;
+  const int f0 = blk * EPB;
   // node layout
   const int le = tid / NP, t = tid - le * NP;
   const int f = f0 + le;
@@ -1058,12 +1075,22 @@ __global__ __launch_bounds__(256, 4) void sbm_face_cg_kernel(int n_faces, const 
   }
 }
 
+// (at least 4 waves per SIMD: keeps the scheduler from holding the whole tile in registers)
+template <typename T, int D, int N1, int EPB>
+__global__ __launch_bounds__(256, 4) void sbm_face_cg_kernel(int n_faces, const int32_t *__restrict__ face_code,
+                                                          const int32_t *__restrict__ face_runs,
+                                                          const double *__restrict__ face_xi,
+                                                          const T *__restrict__ u, T *__restrict__ fbuf,
+                                                          KTab<T, N1> tab, KScal sc) {
+  sbm_face_cg_body<T, D, N1, EPB>(xcd_block(), n_faces, face_code, face_runs, face_xi, u, fbuf, tab, sc);
+}
+
 // DG surrogate-boundary faces: one entity = one face.  Output per face: Rv and Rg at its NP
 // face nodes (fbuf[f][0][t], fbuf[f][1][t]); the DG cell kernels add the face's rows into the
 // cell's block in face order, so the apply has no atomics and is bitwise reproducible.
 // ------------------------------------------------------------------------------------
 template <typename T, int D, int N1, int EPB>
-__global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_t *__restrict__ face_cell,
+__device__ __forceinline__ void sbm_face_body(const int blk, int n_faces, const int32_t *__restrict__ face_cell,
                                                        const int32_t *__restrict__ face_code,
                                                        const double *__restrict__ face_xi, const T *__restrict__ u,
                                                        T *__restrict__ fbuf, KTab<T, N1> tab, KScal sc) {
@@ -1071,7 +1098,7 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
   __shared__ T su_all[EPB * NB];
   __shared__ T f_all[4 * EPB * NP];
   const int le = threadIdx.x / NP, t = threadIdx.x - le * NP;
-  const int f = xcd_block() * EPB + le;
+  const int f = blk * EPB + le;
   const bool act = f < n_faces;
   T *su = su_all + le * NB;
   T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
@@ -1093,6 +1120,14 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
   }
 }
 
+template <typename T, int D, int N1, int EPB>
+__global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_t *__restrict__ face_cell,
+                                                       const int32_t *__restrict__ face_code,
+                                                       const double *__restrict__ face_xi, const T *__restrict__ u,
+                                                       T *__restrict__ fbuf, KTab<T, N1> tab, KScal sc) {
+  sbm_face_body<T, D, N1, EPB>(xcd_block(), n_faces, face_cell, face_code, face_xi, u, fbuf, tab, sc);
+}
+
 // DG surrogate-boundary faces in 3D with (p+1)^3 threads per face: thread (t, i2) takes face
 // point t and slab i2 of the cell.  The cell's values are loaded one per thread; E u at each
 // shifted point is split over the slabs (each thread one slab's (p+1)^2 terms) and the slab
@@ -1102,7 +1137,7 @@ __global__ __launch_bounds__(256) void sbm_face_kernel(int n_faces, const int32_
 // face_runs != nullptr (CG): the cell's values are gathered through its x-run bases
 // (face_runs[f][t] is the first DoF of run t); otherwise (DG) the cell block is contiguous.
 template <typename T, int N1, int EPB>
-__global__ __launch_bounds__(256) void sbm_face_slab_kernel(int n_faces, const int32_t *__restrict__ face_cell,
+__device__ __forceinline__ void sbm_face_slab_body(const int blk, int n_faces, const int32_t *__restrict__ face_cell,
                                                             const int32_t *__restrict__ face_code,
                                                             const double *__restrict__ face_xi,
                                                             const int32_t *__restrict__ face_runs,
@@ -1114,7 +1149,7 @@ __global__ __launch_bounds__(256) void sbm_face_slab_kernel(int n_faces, const i
   __shared__ T f_all[4 * EPB * NP];
   const int le = threadIdx.x / NB, r = threadIdx.x - le * NB;
   const int t = r % NP, i2 = r / NP;
-  const int f = xcd_block() * EPB + le;
+  const int f = blk * EPB + le;
   const bool act = f < n_faces;
   T *su = su_all + le * NB, *sp = sp_all + le * NB;
   T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
@@ -1179,6 +1214,16 @@ __global__ __launch_bounds__(256) void sbm_face_slab_kernel(int n_faces, const i
   }
 }
 
+template <typename T, int N1, int EPB>
+__global__ __launch_bounds__(256) void sbm_face_slab_kernel(int n_faces, const int32_t *__restrict__ face_cell,
+                                                            const int32_t *__restrict__ face_code,
+                                                            const double *__restrict__ face_xi,
+                                                            const int32_t *__restrict__ face_runs,
+                                                            const T *__restrict__ u, T *__restrict__ fbuf,
+                                                            KTab<T, N1> tab, KScal sc) {
+  sbm_face_slab_body<T, N1, EPB>(xcd_block(), n_faces, face_cell, face_code, face_xi, face_runs, u, fbuf, tab, sc);
+}
+
 // ------------------------------------------------------------------------------------
 // DG cell kernel: Laplace cell term + SIPG terms of the cell's interior faces, computed
 // from the cell's side only (each interior face is evaluated twice, once per cell), so
@@ -1190,7 +1235,7 @@ __global__ __launch_bounds__(256) void sbm_face_slab_kernel(int n_faces, const i
 // Face-by-face form (one group of NP threads per cell walks the 2d faces in turn), for the
 // degrees with more than 128 threads per cell in the parallel form below.
 template <typename T, int D, int N1, int EPB>
-__global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int32_t *__restrict__ nbr,
+__device__ __forceinline__ void dg_cell_seq_body(const int blk, int n_cells, const int32_t *__restrict__ nbr,
                                                       const T *__restrict__ u, const T *__restrict__ fbuf,
                                                       T *__restrict__ v, KTab<T, N1> tab, KScal sc, T scale,
                                                       int parts) {
@@ -1201,7 +1246,7 @@ __global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int
   __shared__ T sw_all[EPB * NB];
   __shared__ T f_all[4 * EPB * NP];
   const int le = threadIdx.x / NP, t = threadIdx.x - le * NP;
-  const int cell = xcd_block() * EPB + le;
+  const int cell = blk * EPB + le;
   const bool act = cell < n_cells;
   T *su = su_all + le * NB, *A = sa_all + le * NB, *B = sb_all + le * NB, *sw = sw_all + le * NB;
   T *f1 = f_all + le * NP, *f2 = f1 + EPB * NP, *f3 = f2 + EPB * NP, *f4 = f3 + EPB * NP;
@@ -1299,6 +1344,14 @@ __global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int
   }
 }
 
+template <typename T, int D, int N1, int EPB>
+__global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int32_t *__restrict__ nbr,
+                                                      const T *__restrict__ u, const T *__restrict__ fbuf,
+                                                      T *__restrict__ v, KTab<T, N1> tab, KScal sc, T scale,
+                                                      int parts) {
+  dg_cell_seq_body<T, D, N1, EPB>(xcd_block(), n_cells, nbr, u, fbuf, v, tab, sc, scale, parts);
+}
+
 // Thread layout: 2d groups of NP threads per cell, group g evaluates interior face g (code
 // 2 axis + side) with its own neighbour tile and scratch, all faces at once; then the block's
 // first EPB NP threads form the cells' terms (NP per cell; the rest only pass the barriers).
@@ -1317,7 +1370,7 @@ constexpr int dg_cells_per_block(bool one_wave) {
 }
 
 template <typename T, int D, int N1, int EPB>
-__global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t *__restrict__ nbr,
+__device__ __forceinline__ void dg_cell_body(const int blk, int n_cells, const int32_t *__restrict__ nbr,
                                                       const T *__restrict__ u, const T *__restrict__ fbuf,
                                                       T *__restrict__ v, KTab<T, N1> tab, KScal sc, T scale,
                                                       int parts) {
@@ -1329,7 +1382,7 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
   __shared__ T f_all[EPB * NF * 6 * NP];   // per face: f1..f4 scratch, Rv, Rg
   const int le = threadIdx.x / TPC, r = threadIdx.x - le * TPC;  // cell in block, thread in cell
   const int g = r / NP, t = r - g * NP;                            // face group, node / run
-  const int cell = xcd_block() * EPB + le;
+  const int cell = blk * EPB + le;
   const bool act = cell < n_cells;
   T *su = su_all + le * NB, *sw = sw_all + le * NB;
   T *An = sn_all + (le * NF + g) * NB;
@@ -1430,6 +1483,14 @@ __global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t
       v[(int64_t)cell * NB + i] = val;
     }
   }
+}
+
+template <typename T, int D, int N1, int EPB>
+__global__ __launch_bounds__(256) void dg_cell_kernel(int n_cells, const int32_t *__restrict__ nbr,
+                                                      const T *__restrict__ u, const T *__restrict__ fbuf,
+                                                      T *__restrict__ v, KTab<T, N1> tab, KScal sc, T scale,
+                                                      int parts) {
+  dg_cell_body<T, D, N1, EPB>(xcd_block(), n_cells, nbr, u, fbuf, v, tab, sc, scale, parts);
 }
 
 template <typename T, int N1>
@@ -1542,6 +1603,143 @@ hipError_t apply_impl(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t
                              nc, c->d_nbr, u, (const T *)fbuf, v, tab, sc, scale, parts);
       }
     }
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// Batched applies: the applies of several operators that share a kernel instantiation
+// (discretisation, dimension, degree, precision) run as one launch per stage over all of
+// them (surrogate faces, cells or bricks, brick-boundary sums).  Workgroup g of a stage finds
+// its item through blk_item[g] and runs the body of the single apply with that item's arrays
+// and its block index inside the item, so every item's result is bitwise the one of its own
+// apply.  The DG stages use the many-entities-per-workgroup variants (a batch fills the device).
+// ------------------------------------------------------------------------------------
+struct BatchItem {
+  BrickArgs br;  // CG bricks
+  const int32_t *face_code, *face_runs, *face_cell, *nbr, *halo_dof;
+  const uint8_t *halo_mask;
+  const double *face_xi;
+  const void *u;
+  void *v, *fbuf, *halo;
+  KScal sc;
+  int nf, nc, nh;
+  int blk0[3];  // first workgroup of the item in each stage's launch
+};
+
+template <typename T, int D, int N1>
+struct BatchShape {
+  static constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB;
+  static constexpr int EF = epb<T, D, N1, 2, 0>();  // CG faces per workgroup (as the single apply)
+  // DG faces: the slab layout in 3D where a cell fits one workgroup, else one group per face
+  static constexpr bool SLAB = D == 3 && NB <= 256;
+  static constexpr int EFD = SLAB ? 256 / NB : epb<T, D, N1, 1, 0>();
+  static constexpr int TFD = SLAB ? EFD * NB : EFD * NP;
+  // DG cells: the parallel-face form where a cell needs at most 128 threads
+  static constexpr int TPC = 2 * D * NP;
+  static constexpr bool PAR = TPC <= 128 && ((4 + 2 * D) * NB + 2 * D * 6 * NP + 2 * NB) * (int)sizeof(T) <= 60000;
+  static constexpr int EC = PAR ? dg_cells_per_block<T, D, N1>(false) : epb<T, D, N1, 4, 0>();
+  static constexpr int TC = PAR ? EC * TPC : EC * NP;
+};
+
+template <typename T, int D, int N1>
+__global__ __launch_bounds__((BrickCfg<T, D, N1>::NT)) void brick_batch_kernel(const BatchItem *__restrict__ items,
+                                                                              const int32_t *__restrict__ blk_item,
+                                                                              KTab<T, N1> tab) {
+  const int g = xcd_block();
+  const BatchItem *it = items + blk_item[g];
+  brick_body<T, D, N1>(g - it->blk0[1], it->br, (const T *)it->fbuf, (const T *)it->u, (T *)it->v, (T *)it->halo,
+                       it->nh, tab, T(D == 3 ? it->sc.h : 1.0), SBM_PART_ALL);
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void halo_reduce_batch_kernel(const BatchItem *__restrict__ items,
+                                                                const int32_t *__restrict__ blk_item) {
+  const int g = blockIdx.x;
+  const BatchItem *it = items + blk_item[g];
+  halo_reduce_body<T, D>(g - it->blk0[2], it->nh, it->halo_dof, it->halo_mask, (const T *)it->halo, (T *)it->v);
+}
+
+template <typename T, int D, int N1, int EPB>
+__global__ __launch_bounds__(256, 4) void sbm_face_cg_batch_kernel(const BatchItem *__restrict__ items,
+                                                                   const int32_t *__restrict__ blk_item,
+                                                                   KTab<T, N1> tab) {
+  const int g = xcd_block();
+  const BatchItem *it = items + blk_item[g];
+  sbm_face_cg_body<T, D, N1, EPB>(g - it->blk0[0], it->nf, it->face_code, it->face_runs, it->face_xi,
+                                  (const T *)it->u, (T *)it->fbuf, tab, it->sc);
+}
+
+template <typename T, int D, int N1>
+__global__ __launch_bounds__(256) void sbm_face_dg_batch_kernel(const BatchItem *__restrict__ items,
+                                                                const int32_t *__restrict__ blk_item,
+                                                                KTab<T, N1> tab) {
+  using S = BatchShape<T, D, N1>;
+  const int g = xcd_block();
+  const BatchItem *it = items + blk_item[g];
+  const int b = g - it->blk0[0];
+  if constexpr (S::SLAB)
+    sbm_face_slab_body<T, N1, S::EFD>(b, it->nf, it->face_cell, it->face_code, it->face_xi, (const int32_t *)nullptr,
+                                      (const T *)it->u, (T *)it->fbuf, tab, it->sc);
+  else
+    sbm_face_body<T, D, N1, S::EFD>(b, it->nf, it->face_cell, it->face_code, it->face_xi, (const T *)it->u,
+                                    (T *)it->fbuf, tab, it->sc);
+}
+
+template <typename T, int D, int N1>
+__global__ __launch_bounds__(256) void dg_cell_batch_kernel(const BatchItem *__restrict__ items,
+                                                            const int32_t *__restrict__ blk_item, KTab<T, N1> tab) {
+  using S = BatchShape<T, D, N1>;
+  const int g = xcd_block();
+  const BatchItem *it = items + blk_item[g];
+  const int b = g - it->blk0[1];
+  const T scale = T(D == 3 ? it->sc.h : 1.0);
+  if constexpr (S::PAR)
+    dg_cell_body<T, D, N1, S::EC>(b, it->nc, it->nbr, (const T *)it->u, (const T *)it->fbuf, (T *)it->v, tab, it->sc,
+                                  scale, SBM_PART_ALL);
+  else
+    dg_cell_seq_body<T, D, N1, S::EC>(b, it->nc, it->nbr, (const T *)it->u, (const T *)it->fbuf, (T *)it->v, tab,
+                                      it->sc, scale, SBM_PART_ALL);
+}
+
+// Workgroups of each stage for one item (faces: 0 when the item's surrogate faces are computed
+// elsewhere, i.e. by a truncated extension).
+template <typename T, int D, int N1>
+void batch_blocks_impl(const sbm_ctx *c, bool own_faces, int32_t nb[3]) {
+  using S = BatchShape<T, D, N1>;
+  const int64_t nf = own_faces ? c->n_sbm : 0;
+  if (c->disc == SBM_CG) {
+    nb[0] = (int32_t)((nf + S::EF - 1) / S::EF);
+    nb[1] = (int32_t)c->n_bricks;
+    nb[2] = (int32_t)((c->n_halo_dofs + kHaloPerThread * 256 - 1) / (kHaloPerThread * 256));
+  } else {
+    nb[0] = (int32_t)((nf + S::EFD - 1) / S::EFD);
+    nb[1] = (int32_t)((c->n_cells + S::EC - 1) / S::EC);
+    nb[2] = 0;
+  }
+}
+
+template <typename T, int D, int N1>
+hipError_t batch_launch_impl(const BatchGroup &g, const unsigned char *base, hipStream_t s) {
+  using S = BatchShape<T, D, N1>;
+  const KTab<T, N1> tab = make_ktab<T, N1>(g.first->rules);
+  const BatchItem *items = reinterpret_cast<const BatchItem *>(base + g.off_items);
+  const int32_t *bi[3];
+  for (int k = 0; k < 3; ++k) bi[k] = reinterpret_cast<const int32_t *>(base + g.off_blk[k]);
+  if (g.first->disc == SBM_CG) {
+    if (g.nblk[0] > 0)
+      hipLaunchKernelGGL((sbm_face_cg_batch_kernel<T, D, N1, S::EF>), dim3(g.nblk[0]), dim3(S::EF * S::NP), 0, s,
+                         items, bi[0], tab);
+    if (g.nblk[1] > 0)
+      hipLaunchKernelGGL((brick_batch_kernel<T, D, N1>), dim3(g.nblk[1]), dim3(BrickCfg<T, D, N1>::NT), 0, s, items,
+                         bi[1], tab);
+    if (g.nblk[2] > 0)
+      hipLaunchKernelGGL((halo_reduce_batch_kernel<T, D>), dim3(g.nblk[2]), dim3(256), 0, s, items, bi[2]);
+  } else {
+    if (g.nblk[0] > 0)
+      hipLaunchKernelGGL((sbm_face_dg_batch_kernel<T, D, N1>), dim3(g.nblk[0]), dim3(S::TFD), 0, s, items, bi[0], tab);
+    if (g.nblk[1] > 0)
+      hipLaunchKernelGGL((dg_cell_batch_kernel<T, D, N1>), dim3(g.nblk[1]), dim3(S::TC), 0, s, items, bi[1], tab);
   }
   return hipGetLastError();
 }
@@ -1673,6 +1871,35 @@ hipError_t diag_dim(const sbm_ctx *c, T *diag, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+#define SBM_P_SWITCH(P_, CALL)     \
+  switch (P_) {                    \
+    case 1: return CALL(2);        \
+    case 2: return CALL(3);        \
+    case 3: return CALL(4);        \
+    case 4: return CALL(5);        \
+    case 5: return CALL(6);        \
+    case 6: return CALL(7);        \
+    case 7: return CALL(8);        \
+    case 8: return CALL(9);        \
+  }
+
+template <typename T, int D>
+bool batch_blocks_dim(const sbm_ctx *c, bool own_faces, int32_t nb[3]) {
+#define SBM_BB(N1_) (batch_blocks_impl<T, D, N1_>(c, own_faces, nb), true)
+  SBM_P_SWITCH(c->p, SBM_BB)
+#undef SBM_BB
+  return false;
+}
+
+template <typename T, int D>
+hipError_t batch_launch_dim(const BatchGroup &g, const unsigned char *base, hipStream_t s) {
+#define SBM_BL(N1_) batch_launch_impl<T, D, N1_>(g, base, s)
+  SBM_P_SWITCH(g.first->p, SBM_BL)
+#undef SBM_BL
+  return hipErrorInvalidValue;
+}
+#undef SBM_P_SWITCH
+
 template <typename T, int D>
 hipError_t apply_dim(const sbm_ctx *c, const T *u, T *v, int parts, hipStream_t s, const Scratch &scr) {
   switch (c->p) {
@@ -1716,6 +1943,73 @@ size_t apply_scratch_bytes(const sbm_ctx *c, int prec) {
   const size_t halo = c->disc == SBM_CG ? ((size_t)1 << c->dim) * (size_t)c->n_halo_dofs * s : 0;
   const size_t fbuf = (size_t)c->n_sbm * 2 * (size_t)c->nq_face * s;
   return up(halo) + up(fbuf);
+}
+
+hipError_t batch_group_build(BatchGroup &g, const std::vector<const sbm_ctx *> &cs,
+                             const std::vector<const void *> &u, const std::vector<void *> &v,
+                             const std::vector<int> &own_faces, std::vector<unsigned char> &image) {
+  const sbm_ctx *c0 = cs.empty() ? nullptr : cs[0];
+  if (!c0 || u.size() != cs.size() || v.size() != cs.size() || own_faces.size() != cs.size())
+    return hipErrorInvalidValue;
+  g.first = c0;
+  g.n_items = (int)cs.size();
+  std::vector<BatchItem> items(cs.size());
+  std::vector<int32_t> blk[3];
+  int64_t tot[3] = {0, 0, 0};
+  for (size_t i = 0; i < cs.size(); ++i) {
+    const sbm_ctx *c = cs[i];
+    if (c->disc != c0->disc || c->dim != c0->dim || c->p != c0->p) return hipErrorInvalidValue;
+    int32_t nb[3] = {0, 0, 0};
+    const bool ok = g.prec == SBM_F64 ? (c->dim == 3 ? batch_blocks_dim<double, 3>(c, own_faces[i] != 0, nb)
+                                                     : batch_blocks_dim<double, 2>(c, own_faces[i] != 0, nb))
+                                      : (c->dim == 3 ? batch_blocks_dim<float, 3>(c, own_faces[i] != 0, nb)
+                                                     : batch_blocks_dim<float, 2>(c, own_faces[i] != 0, nb));
+    if (!ok) return hipErrorInvalidValue;
+    BatchItem &it = items[i];
+    it.br = BrickArgs{c->d_brick_cell_off, c->d_brick_runs, c->d_brick_cell_loc, c->d_brick_face_off,
+                      c->d_brick_face_loc, c->d_face_code,  c->d_row_base,       c->d_row_gmask,
+                      c->d_row_bmask,      c->d_row_hbase};
+    it.face_code = c->d_face_code;
+    it.face_runs = c->d_face_runs;
+    it.face_cell = c->d_face_cell;
+    it.nbr = c->d_nbr;
+    it.halo_dof = c->d_halo_dof;
+    it.halo_mask = c->d_halo_mask;
+    it.face_xi = c->d_face_xi;
+    it.u = u[i];
+    it.v = v[i];
+    it.fbuf = c->d_fbuf;
+    it.halo = c->d_halo;
+    it.sc = KScal{c->h, c->sigma_gamma, c->sigma_f};
+    it.nf = (int)c->n_sbm;
+    it.nc = (int)c->n_cells;
+    it.nh = (int)c->n_halo_dofs;
+    for (int k = 0; k < 3; ++k) {
+      it.blk0[k] = (int)tot[k];
+      blk[k].insert(blk[k].end(), (size_t)nb[k], (int32_t)i);
+      tot[k] += nb[k];
+      if (tot[k] > INT32_MAX / 2) return hipErrorInvalidValue;
+    }
+  }
+  auto put = [&image](const void *src, size_t bytes) {
+    const size_t off = (image.size() + 255) / 256 * 256;
+    image.resize(off + std::max<size_t>(bytes, 4));
+    if (bytes) std::memcpy(image.data() + off, src, bytes);
+    return off;
+  };
+  g.off_items = put(items.data(), items.size() * sizeof(BatchItem));
+  for (int k = 0; k < 3; ++k) {
+    g.nblk[k] = (int)tot[k];
+    g.off_blk[k] = put(blk[k].data(), blk[k].size() * sizeof(int32_t));
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_batch_group(const BatchGroup &g, const void *base, hipStream_t s) {
+  const unsigned char *b = static_cast<const unsigned char *>(base);
+  if (g.prec == SBM_F64)
+    return g.first->dim == 3 ? batch_launch_dim<double, 3>(g, b, s) : batch_launch_dim<double, 2>(g, b, s);
+  return g.first->dim == 3 ? batch_launch_dim<float, 3>(g, b, s) : batch_launch_dim<float, 2>(g, b, s);
 }
 
 hipError_t launch_apply(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s,

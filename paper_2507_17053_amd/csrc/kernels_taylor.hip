@@ -383,6 +383,11 @@ hipError_t launch_operator(const sbm_ctx *c, const void *u, void *v, int prec, i
   return launch_apply(c, u, v, prec, parts | SBM_PART_REUSE_FACES, s, scr);
 }
 
+hipError_t launch_taylor_faces(const sbm_ctx *c, const void *u, void *fbuf, int prec, hipStream_t s) {
+  if (c->n_sbm == 0) return hipSuccess;
+  return prec == SBM_F64 ? taylor_run<double>(c, u, fbuf, nullptr, s) : taylor_run<float>(c, u, fbuf, nullptr, s);
+}
+
 hipError_t launch_operator_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s) {
   hipError_t e = launch_diagonal(c, diag, prec, s);
   if (e != hipSuccess || c->taylor_m < 0) return e;

@@ -161,6 +161,27 @@ hipError_t launch_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s
 hipError_t launch_operator(const sbm_ctx *c, const void *u, void *v, int prec, int parts, hipStream_t s,
                            const Scratch *scr = nullptr);
 hipError_t launch_operator_diagonal(const sbm_ctx *c, void *diag, int prec, hipStream_t s);
+// Batched applies (kernels_apply.hip).  A group holds operators of one kernel instantiation
+// (discretisation, dimension, degree; prec); its applies run as one launch per stage.  The
+// group's device tables (per item: its arrays and vectors and its first workgroup in every
+// stage; per stage: the item of every workgroup) are appended to image, the host copy of the
+// plan's device memory, at 256-byte aligned offsets recorded in the group.  own_faces[i] = 0:
+// item i's surrogate-face results are computed elsewhere (truncated extension) before the group.
+struct BatchGroup {
+  const sbm_ctx *first = nullptr;
+  int prec = SBM_F64;
+  int n_items = 0;
+  int nblk[3] = {0, 0, 0};  // workgroups per stage: surrogate faces, cells or bricks, brick-boundary sums
+  size_t off_items = 0, off_blk[3] = {0, 0, 0};
+};
+hipError_t batch_group_build(BatchGroup &g, const std::vector<const sbm_ctx *> &cs,
+                             const std::vector<const void *> &u, const std::vector<void *> &v,
+                             const std::vector<int> &own_faces, std::vector<unsigned char> &image);
+// Launches a group's stages; base = device address of the plan's tables (the uploaded image).
+hipError_t launch_batch_group(const BatchGroup &g, const void *base, hipStream_t s);
+// The truncated extension's surrogate-face results (Rv, Rg per face node) of u into fbuf
+// (kernels_taylor.hip); nothing to do for an operator without surrogate faces.
+hipError_t launch_taylor_faces(const sbm_ctx *c, const void *u, void *fbuf, int prec, hipStream_t s);
 // Brick shape (cells per direction) used by the CG kernel for (dim, p).
 void brick_dims(int dim, int p, int *bx, int *by, int *bz);
 // Brick numbering from the per-slot cell and face counts of the brick grid: key_of[b] is the

@@ -1287,19 +1287,6 @@ sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double 
   return SBM_OK;
 }
 
-sbm_status sbm_apply_batch(int n, const sbm_handle *hs, const void *const *u, void *const *v, int prec,
-                           void *stream) {
-  if (n < 0 || (n > 0 && (!hs || !u || !v))) {
-    set_error("sbm_apply_batch: bad arguments");
-    return SBM_EINVAL;
-  }
-  for (int i = 0; i < n; ++i) {
-    sbm_status st = sbm_apply(hs[i], u[i], v[i], prec, stream);
-    if (st != SBM_OK) return st;
-  }
-  return SBM_OK;
-}
-
 sbm_status sbm_diagonal(sbm_handle h, void *diag, int prec, void *stream) {
   if (!h || (!diag && h->n_dofs > 0) || h->host_only || (prec != SBM_F64 && prec != SBM_F32)) {
     set_error("sbm_diagonal: invalid argument");

@@ -80,6 +80,10 @@ _lib.sbm_apply_parts.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]
 _lib.sbm_apply_noalloc.argtypes = [_P, _P, _P, ctypes.c_int, _P]
 _lib.sbm_apply_batch.argtypes = [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                  ctypes.c_int, _P]
+_lib.sbm_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                  ctypes.c_int, ctypes.c_int, ctypes.POINTER(_P)]
+_lib.sbm_batch_run.argtypes = [_P, _P]
+_lib.sbm_batch_destroy.argtypes = [_P]
 _lib.sbm_dof_points.argtypes = [_P, _P]
 _lib.sbm_rhs_points.argtypes = [_P, _P, _P]
 _lib.sbm_rhs.argtypes = [_P, _P, _P, _P, _P]
@@ -98,7 +102,7 @@ PART_CELLS, PART_SBM_FACES, PART_ALL, PART_NO_ASSEMBLY, PART_REUSE_FACES = 2, 4,
 _lib.sbm_layout_stats.argtypes = [_P, _I64P, _I64P, _I64P]
 EXPORTED = ["sbm_setup", "sbm_info", "sbm_destroy", "sbm_last_error", "sbm_apply", "sbm_apply_noalloc",
             "sbm_apply_parts",
-            "sbm_apply_batch", "sbm_layout_stats",
+            "sbm_apply_batch", "sbm_batch_create", "sbm_batch_run", "sbm_batch_destroy", "sbm_layout_stats",
             "sbm_dof_points", "sbm_rhs_points", "sbm_rhs", "sbm_l2_error", "sbm_solve", "sbm_diagonal",
             "sbm_footprint_estimate", "sbm_export_cells", "sbm_export_sbm_faces", "sbm_export_face_xi",
             "sbm_export_cell_dofs"]
@@ -359,14 +363,63 @@ class Operator:
         return out
 
 
-def apply_batch(ops, us, vs, stream=None):
+def _batch_args(ops, us, vs):
     import torch
     n = len(ops)
-    hs = (_P * n)(*[o.handle for o in ops])
-    up = (_P * n)(*[u.data_ptr() for u in us])
-    vp = (_P * n)(*[v.data_ptr() for v in vs])
-    prec = SBM_F64 if us[0].dtype == torch.float64 else SBM_F32
+    if len(us) != n or len(vs) != n:
+        raise ValueError("one input and one output per operator")
+    dt = us[0].dtype if n else torch.float64
+    for o, u, v in zip(ops, us, vs):
+        if u.dtype != dt or v.dtype != dt or u.numel() != o.n_dofs or v.numel() != o.n_dofs:
+            raise ValueError("vectors must have the operators' sizes and one dtype")
+    hs = (_P * max(n, 1))(*[o.handle for o in ops])
+    up = (_P * max(n, 1))(*[u.data_ptr() for u in us])
+    vp = (_P * max(n, 1))(*[v.data_ptr() for v in vs])
+    return n, hs, up, vp, (SBM_F64 if dt == torch.float64 else SBM_F32)
+
+
+def apply_batch(ops, us, vs, stream=None):
+    """v_i = A_i u_i for every i, the operators of one kernel instantiation in shared launches
+    (sbm_apply_batch; asynchronous)."""
+    n, hs, up, vp, prec = _batch_args(ops, us, vs)
     _check(_lib.sbm_apply_batch(n, hs, up, vp, prec, _stream_ptr(stream)), "sbm_apply_batch")
+
+
+class Batch:
+    """A fixed batch of applies v_i = A_i u_i prepared once and run many times (sbm_batch_*):
+    operators of one kernel instantiation share one launch per stage; with graph=True the first
+    run (on a non-default stream) captures the batch into a HIP graph that later runs replay.
+    The operators and vectors must outlive the batch."""
+
+    def __init__(self, ops, us, vs, graph=True):
+        n, hs, up, vp, prec = _batch_args(ops, us, vs)
+        self._keep = (list(ops), list(us), list(vs))
+        h = _P()
+        _check(_lib.sbm_batch_create(n, hs, up, vp, prec, 1 if graph else 0, ctypes.byref(h)), "sbm_batch_create")
+        self._b = h
+
+    def run(self, stream=None):
+        if self._b is None:
+            raise SbmError(SBM_EINVAL, "batch is closed")
+        _check(_lib.sbm_batch_run(self._b, _stream_ptr(stream)), "sbm_batch_run")
+
+    def close(self):
+        if self._b is not None:
+            b, self._b = self._b, None
+            _check(_lib.sbm_batch_destroy(b), "sbm_batch_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+        return False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def status_name(code):

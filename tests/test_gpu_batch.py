@@ -1,0 +1,135 @@
+"""Batched applies across operators (sbm_apply_batch, sbm_batch_create / run / destroy).
+
+Operators that share a kernel instantiation run in one launch per stage; every result must be
+bitwise the operator's own sbm_apply (the single apply is held to the FP64 oracle by the apply
+parity tests).  The mix covers CG and DG, 2D and 3D, several degrees, groups with several
+operators of different mesh sizes, the two DG cell-kernel forms (parallel faces at p <= 3,
+face by face above), the 2D and 3D DG face kernels, a truncated extension inside a group and a
+high-degree brick."""
+
+import pytest
+
+from paper_2507_17053_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+sbm = pytest.importorskip("paper_2507_17053_amd.sbm")
+
+MIX = [
+    dict(d=3, n=10, ls=inputs.sphere((0, 0, 0), 0.75), p=4, disc="cg"),
+    dict(d=3, n=12, ls=inputs.ellipsoid((0.0, 0.02, -0.01), (0.8, 0.6, 0.7)), p=4, disc="cg"),
+    dict(d=3, n=8, ls=inputs.torus(0.55, 0.4), p=4, disc="cg", taylor=1),
+    dict(d=2, n=16, ls=inputs.sphere((0.05, -0.03), 0.7), p=2, disc="cg"),
+    dict(d=2, n=20, ls=inputs.ellipsoid((0.02, 0.01), (0.8, 0.45)), p=2, disc="cg"),
+    dict(d=3, n=6, ls=inputs.sphere((0, 0, 0), 0.75), p=2, disc="dg"),
+    dict(d=3, n=8, ls=inputs.torus(0.55, 0.4), p=2, disc="dg"),
+    dict(d=3, n=6, ls=inputs.sphere((0, 0, 0), 0.75), p=3, disc="dg"),
+    dict(d=3, n=5, ls=inputs.sphere((0, 0, 0), 0.75), p=5, disc="dg"),
+    dict(d=2, n=9, ls=inputs.sphere((0.05, -0.03), 0.7), p=3, disc="dg"),
+    dict(d=3, n=5, ls=inputs.sphere((0, 0, 0), 0.75), p=7, disc="cg"),
+]
+
+
+def _ops(cases):
+    ops = []
+    for c in cases:
+        ops.append(sbm.Operator(c["d"], c["n"], -1.0, 1.0, c["ls"], c["p"], disc=c["disc"],
+                                taylor_order=c.get("taylor")))
+    return ops
+
+
+def _vectors(ops, dtype, seed0):
+    us = [torch.from_numpy(inputs.uniform_vector(o.n_dofs, seed=seed0 + i)).to("cuda", dtype)
+          for i, o in enumerate(ops)]
+    vs = [torch.full_like(u, 7.0) for u in us]
+    return us, vs
+
+
+def _singles(ops, us):
+    refs = []
+    for o, u in zip(ops, us):
+        r = torch.empty_like(u)
+        o.apply(u, r)
+        refs.append(r)
+    torch.cuda.synchronize()
+    return refs
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_batch_mix_is_bitwise_single_applies(dtype):
+    print(f"batch mix {dtype}", flush=True)
+    ops = _ops(MIX)
+    try:
+        us, vs = _vectors(ops, dtype, 100)
+        refs = _singles(ops, us)
+        sbm.apply_batch(ops, us, vs)
+        torch.cuda.synchronize()
+        for c, v, r in zip(MIX, vs, refs):
+            assert torch.equal(v, r), c
+        # the caller's order does not matter: reversed, and a second one-shot batch right after
+        vs2 = [torch.full_like(u, -3.0) for u in us]
+        sbm.apply_batch(ops[::-1], us[::-1], vs2[::-1])
+        sbm.apply_batch(ops[:3], us[:3], vs[:3])
+        torch.cuda.synchronize()
+        for c, v, v2, r in zip(MIX, vs, vs2, refs):
+            assert torch.equal(v2, r), c
+            assert torch.equal(v, r), c
+    finally:
+        for o in ops:
+            o.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_batch_plan_graph_replays(dtype):
+    """A prepared batch captured into a graph on a side stream: three replays with new inputs
+    written into the same vectors between them (and eager applies in between), each replay
+    equal bit for bit to the single applies of that input."""
+    print(f"batch plan {dtype}", flush=True)
+    ops = _ops(MIX)
+    s = torch.cuda.Stream()
+    try:
+        us, vs = _vectors(ops, dtype, 200)
+        with sbm.Batch(ops, us, vs, graph=True) as b:
+            for rep in range(3):
+                for i, u in enumerate(us):
+                    u.copy_(torch.from_numpy(inputs.uniform_vector(u.numel(), seed=300 + 17 * rep + i)).to(dtype))
+                torch.cuda.synchronize()
+                b.run(s)
+                s.synchronize()
+                refs = _singles(ops, us)
+                for c, v, r in zip(MIX, vs, refs):
+                    assert torch.equal(v, r), (rep, c)
+                for v in vs:
+                    v.fill_(5.0)  # eager work between replays; the next replay rewrites every entry
+                torch.cuda.synchronize()
+    finally:
+        for o in ops:
+            o.close()
+
+
+def test_batch_rejects_overlapping_arguments():
+    ops = _ops(MIX[:1] + MIX[:1] + MIX[5:6])  # the first two alike (same sizes)
+    try:
+        us, vs = _vectors(ops, torch.float64, 400)
+        with pytest.raises(sbm.SbmError):
+            sbm.apply_batch([ops[0], ops[0]], [us[0], us[1]], [vs[0], vs[1]])  # one handle twice
+        with pytest.raises(sbm.SbmError):
+            sbm.Batch([ops[0], ops[1]], [us[0], vs[0]], [vs[0], vs[1]])  # an input is another's output
+        with pytest.raises(sbm.SbmError):
+            sbm.apply_batch([ops[0], ops[1]], [us[0], us[1]], [vs[0], vs[0]])  # one output twice
+        with pytest.raises(ValueError):
+            sbm.apply_batch(ops, us, vs[:2])
+        with pytest.raises(ValueError):
+            sbm.apply_batch(ops[1:], [us[2], us[1]], vs[1:])  # sizes do not match the operators
+        sbm.apply_batch([], [], [])  # empty batch: no-op
+        b = sbm.Batch(ops, us, vs, graph=False)
+        b.run()
+        b.close()
+        b.close()
+        with pytest.raises(sbm.SbmError):
+            b.run()
+        torch.cuda.synchronize()
+    finally:
+        for o in ops:
+            o.close()
