@@ -293,6 +293,63 @@ def solve_section(torch, sbm, inputs):
     return out
 
 
+def batch_section(torch, sbm, inputs, reps=20):
+    """Applies of many operators at once (serving's launches): the operators of request streams
+    (p in 2..6, ellipsoid or 8-ball union, CG or SIPG) applied one by one (eager, and captured
+    into a graph) against the batched launches (one launch per stage per group of operators
+    with the same discretisation and degree: the one-shot call on one stream, and prepared
+    batches with the groups on one stream or forked over four, replayed from their graphs or
+    launched directly).  FP64; times per pass over all operators, from events on the stream."""
+    out = {}
+    mixes = [("serving_stream_first_32", inputs.serving_requests(32, seed=2)),
+             ("small_64_n16_24", inputs.serving_requests(64, seed=5, n_range=(16, 24)))]
+    side = torch.cuda.Stream()
+    for name, reqs in mixes:
+        ops = [sbm.Operator(r["d"], r["n"], r["lo"], r["hi"], r["levelset"], r["p"], disc=r["disc"]) for r in reqs]
+        us = [torch.from_numpy(inputs.uniform_vector(o.n_dofs, seed=i)).to("cuda") for i, o in enumerate(ops)]
+        vs = [torch.empty_like(u) for u in us]
+        ndofs = sum(o.n_dofs for o in ops)
+        groups = len({(o.disc, o.p) for o in ops})
+
+        def loop():
+            for o, u, v in zip(ops, us, vs):
+                o.apply(u, v)
+
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                loop()
+                sbm.apply_batch(ops, us, vs)
+            plan = sbm.Batch(ops, us, vs, graph=True, streams=4)
+            plan1 = sbm.Batch(ops, us, vs, graph=True, streams=1)
+            plan_e = sbm.Batch(ops, us, vs, graph=False, streams=4)
+            for pl in (plan, plan1, plan_e):
+                pl.run()
+            torch.cuda.synchronize()
+            t_loop, w_loop, _ = time_launches(torch, loop, reps, 0)
+            t_loop_g, _, _ = time_launches(torch, loop, reps, 2)
+            t_once, w_once, _ = time_launches(torch, lambda: sbm.apply_batch(ops, us, vs), reps, 0)
+            t_plan, w_plan, _ = time_launches(torch, plan.run, reps, 0)
+            t_plan1, _, _ = time_launches(torch, plan1.run, reps, 0)
+            t_plan_e, _, _ = time_launches(torch, plan_e.run, reps, 0)
+            for pl in (plan, plan1, plan_e):
+                pl.close()
+        out[name] = {"operators": len(ops), "groups": groups, "total_dofs": int(ndofs),
+                     "loop_eager_ms": t_loop * 1e3, "loop_eager_wall_ms": w_loop * 1e3,
+                     "loop_graph_ms": t_loop_g * 1e3, "apply_batch_ms": t_once * 1e3,
+                     "apply_batch_wall_ms": w_once * 1e3, "batch_graph_ms": t_plan * 1e3,
+                     "batch_graph_wall_ms": w_plan * 1e3, "batch_graph_one_stream_ms": t_plan1 * 1e3,
+                     "batch_eager_4_streams_ms": t_plan_e * 1e3,
+                     "batch_graph_dofs_per_s": ndofs / t_plan, "loop_graph_dofs_per_s": ndofs / t_loop_g,
+                     "speedup_batch_graph_vs_loop_graph": t_loop_g / t_plan,
+                     "speedup_batch_graph_vs_loop_eager": t_loop / t_plan}
+        print(f"# batched applies {name}: {out[name]}", file=sys.stderr, flush=True)
+        for o in ops:
+            o.close()
+        del us, vs
+        torch.cuda.empty_cache()
+    return out
+
+
 def serve_section(n_req, max_it, rate, slots, budget_gb, deadline_s):
     """Request stream (p in 2..6, 16^3..64^3 cells, ellipsoid or 8-ball union, CG or SIPG,
     FP32 GMRES inside FP64 refinement to 1e-10 with an iteration cap).  First closed loop (all
@@ -378,6 +435,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' applies")
     ap.add_argument("--no-solve", action="store_true", help="skip the FP64 vs FP32+refinement solves")
     ap.add_argument("--no-taylor", action="store_true", help="skip the truncated-Taylor extension section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-applies section")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched-applies section")
     ap.add_argument("--profile-run", action="store_true", help="few eager applies + copies (counter runs)")
     ap.add_argument("--profile-order", type=int, default=None,
                     help="with --profile-run: extension order of the operator (default: full extension)")
@@ -412,6 +471,9 @@ def main():
 
     if args.profile_run:
         profile_run(torch, sbm, inputs, order=args.profile_order, prec=args.profile_prec, workload=args.workload)
+        return
+    if args.batch_only:
+        print(json.dumps({"batched_apply": batch_section(torch, sbm, inputs)}), flush=True)
         return
 
     w = inputs.workload(args.workload)
@@ -506,6 +568,8 @@ def main():
                                                  min(args.steps, 200), gb)
     if not args.no_configs:
         out["other_configs"] = configs_section(torch, sbm, inputs, min(args.steps, 200), gb)
+    if not args.no_batch:
+        out["batched_apply"] = batch_section(torch, sbm, inputs)
     if not args.no_solve:
         out["solve"] = solve_section(torch, sbm, inputs)
     if args.serve > 0:

@@ -134,9 +134,11 @@ sbm_status sbm_info(sbm_handle h, int64_t *n_dofs, int64_t *n_cells, int64_t *n_
                     int64_t *n_interior_faces, size_t *device_bytes);
 
 /* Releases every resource of h (NULL is ignored).  Waits for the handle's last asynchronous
- * work (apply, diagonal) to finish, then returns its device memory to the library's pool
- * stream-ordered: nothing else on the device is waited for, so other handles' work in flight
- * continues.  Work on h enqueued on a stream after that last call must not exist. */
+ * work (apply, diagonal) to finish, and for the last run of every batch of applies
+ * (sbm_apply_batch, sbm_batch_run) still pending or not destroyed, then returns its device
+ * memory to the library's pool stream-ordered: nothing else on the device is waited for, so
+ * other handles' work in flight continues.  Work on h enqueued on a stream after that last
+ * call must not exist; a prepared batch that includes h must be destroyed first. */
 void sbm_destroy(sbm_handle h);
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -230,20 +232,24 @@ sbm_status sbm_set_extension_order(sbm_handle h, int m);
  * broken, NULL arrays with n > 0), EHIP.
  *
  * sbm_batch_create -- validate and prepare (host tables, one device allocation holding them,
- *   uploaded before returning).  graph != 0: the first sbm_batch_run captures the batch's
- *   launches into a HIP graph (on the stream given to it, which must not be the legacy
- *   default stream; otherwise, or if capture fails, launches are issued directly) and every
- *   later run replays it.  The handles and vectors must stay valid until sbm_batch_destroy;
- *   changing a handle's extension order after creation is not seen by the batch.
+ *   uploaded before returning).  max_streams > 1: the groups' launch chains (independent of
+ *   each other) are spread over up to max_streams streams owned by the batch (default
+ *   priority), forked from the run's stream and joined back to it, so that the launches of
+ *   small groups overlap on the device; 1 (or 0): every launch on the run's stream.
+ *   graph != 0: the first sbm_batch_run captures the batch's launches (fork and join included)
+ *   into a HIP graph (on the stream given to it, which must not be the legacy default stream;
+ *   otherwise, or if capture fails, launches are issued directly) and every later run replays
+ *   it.  The handles and vectors must stay valid until sbm_batch_destroy; changing a handle's
+ *   extension order after creation is not seen by the batch.
  * sbm_batch_run -- enqueue the batch on stream (asynchronous).  A batch is not to be run from
  *   two threads at once, nor concurrently with other work on its handles.
  * sbm_batch_destroy -- waits for the batch's last run, then releases it (NULL: no-op).
- * sbm_apply_batch -- one-shot form: create (no graph), run on stream, release the tables once
- *   the run has completed (without waiting for it).  n = 0: no-op.
+ * sbm_apply_batch -- one-shot form: create (no graph, every launch on stream), run, release
+ *   the tables once the run has completed (without waiting for it).  n = 0: no-op.
  */
 typedef struct sbm_batch_s *sbm_batch;
 sbm_status sbm_batch_create(int n, const sbm_handle *hs, const void *const *u, void *const *v, int prec,
-                            int graph, sbm_batch *out);
+                            int graph, int max_streams, sbm_batch *out);
 sbm_status sbm_batch_run(sbm_batch b, void *stream);
 sbm_status sbm_batch_destroy(sbm_batch b);
 sbm_status sbm_apply_batch(int n, const sbm_handle *hs, const void *const *u, void *const *v,

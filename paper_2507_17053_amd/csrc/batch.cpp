@@ -23,15 +23,23 @@ struct sbm_batch_s {
   std::vector<void *> v;
   std::vector<int> taylor;           // indices (into hs) whose surrogate faces launch one by one
   std::vector<BatchGroup> groups;
+  std::vector<double> work;          // per group: DoFs (the balance estimate)
   void *d_tables = nullptr;
   bool use_graph = false, graph_off = false;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;         // completion of the last run
+  // groups spread over the batch's own streams (forked from and joined to the run's stream)
+  std::vector<hipStream_t> streams;
+  std::vector<std::vector<int>> lanes;  // per stream: its groups
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
 };
 
 namespace {
 
-// Tables of one-shot batches (sbm_apply_batch), released once their run has completed.
+// Tables of one-shot batches (sbm_apply_batch), released once their run has completed, and the
+// prepared batches alive: sbm_destroy waits for the runs of both (a batch records one event per
+// run instead of one per handle, which would cost a host call per operator).
 std::mutex g_deferred_mu;
 struct Deferred {
   int device;
@@ -39,6 +47,7 @@ struct Deferred {
   void *mem;
 };
 std::vector<Deferred> g_deferred;
+std::set<sbm_batch> g_live;
 
 void reap_deferred() {
   int dev = 0;
@@ -59,13 +68,16 @@ void reap_deferred() {
 
 void release(sbm_batch b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
+  for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->d_tables) dev_free(b->d_tables);
   if (b->done) (void)hipEventDestroy(b->done);
   delete b;
 }
 
 sbm_status build(int n, const sbm_handle *hs, const void *const *u, void *const *v, int prec, int graph,
-                 sbm_batch *out) {
+                 int max_streams, sbm_batch *out) {
   if (n < 0 || !out || (n > 0 && (!hs || !u || !v)) || (prec != SBM_F64 && prec != SBM_F32)) {
     set_error("sbm_batch_create: invalid argument");
     return SBM_EINVAL;
@@ -145,6 +157,9 @@ sbm_status build(int n, const sbm_handle *hs, const void *const *u, void *const 
       return SBM_EINVAL;
     }
     b->groups.push_back(g);
+    double w = 0.0;
+    for (const sbm_ctx *c : cs) w += (double)c->n_dofs;
+    b->work.push_back(w);
   }
   if (!image.empty()) {
     hipError_t e = dev_alloc(&b->d_tables, image.size());
@@ -163,22 +178,69 @@ sbm_status build(int n, const sbm_handle *hs, const void *const *u, void *const 
     set_error("sbm_batch_create: event");
     return SBM_EHIP;
   }
+  // the groups' launch chains are independent: with more than one group, spread them over up
+  // to max_streams streams of the batch (largest first, each to the least loaded stream)
+  const int k = std::min<int>(std::max(1, max_streams), (int)b->groups.size());
+  if (k > 1) {
+    std::vector<int> order(b->groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->work[x] > b->work[y]; });
+    std::vector<double> load(k, 0.0);
+    b->lanes.assign(k, {});
+    for (int gi : order) {
+      const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      b->lanes[j].push_back(gi);
+      load[j] += b->work[gi];
+    }
+    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    if (!ok) b->fork = nullptr;
+    for (int j = 0; ok && j < k; ++j) {
+      hipStream_t st = nullptr;
+      hipEvent_t e = nullptr;
+      ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+      if (ok) b->streams.push_back(st);
+      ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+      if (ok) b->join.push_back(e);
+    }
+    if (!ok) {
+      release(b);
+      set_error("sbm_batch_create: streams");
+      return SBM_EHIP;
+    }
+  }
   *out = b;
   return SBM_OK;
 }
 
-// Every launch of the batch, in order: the truncated-extension faces, then each group's stages.
-hipError_t enqueue(sbm_batch b, hipStream_t s) {
+// One group's launches: its truncated-extension faces, then its stages.
+hipError_t enqueue_group(sbm_batch b, int gi, hipStream_t s) {
+  const BatchGroup &g = b->groups[gi];
   for (int k : b->taylor) {
     const sbm_ctx *c = b->hs[k];
+    if (c->disc != g.first->disc || c->dim != g.first->dim || c->p != g.first->p) continue;
     hipError_t e = launch_taylor_faces(c, b->u[k], c->d_fbuf, b->prec, s);
     if (e != hipSuccess) return e;
   }
-  for (const BatchGroup &g : b->groups) {
-    hipError_t e = launch_batch_group(g, b->d_tables, s);
-    if (e != hipSuccess) return e;
+  return launch_batch_group(g, b->d_tables, s);
+}
+
+// Every launch of the batch: on s, or forked over the batch's streams and joined back to s.
+hipError_t enqueue(sbm_batch b, hipStream_t s) {
+  if (b->streams.empty()) {
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      hipError_t e = enqueue_group(b, (int)gi, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
-  return hipSuccess;
+  hipError_t e = hipEventRecord(b->fork, s);
+  for (size_t j = 0; e == hipSuccess && j < b->streams.size(); ++j) {
+    e = hipStreamWaitEvent(b->streams[j], b->fork, 0);
+    for (size_t q = 0; e == hipSuccess && q < b->lanes[j].size(); ++q) e = enqueue_group(b, b->lanes[j][q], b->streams[j]);
+    if (e == hipSuccess) e = hipEventRecord(b->join[j], b->streams[j]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[j], 0);
+  }
+  return e;
 }
 
 sbm_status run(sbm_batch b, hipStream_t s) {
@@ -209,18 +271,31 @@ sbm_status run(sbm_batch b, hipStream_t s) {
     SBM_HIP_CHECK(enqueue(b, s));
   }
   SBM_HIP_CHECK(hipEventRecord(b->done, s));
-  for (sbm_ctx *c : b->hs) note_work(c, s);
   return SBM_OK;
 }
 
 }  // namespace
 
+namespace sbm {
+void wait_batches() {
+  std::lock_guard<std::mutex> lk(g_deferred_mu);
+  for (const Deferred &d : g_deferred) (void)hipEventSynchronize(d.done);
+  for (sbm_batch b : g_live)
+    if (b->done) (void)hipEventSynchronize(b->done);
+}
+}  // namespace sbm
+
 extern "C" {
 
 sbm_status sbm_batch_create(int n, const sbm_handle *hs, const void *const *u, void *const *v, int prec, int graph,
-                            sbm_batch *out) {
+                            int max_streams, sbm_batch *out) {
   reap_deferred();
-  return build(n, hs, u, v, prec, graph, out);
+  const sbm_status st = build(n, hs, u, v, prec, graph, max_streams, out);
+  if (st == SBM_OK) {
+    std::lock_guard<std::mutex> lk(g_deferred_mu);
+    g_live.insert(*out);
+  }
+  return st;
 }
 
 sbm_status sbm_batch_run(sbm_batch b, void *stream) {
@@ -233,6 +308,10 @@ sbm_status sbm_batch_run(sbm_batch b, void *stream) {
 
 sbm_status sbm_batch_destroy(sbm_batch b) {
   if (!b) return SBM_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_deferred_mu);
+    g_live.erase(b);
+  }
   const hipError_t e = b->done ? hipEventSynchronize(b->done) : hipSuccess;
   release(b);
   if (e != hipSuccess) {
@@ -247,7 +326,7 @@ sbm_status sbm_apply_batch(int n, const sbm_handle *hs, const void *const *u, vo
   if (n == 0) return SBM_OK;
   reap_deferred();
   sbm_batch b = nullptr;
-  sbm_status st = build(n, hs, u, v, prec, 0, &b);
+  sbm_status st = build(n, hs, u, v, prec, 0, 1, &b);
   if (st != SBM_OK) return st;
   st = run(b, (hipStream_t)stream);
   if (st != SBM_OK) {

@@ -205,6 +205,9 @@ void dev_free(void *p);
 // Record the completion of the work just enqueued on stream for handle c (skipped while the
 // stream is being captured into a graph).
 void note_work(sbm_ctx *c, hipStream_t stream);
+// Wait for the last run of every batch of applies still pending or alive (batch.cpp; batches
+// record their completion once per run, not per handle).
+void wait_batches();
 // Device bytes of the handle's solver workspace (0 before the first solve).
 size_t workspace_bytes(const sbm_ctx *c);
 // Vector kernels (vec.hip)

@@ -1015,6 +1015,7 @@ void sbm_destroy(sbm_handle h) {
     (void)hipEventDestroy(h->last_work);
     h->last_work = nullptr;
   }
+  sbm::wait_batches();  // batches that include h record their completion, not h's
   sbm::free_workspace(h);
   free_device(h);
   delete h;

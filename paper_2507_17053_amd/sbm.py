@@ -81,7 +81,7 @@ _lib.sbm_apply_noalloc.argtypes = [_P, _P, _P, ctypes.c_int, _P]
 _lib.sbm_apply_batch.argtypes = [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                  ctypes.c_int, _P]
 _lib.sbm_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
-                                  ctypes.c_int, ctypes.c_int, ctypes.POINTER(_P)]
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_P)]
 _lib.sbm_batch_run.argtypes = [_P, _P]
 _lib.sbm_batch_destroy.argtypes = [_P]
 _lib.sbm_dof_points.argtypes = [_P, _P]
@@ -388,14 +388,16 @@ def apply_batch(ops, us, vs, stream=None):
 class Batch:
     """A fixed batch of applies v_i = A_i u_i prepared once and run many times (sbm_batch_*):
     operators of one kernel instantiation share one launch per stage; with graph=True the first
-    run (on a non-default stream) captures the batch into a HIP graph that later runs replay.
-    The operators and vectors must outlive the batch."""
+    run (on a non-default stream) captures the batch into a HIP graph that later runs replay;
+    streams > 1 spreads the groups over that many streams of the batch.  The operators and
+    vectors must outlive the batch."""
 
-    def __init__(self, ops, us, vs, graph=True):
+    def __init__(self, ops, us, vs, graph=True, streams=4):
         n, hs, up, vp, prec = _batch_args(ops, us, vs)
         self._keep = (list(ops), list(us), list(vs))
         h = _P()
-        _check(_lib.sbm_batch_create(n, hs, up, vp, prec, 1 if graph else 0, ctypes.byref(h)), "sbm_batch_create")
+        _check(_lib.sbm_batch_create(n, hs, up, vp, prec, 1 if graph else 0, int(streams), ctypes.byref(h)),
+               "sbm_batch_create")
         self._b = h
 
     def run(self, stream=None):

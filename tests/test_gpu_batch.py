@@ -80,17 +80,20 @@ def test_batch_mix_is_bitwise_single_applies(dtype):
             o.close()
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_batch_plan_graph_replays(dtype):
-    """A prepared batch captured into a graph on a side stream: three replays with new inputs
-    written into the same vectors between them (and eager applies in between), each replay
-    equal bit for bit to the single applies of that input."""
-    print(f"batch plan {dtype}", flush=True)
+@pytest.mark.parametrize("dtype,graph,streams", [(torch.float64, True, 4), (torch.float32, True, 4),
+                                                  (torch.float64, False, 4), (torch.float64, True, 1)],
+                         ids=["f64-graph-4streams", "f32-graph-4streams", "f64-eager-4streams", "f64-graph-1stream"])
+def test_batch_plan_replays(dtype, graph, streams):
+    """A prepared batch (groups forked over the batch's streams, or all on the run's stream;
+    captured into a graph on a side stream, or launched directly): three runs with new inputs
+    written into the same vectors between them (and eager work in between), each run equal bit
+    for bit to the single applies of that input."""
+    print(f"batch plan {dtype} graph={graph} streams={streams}", flush=True)
     ops = _ops(MIX)
     s = torch.cuda.Stream()
     try:
         us, vs = _vectors(ops, dtype, 200)
-        with sbm.Batch(ops, us, vs, graph=True) as b:
+        with sbm.Batch(ops, us, vs, graph=graph, streams=streams) as b:
             for rep in range(3):
                 for i, u in enumerate(us):
                     u.copy_(torch.from_numpy(inputs.uniform_vector(u.numel(), seed=300 + 17 * rep + i)).to(dtype))
