@@ -342,9 +342,35 @@ def batch_section(torch, sbm, inputs, reps=20):
                      "batch_graph_dofs_per_s": ndofs / t_plan, "loop_graph_dofs_per_s": ndofs / t_loop_g,
                      "speedup_batch_graph_vs_loop_graph": t_loop_g / t_plan,
                      "speedup_batch_graph_vs_loop_eager": t_loop / t_plan}
+        # the solve phase of serving: the same systems solved one after another (sbm_solve)
+        # against one lockstep batch (sbm_solve_batch), FP32 GMRES(32) inside FP64 refinement
+        # with the serving iteration cap; the results are identical, so are the iteration counts
+        bs = [torch.from_numpy(inputs.uniform_vector(o.n_dofs, seed=700 + i)).to("cuda") for i, o in enumerate(ops)]
+        xs = [torch.zeros_like(b) for b in bs]
+        for o, b, x in zip(ops, bs, xs):  # workspaces allocated outside the timing
+            o.solve(b, x, rel_tol=1e-10, max_it=4, mode="gmres_ir", restart=32)
+        torch.cuda.synchronize()
+        for x in xs:
+            x.zero_()
+        t0 = time.perf_counter()
+        single = [o.solve(b, x, rel_tol=1e-10, max_it=100, mode="gmres_ir", restart=32) for o, b, x in zip(ops, bs, xs)]
+        torch.cuda.synchronize()
+        t_single = time.perf_counter() - t0
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = sbm.solve_batch(ops, bs, xs, rel_tol=1e-10, max_it=100, mode="gmres_ir", restart=32)
+        t_batch = time.perf_counter() - t0
+        out[name]["solves"] = {
+            "mode": "gmres_ir", "restart": 32, "max_it": 100,
+            "one_by_one_s": t_single, "lockstep_batch_s": t_batch, "speedup": t_single / t_batch,
+            "same_iterations": all(a["inner_its"] == b["inner_its"] for a, b in zip(single, infos)),
+            "krylov_its_total": int(sum(i["inner_its"] for i in infos))}
         print(f"# batched applies {name}: {out[name]}", file=sys.stderr, flush=True)
         for o in ops:
             o.close()
+        del bs, xs
         del us, vs
         torch.cuda.empty_cache()
     return out
@@ -355,15 +381,20 @@ def serve_section(n_req, max_it, rate, slots, budget_gb, deadline_s):
     FP32 GMRES inside FP64 refinement to 1e-10 with an iteration cap).  First closed loop (all
     requests queued at t = 0) for the capacity mu in solves/s, then open loop with Poisson
     arrivals at 0.7 mu (rate > 0 overrides the open-loop rate); then the same requests in closed
-    loop with the first-order extension E_1 and a 10x iteration cap.  Each run admits requests
-    for at most deadline_s seconds (the prefix served is reported)."""
+    loop with the first-order extension E_1 and a 10x iteration cap; then closed loop again in
+    lockstep batches (every admitted request of a set solved together by sbm_solve_batch, the
+    applies of each Krylov step batched).  Each run admits requests for at most deadline_s
+    seconds (the prefix served is reported)."""
     from paper_2507_17053_amd import inputs
-    from paper_2507_17053_amd.serving import Server
+    from paper_2507_17053_amd.serving import Server, run_batched
 
-    def one(reqs, time_scale, cap=max_it):
-        srv = Server(budget_bytes=int(budget_gb * (1 << 30)), slots=slots, mode="gmres_ir", rel_tol=1e-10,
-                     max_it=cap, restart=32)
-        s = srv.run(reqs, time_scale=time_scale, deadline_s=deadline_s)
+    def one(reqs, time_scale, cap=max_it, batched_slots=0):
+        srv = Server(budget_bytes=int(budget_gb * (1 << 30)), slots=batched_slots or slots, mode="gmres_ir",
+                     rel_tol=1e-10, max_it=cap, restart=32)
+        if batched_slots:
+            s = run_batched(srv, reqs, time_scale=time_scale, deadline_s=deadline_s)
+        else:
+            s = srv.run(reqs, time_scale=time_scale, deadline_s=deadline_s)
         res = list(s["results"].values())
         rr = sorted(r["info"].get("rel_residual", float("nan")) for r in res)
         conv = [r for r in res if r["error"] is None and r["info"].get("status") == 0]
@@ -384,7 +415,10 @@ def serve_section(n_req, max_it, rate, slots, budget_gb, deadline_s):
     # the same requests with the first-order extension E_1, closed loop, 10x iteration cap
     first = one([dict(r, taylor_order=1) for r in inputs.serving_requests(n_req, seed=2, rate=1.0)], 0.0,
                 cap=10 * max_it)
-    return {"closed_loop": closed, "open_loop": dict(opened, arrival_rate_per_s=lam), "slots": slots,
+    # lockstep batches of up to 32 admitted requests (sbm_solve_batch), closed loop
+    batched = one(inputs.serving_requests(n_req, seed=2, rate=1.0), 0.0, batched_slots=32)
+    return {"closed_loop": closed, "open_loop": dict(opened, arrival_rate_per_s=lam),
+            "closed_loop_lockstep_batches": dict(batched, batch_slots=32), "slots": slots,
             "hbm_budget_GB": budget_gb, "krylov_cap": max_it, "admission_deadline_s": deadline_s,
             "closed_loop_first_order_extension": dict(first, krylov_cap=10 * max_it)}
 

@@ -329,6 +329,26 @@ sbm_status sbm_solve(sbm_handle h, const double *b, double *x, double rel_tol, i
                      int mode, int restart, int jacobi, void *stream, sbm_solve_info *info);
 
 /*
+ * sbm_solve_batch -- n independent solves A_i x_i = b_i (serving), each to
+ * ||b_i - A_i x_i|| <= rel_tol ||b_i||, by restarted GMRES in lockstep: mode
+ * SBM_SOLVE_GMRES_F64 or SBM_SOLVE_GMRES_IR (others: EUNSUPPORTED), no preconditioner.  At
+ * every Krylov step the operator applies of all systems still iterating run as one batch of
+ * applies (sbm_batch_*: one launch per stage per group of operators sharing a kernel
+ * instantiation, groups on up to four streams); the other kernels of each system are the
+ * ones sbm_solve launches, in the same order on that system's own workspace, so x_i and
+ * infos[i] are those of sbm_solve(h_i, b_i, x_i, ...) with jacobi = 0 (bit for bit), except
+ * the seconds, which are the wall time of the whole call.  Systems leave the lockstep as
+ * they converge or reach max_it.  Argument rules as sbm_solve for each i, plus: a handle
+ * appears at most once.  Runs on stream (after the work already on it); synchronous.
+ * infos: n entries, each filled as sbm_solve fills its info.  Returns SBM_OK when every
+ * system converged, else the first failing status (ENOCONV: see infos[i].status and
+ * rel_residual).  Errors: EINVAL, ENOMEM, EUNSUPPORTED, EHIP.
+ */
+sbm_status sbm_solve_batch(int n, const sbm_handle *hs, const double *const *b, double *const *x,
+                           double rel_tol, int max_it, int mode, int restart, void *stream,
+                           sbm_solve_info *infos);
+
+/*
  * sbm_diagonal -- the diagonal of A (device vector of n_dofs entries, precision prec),
  * computed matrix-free from the cell and face contributions.  Asynchronous.
  */

@@ -90,6 +90,7 @@ __global__ void update_kernel(const T *__restrict__ V, int m1, int ncol, const d
   for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
     double s = 0.0;
     const int64_t base = tile_ix(k, 0, m1);
+#pragma unroll 8
     for (int i = 0; i < ncol; ++i) s += y[i] * (double)V[base + (int64_t)i * kTile];
     if (dinv) s *= (double)dinv[k];
     x[k] = (T)((double)x[k] + s);
@@ -298,11 +299,11 @@ __device__ __forceinline__ double wave_sum(const double *__restrict__ p, int nbl
 // block b at partial[i kMaxBlocks + b]); the last block to finish (ticket on *counter, which it
 // resets to 0 for the next launch) adds them in a fixed order, so the result is independent of
 // the block schedule.
-template <typename T, int CPW, int MODE>
-__global__ __launch_bounds__(kThreads) void gs_kernel(const T *__restrict__ V, int m1, int ncol,
-                                                      const double *__restrict__ coef, T *__restrict__ w, int64_t n,
-                                                      double *__restrict__ partial, unsigned *__restrict__ counter,
-                                                      double *__restrict__ out, ArnoldiArgs aa) {
+template <typename T, int CPW, int MODE, bool TICKET = true>
+__device__ __forceinline__ void gs_body(const int blk, const int nblk, const T *__restrict__ V, int m1, int ncol,
+                                        const double *__restrict__ coef, T *__restrict__ w, int64_t n,
+                                        double *__restrict__ partial, unsigned *__restrict__ counter,
+                                        double *__restrict__ out, const ArnoldiArgs &aa) {
   constexpr int NW = kThreads / 64, R = 32 / CPW;
   __shared__ double red[MODE == 0 ? 1 : NW][64 * R];
   __shared__ bool last;
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(kThreads) void gs_kernel(const T *__restrict__ V, i
     acc[c] = 0.0;
     cf[c] = (MODE != 0 && i < ncol) ? coef[i] : 0.0;
   }
-  for (int64_t r0 = (int64_t)blockIdx.x * 64 * R; r0 < n; r0 += (int64_t)gridDim.x * 64 * R) {
+  for (int64_t r0 = (int64_t)blk * 64 * R; r0 < n; r0 += (int64_t)nblk * 64 * R) {
     // unconditional loads from a clamped index (entry 0 outside the range), masked after the
     // conversion: no branch separates a load from the next, so all of them are in flight at once
     T tv[R][CPW], tw[R];
@@ -377,18 +378,18 @@ __global__ __launch_bounds__(kThreads) void gs_kernel(const T *__restrict__ V, i
     double sacc = acc[c];
     for (int off = 32; off > 0; off >>= 1) sacc += __shfl_down(sacc, off, 64);
     const bool mine = MODE == 2 ? (c == 0 && wave == 0) : i < ncol;
-    if (lane == 0 && mine) partial[(int64_t)i * kMaxBlocks + blockIdx.x] = sacc;
+    if (lane == 0 && mine) partial[(int64_t)i * kMaxBlocks + blk] = sacc;
   }
+  if constexpr (!TICKET) return;  // the partials are summed by a later launch (gs_reduce_batch_kernel)
   __syncthreads();  // the block's partials are written (each wave waited for its stores)
   if (threadIdx.x == 0) {
     __threadfence();  // release: the partials before the ticket
-    last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    last = atomicAdd(counter, 1u) == (unsigned)(nblk - 1);
   }
   __syncthreads();
   if (!last) return;
   __threadfence();  // acquire: the other blocks' partials
-  const int nblk = gridDim.x;
-  if constexpr (MODE == 2) {
+    if constexpr (MODE == 2) {
     if (wave == 0) {
       const double sum = wave_sum(partial, nblk, lane);
       if (lane == 0) {
@@ -404,6 +405,14 @@ __global__ __launch_bounds__(kThreads) void gs_kernel(const T *__restrict__ V, i
     }
     if (threadIdx.x == 0) *counter = 0u;
   }
+}
+
+template <typename T, int CPW, int MODE>
+__global__ __launch_bounds__(kThreads) void gs_kernel(const T *__restrict__ V, int m1, int ncol,
+                                                      const double *__restrict__ coef, T *__restrict__ w, int64_t n,
+                                                      double *__restrict__ partial, unsigned *__restrict__ counter,
+                                                      double *__restrict__ out, ArnoldiArgs aa) {
+  gs_body<T, CPW, MODE>(blockIdx.x, gridDim.x, V, m1, ncol, coef, w, n, partial, counter, out, aa);
 }
 
 // The Gram-Schmidt kernels for more than 64 columns: the columns are taken in chunks of 64
@@ -540,9 +549,29 @@ __global__ void gmres_init_kernel(const double *__restrict__ nrm2, double *__res
   for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = i == 0 ? sqrt(*nrm2) : 0.0;
 }
 
-// y = R^-1 g for the leading j x j upper triangle R of H (one thread)
-__global__ void backsub_kernel(int j, int m, const double *__restrict__ H, const double *__restrict__ g,
-                               double *__restrict__ y) {
+// y = R^-1 g for the leading j x j upper triangle R of H, by one thread; for j <= 64 the
+// triangle and g are first staged in LDS by the whole block (the same operations in the same
+// order, without a global-memory round trip per term)
+constexpr int kBacksubLds = 64;
+__device__ void backsub_body(int j, int m, const double *__restrict__ H, const double *__restrict__ g,
+                             double *__restrict__ y) {
+  __shared__ double sH[kBacksubLds * kBacksubLds], sg[kBacksubLds], sy[kBacksubLds];
+  if (j <= kBacksubLds) {
+    for (int t = threadIdx.x; t < j * j; t += blockDim.x) sH[t] = H[(int64_t)(t / j) * m + t % j];
+    for (int t = threadIdx.x; t < j; t += blockDim.x) sg[t] = g[t];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int i = j - 1; i >= 0; --i) {
+        double s = sg[i];
+        for (int k = i + 1; k < j; ++k) s -= sH[i * j + k] * sy[k];
+        const double d = sH[i * j + i];
+        sy[i] = d != 0.0 ? s / d : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < j; t += blockDim.x) y[t] = sy[t];
+    return;
+  }
   if (threadIdx.x != 0) return;
   for (int i = j - 1; i >= 0; --i) {
     double s = g[i];
@@ -550,6 +579,11 @@ __global__ void backsub_kernel(int j, int m, const double *__restrict__ H, const
     const double d = H[(int64_t)i * m + i];
     y[i] = d != 0.0 ? s / d : 0.0;
   }
+}
+
+__global__ void backsub_kernel(int j, int m, const double *__restrict__ H, const double *__restrict__ g,
+                               double *__restrict__ y) {
+  backsub_body(j, m, H, g, y);
 }
 
 // Basis vector col = x * f, stored in column col of the tiled basis V (m1 columns) and in the
@@ -561,6 +595,119 @@ __global__ void basis_store_kernel(const T *__restrict__ x, const double *__rest
   for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
     const T y = (T)((double)x[k] * f);
     V[tile_ix(k, col, m1)] = y;
+    vc[k] = y;
+  }
+}
+
+// ---- the orthogonalisation of a step for several GMRES runs at once (lockstep batches):
+// workgroup g of a launch serves the run blk_item[g] with its own block index and its own
+// block count, the ones the run's single launch would have, so every run's reductions are
+// summed exactly as in its own solve ----
+constexpr int kOrthoKinds = 13;  // 4 column classes (2, 4, 8, 16 columns per wave) x 3 modes, basis store
+struct OrthoItem {
+  void *V, *w, *vc, *x;
+  int64_t n;
+  int m1, m;
+  double *partial;
+  unsigned *counter;
+  double *h1, *h2, *hn, *y;
+  double *H, *cs, *sn, *g, *res, *fac;
+  int blk0[kOrthoKinds], nblk[kOrthoKinds];
+};
+
+template <typename T, int CPW, int MODE>
+__global__ __launch_bounds__(kThreads) void gs_batch_kernel(const OrthoItem *__restrict__ items,
+                                                            const int32_t *__restrict__ blk_item, int ncol, int k) {
+  constexpr int L = CPW == 2 ? 0 : (CPW == 4 ? 1 : (CPW == 8 ? 2 : 3)), KIND = 3 * L + MODE;
+  const int g = blockIdx.x;
+  const OrthoItem *it = items + blk_item[g];
+  const ArnoldiArgs aa{k, it->m, it->h1, it->h2, it->H, it->cs, it->sn, it->g, it->res, it->fac};
+  const double *coef = MODE == 0 ? nullptr : (MODE == 1 ? it->h1 : it->h2);
+  double *out = MODE == 0 ? it->h1 : (MODE == 1 ? it->h2 : it->hn);
+  gs_body<T, CPW, MODE, false>(g - it->blk0[KIND], it->nblk[KIND], (const T *)it->V, it->m1, ncol, coef, (T *)it->w,
+                               it->n, it->partial, it->counter, out, aa);
+}
+
+// The sums of the block partials of a batched Gram-Schmidt launch, one workgroup per run:
+// exactly the last-block sums of gs_body (same partials, same order); MODE 2 also does the
+// run's Arnoldi step.
+template <int CPW, int MODE>
+__global__ __launch_bounds__(kThreads) void gs_reduce_batch_kernel(const OrthoItem *__restrict__ items, int ncol,
+                                                                   int k) {
+  constexpr int L = CPW == 2 ? 0 : (CPW == 4 ? 1 : (CPW == 8 ? 2 : 3)), KIND = 3 * L + MODE, NW = kThreads / 64;
+  const OrthoItem *it = items + blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nblk = it->nblk[KIND];
+  if constexpr (MODE == 2) {
+    if (wave == 0) {
+      const double sum = wave_sum(it->partial, nblk, lane);
+      if (lane == 0) {
+        *it->hn = sum;
+        const ArnoldiArgs aa{k, it->m, it->h1, it->h2, it->H, it->cs, it->sn, it->g, it->res, it->fac};
+        arnoldi_step(aa, sum);
+      }
+    }
+  } else {
+    double *out = MODE == 0 ? it->h1 : it->h2;
+    for (int i = wave; i < ncol; i += NW) {
+      const double sum = wave_sum(it->partial + (int64_t)i * kMaxBlocks, nblk, lane);
+      if (lane == 0) out[i] = sum;
+    }
+  }
+}
+
+// The end of a restart cycle for several runs: y = R^-1 g (one workgroup per run, ncol[i]
+// columns), then x += V y (workgroups of the basis-store table); and the residual estimates
+// res[j0 .. j0 + cnt) of every run gathered into out (run i at out[i * cnt]).
+__global__ __launch_bounds__(kThreads) void backsub_batch_kernel(const OrthoItem *__restrict__ items,
+                                                                 const int *__restrict__ ncol) {
+  const OrthoItem *it = items + blockIdx.x;
+  backsub_body(ncol[blockIdx.x], it->m, it->H, it->g, it->y);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void update_batch_kernel(const OrthoItem *__restrict__ items,
+                                                                const int32_t *__restrict__ blk_item,
+                                                                const int *__restrict__ ncols) {
+  const int gi = blk_item[blockIdx.x];
+  const OrthoItem *it = items + gi;
+  const int b = blockIdx.x - it->blk0[kOrthoKinds - 1], nb = it->nblk[kOrthoKinds - 1], ncol = ncols[gi];
+  const T *V = (const T *)it->V;
+  T *x = (T *)it->x;
+  const double *y = it->y;
+  for (int64_t k = b * (int64_t)kThreads + threadIdx.x; k < it->n; k += (int64_t)nb * kThreads) {
+    double s = 0.0;
+    const int64_t base = tile_ix(k, 0, it->m1);
+#pragma unroll 8
+    for (int i = 0; i < ncol; ++i) s += y[i] * (double)V[base + (int64_t)i * kTile];
+    x[k] = (T)((double)x[k] + s);
+  }
+}
+
+__global__ void gather_res_batch_kernel(const OrthoItem *__restrict__ items, int n_items, int j0, int cnt,
+                                        double *__restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_items * cnt) return;
+  out[t] = items[t / cnt].res[j0 + t % cnt];
+}
+
+__global__ void gather_norm_batch_kernel(const OrthoItem *__restrict__ items, int n_items, double *__restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_items) out[t] = *items[t].hn;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void basis_store_batch_kernel(const OrthoItem *__restrict__ items,
+                                                                     const int32_t *__restrict__ blk_item, int col) {
+  const int g = blockIdx.x;
+  const OrthoItem *it = items + blk_item[g];
+  const int b = g - it->blk0[kOrthoKinds - 1], nb = it->nblk[kOrthoKinds - 1];
+  const double f = *it->fac;
+  const T *x = (const T *)it->w;
+  T *V = (T *)it->V, *vc = (T *)it->vc;
+  for (int64_t k = b * (int64_t)kThreads + threadIdx.x; k < it->n; k += (int64_t)nb * kThreads) {
+    const T y = (T)((double)x[k] * f);
+    V[tile_ix(k, col, it->m1)] = y;
     vc[k] = y;
   }
 }
@@ -745,9 +892,11 @@ static void gs_launch(const Workspace *ws, const T *V, int m1, int ncol, const d
 // column k): w = A M^-1 v_k, two classical Gram-Schmidt passes (CGS2), the norm, the device
 // rotation update (arnoldi_step) and v_(k+1) = w / h_(k+1,k).  Launches only (no host
 // synchronisation).
+// Step k of an Arnoldi run after the apply w = A M^-1 v_k: two classical Gram-Schmidt passes
+// (CGS2: h1 = V^T w; w -= V h1, h2 = V^T w; w -= V h2), |w|^2 and the rotation update, and
+// v_(k+1) = w / h_(k+1,k) into V and vc.
 template <typename T>
-static sbm_status arnoldi_steps(sbm_ctx *c, int prec, T *V, T *vc, T *w, T *z, const T *dinv, int m, int j,
-                                int j1, hipStream_t s) {
+static void arnoldi_orthogonalise(sbm_ctx *c, T *V, T *vc, T *w, int m, int k, hipStream_t s) {
   Workspace *ws = c->ws;
   const int64_t n = c->n_dofs;
   const int nb = nblocks(n);
@@ -755,6 +904,18 @@ static sbm_status arnoldi_steps(sbm_ctx *c, int prec, T *V, T *vc, T *w, T *z, c
   double *h1 = ws->h, *h2 = ws->h + (m + 2), *hn = ws->h + 2 * (m + 2);
   double *H = ws->gm, *cs = H + (size_t)(m + 1) * m, *sn = cs + m, *g = sn + m, *dres = g + (m + 1);
   double *fac = dres + m;
+  const ArnoldiArgs aa{k, m, h1, h2, H, cs, sn, g, dres, fac};
+  gs_launch<T, 0>(ws, V, m1, k + 1, nullptr, w, n, ws->partial, ws->ticket, h1, aa, s);
+  gs_launch<T, 1>(ws, V, m1, k + 1, h1, w, n, ws->partial, ws->ticket, h2, aa, s);
+  gs_launch<T, 2>(ws, V, m1, k + 1, h2, w, n, ws->partial, ws->ticket, hn, aa, s);
+  hipLaunchKernelGGL(basis_store_kernel<T>, dim3(nb), dim3(kThreads), 0, s, w, fac, 0, V, k + 1, m1, vc, n);
+}
+
+template <typename T>
+static sbm_status arnoldi_steps(sbm_ctx *c, int prec, T *V, T *vc, T *w, T *z, const T *dinv, int m, int j,
+                                int j1, hipStream_t s) {
+  const int64_t n = c->n_dofs;
+  const int nb = nblocks(n);
   for (int k = j; k < j1; ++k) {
     // vc holds v_k contiguously
     const T *src = vc;
@@ -763,12 +924,7 @@ static sbm_status arnoldi_steps(sbm_ctx *c, int prec, T *V, T *vc, T *w, T *z, c
       src = z;
     }
     SBM_HIP_CHECK(launch_operator(c, src, w, prec, SBM_PART_ALL, s));
-    // CGS2: h1 = V^T w; w -= V h1, h2 = V^T w; w -= V h2, |w|^2 and the rotation update
-    const ArnoldiArgs aa{k, m, h1, h2, H, cs, sn, g, dres, fac};
-    gs_launch<T, 0>(ws, V, m1, k + 1, nullptr, w, n, ws->partial, ws->ticket, h1, aa, s);
-    gs_launch<T, 1>(ws, V, m1, k + 1, h1, w, n, ws->partial, ws->ticket, h2, aa, s);
-    gs_launch<T, 2>(ws, V, m1, k + 1, h2, w, n, ws->partial, ws->ticket, hn, aa, s);
-    hipLaunchKernelGGL(basis_store_kernel<T>, dim3(nb), dim3(kThreads), 0, s, w, fac, 0, V, k + 1, m1, vc, n);
+    arnoldi_orthogonalise<T>(c, V, vc, w, m, k, s);
   }
   SBM_HIP_CHECK(hipGetLastError());
   return SBM_OK;
@@ -1122,6 +1278,553 @@ static sbm_status solve_on(sbm_handle h, const double *b, double *x, double rel_
   return st;
 }
 
+// ---- batched solves: restarted GMRES (FP64, or FP32 inside FP64 refinement) of several
+// operators in lockstep.  Every operator apply of a step runs for all operators at once
+// through a batch of applies (sbm_batch_*: one launch per stage per group of operators of one
+// kernel instantiation); everything else is launched per operator exactly as a single solve
+// launches it, in the same order on its own data, so each result is bitwise that operator's
+// sbm_solve (the residual checks are only read back at other points of the run) ----
+
+namespace {
+
+// One operator's restarted-GMRES run inside a lockstep batch (the state gmres_run keeps in
+// locals).
+template <typename T>
+struct GItem {
+  sbm_ctx *c = nullptr;
+  const T *rhs = nullptr;
+  T *x = nullptr, *V = nullptr, *vc = nullptr, *w = nullptr;
+  double tol_abs = 0.0;
+  int max_it = 0;
+  int its = 0, applies = 0;
+  double res = 0.0;
+  bool done = false;   // the run has ended (tolerance, iteration bound or breakdown)
+  int j = 0, j1 = 0;   // Arnoldi steps of the current cycle: done so far, and this chunk's end
+  bool stop = false;
+  sbm_status st = SBM_OK;
+};
+
+// A batch of applies kept while its membership does not change.
+struct PlanCache {
+  sbm_batch b = nullptr;
+  std::vector<const void *> key;
+  ~PlanCache() { (void)sbm_batch_destroy(b); }
+  sbm_status run(const std::vector<sbm_ctx *> &cs, const std::vector<const void *> &u, const std::vector<void *> &v,
+                 int prec, hipStream_t s) {
+    std::vector<const void *> k;
+    for (size_t i = 0; i < cs.size(); ++i) {
+      k.push_back(cs[i]);
+      k.push_back(u[i]);
+      k.push_back(v[i]);
+    }
+    if (!b || k != key) {
+      (void)sbm_batch_destroy(b);
+      b = nullptr;
+      std::vector<sbm_handle> hs(cs.begin(), cs.end());
+      std::vector<void *> vv(v.begin(), v.end());
+      const sbm_status st =
+          sbm_batch_create((int)cs.size(), hs.data(), u.data(), vv.data(), prec, 0, 4, &b);
+      if (st != SBM_OK) return st;
+      key = k;
+    }
+    return sbm_batch_run(b, s);
+  }
+};
+
+// The orthogonalisation of step k for a set of runs (all at the same step, so with the same
+// number of columns): one launch per Gram-Schmidt kernel and one for the basis store, with the
+// tables of the set (every column class and mode) built once per set.  Past 64 columns
+// (restart > 63) the runs are launched one by one.
+template <typename T>
+struct OrthoPlan {
+  void *d = nullptr;
+  std::vector<const void *> key;
+  size_t off_items = 0, off_tab[kOrthoKinds] = {}, off_ncol = 0, off_out = 0;
+  int total[kOrthoKinds] = {};
+  std::vector<GItem<T> *> set;
+  std::vector<int> ncol_h;  // host copy of the column counts being uploaded (kept until the next sync)
+  ~OrthoPlan() { dev_free(d); }
+
+  sbm_status prepare(const std::vector<GItem<T> *> &sub, int m, hipStream_t s) {
+    std::vector<const void *> k(sub.begin(), sub.end());
+    if (d && k == key) return SBM_OK;
+    if (d) {
+      SBM_HIP_CHECK(hipStreamSynchronize(s));  // the old tables may still be read
+      dev_free(d);
+      d = nullptr;
+    }
+    std::vector<OrthoItem> items(sub.size());
+    std::vector<int32_t> tab[kOrthoKinds];
+    int tot[kOrthoKinds] = {};
+    for (size_t i = 0; i < sub.size(); ++i) {
+      GItem<T> *a = sub[i];
+      Workspace *ws = a->c->ws;
+      const int64_t n = a->c->n_dofs;
+      OrthoItem &o = items[i];
+      o.V = a->V;
+      o.w = a->w;
+      o.vc = a->vc;
+      o.x = a->x;
+      o.y = ws->y;
+      o.n = n;
+      o.m1 = ws->m + 1;
+      o.m = m;
+      o.partial = ws->partial;
+      o.counter = ws->ticket;
+      o.h1 = ws->h;
+      o.h2 = ws->h + (m + 2);
+      o.hn = ws->h + 2 * (m + 2);
+      o.H = ws->gm;
+      o.cs = o.H + (size_t)(m + 1) * m;
+      o.sn = o.cs + m;
+      o.g = o.sn + m;
+      o.res = o.g + (m + 1);
+      o.fac = o.res + m;
+      const int(*caps)[3] = ws->gs_grid[sizeof(T) == 4 ? 1 : 0];
+      for (int kind = 0; kind < kOrthoKinds; ++kind) {
+        int nb;
+        if (kind < kOrthoKinds - 1) {
+          const int L = kind / 3, mode = kind % 3;
+          const int64_t rows = 64 * (32 / (2 << L));  // as gs_launch1
+          nb = (int)std::max<int64_t>(1, std::min<int64_t>((n + rows - 1) / rows, caps[L][mode]));
+        } else {
+          nb = nblocks(n);
+        }
+        o.blk0[kind] = tot[kind];
+        o.nblk[kind] = nb;
+        tab[kind].insert(tab[kind].end(), (size_t)nb, (int32_t)i);
+        tot[kind] += nb;
+      }
+    }
+    std::vector<unsigned char> image;
+    auto put = [&image](const void *src, size_t bytes) {
+      const size_t off = (image.size() + 255) / 256 * 256;
+      image.resize(off + std::max<size_t>(bytes, 4));
+      if (bytes) std::memcpy(image.data() + off, src, bytes);
+      return off;
+    };
+    off_items = put(items.data(), items.size() * sizeof(OrthoItem));
+    for (int kind = 0; kind < kOrthoKinds; ++kind) {
+      off_tab[kind] = put(tab[kind].data(), tab[kind].size() * sizeof(int32_t));
+      total[kind] = tot[kind];
+    }
+    off_ncol = put(nullptr, 0);
+    image.resize(off_ncol + sizeof(int) * sub.size());
+    off_out = put(nullptr, 0);
+    image.resize(off_out + sizeof(double) * sub.size() * (size_t)(m + 1));
+    SBM_HIP_CHECK(dev_alloc(&d, image.size()));
+    SBM_HIP_CHECK(hipMemcpyAsync(d, image.data(), image.size(), hipMemcpyHostToDevice, lib_stream()));
+    SBM_HIP_CHECK(hipStreamSynchronize(lib_stream()));
+    key = k;
+    set = sub;
+    return SBM_OK;
+  }
+
+  template <int CPW>
+  void launch_modes(int ncol, int k, hipStream_t s) {
+    constexpr int L = CPW == 2 ? 0 : (CPW == 4 ? 1 : (CPW == 8 ? 2 : 3));
+    const unsigned char *b = static_cast<const unsigned char *>(d);
+    const OrthoItem *items = reinterpret_cast<const OrthoItem *>(b + off_items);
+    auto tab = [&](int kind) { return reinterpret_cast<const int32_t *>(b + off_tab[kind]); };
+    const int ni = (int)set.size();
+    hipLaunchKernelGGL((gs_batch_kernel<T, CPW, 0>), dim3(total[3 * L]), dim3(kThreads), 0, s, items, tab(3 * L),
+                       ncol, k);
+    hipLaunchKernelGGL((gs_reduce_batch_kernel<CPW, 0>), dim3(ni), dim3(kThreads), 0, s, items, ncol, k);
+    hipLaunchKernelGGL((gs_batch_kernel<T, CPW, 1>), dim3(total[3 * L + 1]), dim3(kThreads), 0, s, items,
+                       tab(3 * L + 1), ncol, k);
+    hipLaunchKernelGGL((gs_reduce_batch_kernel<CPW, 1>), dim3(ni), dim3(kThreads), 0, s, items, ncol, k);
+    hipLaunchKernelGGL((gs_batch_kernel<T, CPW, 2>), dim3(total[3 * L + 2]), dim3(kThreads), 0, s, items,
+                       tab(3 * L + 2), ncol, k);
+    hipLaunchKernelGGL((gs_reduce_batch_kernel<CPW, 2>), dim3(ni), dim3(kThreads), 0, s, items, ncol, k);
+    hipLaunchKernelGGL((basis_store_batch_kernel<T>), dim3(total[kOrthoKinds - 1]), dim3(kThreads), 0, s, items,
+                       tab(kOrthoKinds - 1), k + 1);
+  }
+
+  const OrthoItem *items_dev() const {
+    return reinterpret_cast<const OrthoItem *>(static_cast<const unsigned char *>(d) + off_items);
+  }
+  double *out_dev() const { return reinterpret_cast<double *>(static_cast<unsigned char *>(d) + off_out); }
+
+  // res[j0 .. j0 + cnt) of every run of the set, run i at out[i cnt] (one copy, one sync)
+  sbm_status gather_res(int j0, int cnt, std::vector<double> &out, hipStream_t s) {
+    const int ni = (int)set.size(), tot = ni * cnt;
+    out.assign((size_t)tot, 0.0);
+    if (tot == 0) return SBM_OK;
+    hipLaunchKernelGGL(gather_res_batch_kernel, dim3((tot + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                       items_dev(), ni, j0, cnt, out_dev());
+    SBM_HIP_CHECK(hipMemcpyAsync(out.data(), out_dev(), sizeof(double) * tot, hipMemcpyDeviceToHost, s));
+    SBM_HIP_CHECK(hipStreamSynchronize(s));
+    return SBM_OK;
+  }
+
+  // the squared norms *hn of every run of the set
+  sbm_status gather_norms(std::vector<double> &out, hipStream_t s) {
+    const int ni = (int)set.size();
+    out.assign((size_t)ni, 0.0);
+    hipLaunchKernelGGL(gather_norm_batch_kernel, dim3((ni + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                       items_dev(), ni, out_dev());
+    SBM_HIP_CHECK(hipMemcpyAsync(out.data(), out_dev(), sizeof(double) * ni, hipMemcpyDeviceToHost, s));
+    SBM_HIP_CHECK(hipStreamSynchronize(s));
+    return SBM_OK;
+  }
+
+  // y = R^-1 g and x += V y with ncol[i] columns for run i of the set
+  sbm_status finish(const std::vector<int> &ncol, hipStream_t s) {
+    ncol_h = ncol;
+    int *dn = reinterpret_cast<int *>(static_cast<unsigned char *>(d) + off_ncol);
+    SBM_HIP_CHECK(hipMemcpyAsync(dn, ncol_h.data(), sizeof(int) * ncol_h.size(), hipMemcpyHostToDevice, s));
+    const unsigned char *b = static_cast<const unsigned char *>(d);
+    hipLaunchKernelGGL(backsub_batch_kernel, dim3((unsigned)set.size()), dim3(kThreads), 0, s, items_dev(),
+                       (const int *)dn);
+    hipLaunchKernelGGL((update_batch_kernel<T>), dim3(total[kOrthoKinds - 1]), dim3(kThreads), 0, s, items_dev(),
+                       reinterpret_cast<const int32_t *>(b + off_tab[kOrthoKinds - 1]), (const int *)dn);
+    SBM_HIP_CHECK(hipGetLastError());
+    return SBM_OK;
+  }
+
+  // step k (column k + 1 formed) for the prepared set
+  void launch(int m, int k, hipStream_t s) {
+    const int ncol = k + 1;
+    if (ncol <= 8) {
+      launch_modes<2>(ncol, k, s);
+    } else if (ncol <= 16) {
+      launch_modes<4>(ncol, k, s);
+    } else if (ncol <= 32) {
+      launch_modes<8>(ncol, k, s);
+    } else if (ncol <= 64) {
+      launch_modes<16>(ncol, k, s);
+    } else {
+      for (GItem<T> *a : set) arnoldi_orthogonalise<T>(a->c, a->V, a->vc, a->w, m, k, s);
+    }
+  }
+};
+
+// Reads one device double per entry of src into out (one synchronisation).
+static hipError_t read_scalars(const std::vector<const double *> &src, std::vector<double> &out, hipStream_t s) {
+  out.assign(src.size(), 0.0);
+  for (size_t i = 0; i < src.size(); ++i) {
+    hipError_t e = hipMemcpyAsync(&out[i], src[i], sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipStreamSynchronize(s);
+}
+
+template <typename T>
+static sbm_status gmres_batch(std::vector<GItem<T>> &items, int prec, int m, hipStream_t s) {
+  const int check = 8;  // steps between residual read-backs
+  PlanCache px, pv;
+  OrthoPlan<T> ortho, pact, prun;
+  for (auto &it : items) {
+    int(*grid)[3] = it.c->ws->gs_grid[sizeof(T) == 4 ? 1 : 0];
+    if (grid[0][0] == 0) gs_grid_caps<T>(grid);
+    it.its = 0;
+    it.done = false;
+  }
+  for (int cycle = 0;; ++cycle) {
+    std::vector<GItem<T> *> act;
+    for (auto &it : items)
+      if (!it.done) act.push_back(&it);
+    if (act.empty()) return SBM_OK;
+    // r = rhs - A x -> V_0, for every run still going
+    {
+      std::vector<sbm_ctx *> cs;
+      std::vector<const void *> us;
+      std::vector<void *> vs;
+      for (auto *a : act) {
+        cs.push_back(a->c);
+        us.push_back(a->x);
+        vs.push_back(a->w);
+      }
+      const sbm_status st = px.run(cs, us, vs, prec, s);
+      if (st != SBM_OK) return st;
+    }
+    for (auto *a : act) {
+      Workspace *ws = a->c->ws;
+      const int64_t n = a->c->n_dofs;
+      ++a->applies;
+      hipLaunchKernelGGL(residual_kernel<T>, dim3(nblocks(n)), dim3(kThreads), 0, s, a->rhs, a->w, a->vc, n);
+      SBM_HIP_CHECK(multidot<T>(a->vc, n, 1, a->vc, n, ws->partial, ws->h + 2 * (m + 2), s));
+    }
+    std::vector<double> b2;
+    {
+      sbm_status st = pact.prepare(act, m, s);
+      if (st == SBM_OK) st = pact.gather_norms(b2, s);
+      if (st != SBM_OK) return st;
+    }
+    std::vector<GItem<T> *> run;
+    for (size_t i = 0; i < act.size(); ++i) {
+      GItem<T> *a = act[i];
+      const double beta = std::sqrt(b2[i]);
+      a->res = beta;
+      if (!(beta > a->tol_abs) || a->its >= a->max_it) {
+        a->done = true;
+        a->st = std::isfinite(beta) ? SBM_OK : SBM_ENOCONV;
+        continue;
+      }
+      Workspace *ws = a->c->ws;
+      const int64_t n = a->c->n_dofs;
+      double *hn = ws->h + 2 * (m + 2);
+      double *g = ws->gm + (size_t)(m + 1) * m + 2 * m;
+      hipLaunchKernelGGL(basis_store_kernel<T>, dim3(nblocks(n)), dim3(kThreads), 0, s, a->vc, hn, 1, a->V, 0,
+                         ws->m + 1, a->vc, n);
+      hipLaunchKernelGGL(gmres_init_kernel, dim3(1), dim3(64), 0, s, hn, g, m);
+      a->j = 0;
+      a->stop = false;
+      run.push_back(a);
+    }
+    // Arnoldi steps in chunks of `check`, the applies of each step batched over the runs
+    // taking it
+    for (;;) {
+      std::vector<GItem<T> *> in;
+      for (auto *a : run)
+        if (a->j < m && a->its < a->max_it && !a->stop) in.push_back(a);
+      if (in.empty()) break;
+      int k0 = m, k1 = 0;
+      for (auto *a : in) {
+        a->j1 = std::min({m, a->j + check, a->j + (a->max_it - a->its)});
+        k0 = std::min(k0, a->j);
+        k1 = std::max(k1, a->j1);
+      }
+      for (int k = k0; k < k1; ++k) {
+        std::vector<sbm_ctx *> cs;
+        std::vector<const void *> us;
+        std::vector<void *> vs;
+        std::vector<GItem<T> *> sub;
+        for (auto *a : in)
+          if (a->j <= k && k < a->j1) {
+            cs.push_back(a->c);
+            us.push_back(a->vc);
+            vs.push_back(a->w);
+            sub.push_back(a);
+          }
+        sbm_status st = pv.run(cs, us, vs, prec, s);
+        if (st == SBM_OK) st = ortho.prepare(sub, m, s);
+        if (st != SBM_OK) return st;
+        ortho.launch(m, k, s);
+      }
+      SBM_HIP_CHECK(hipGetLastError());
+      // residual estimates of the chunk (gathered into one copy when every run took the same
+      // steps), then the same stopping rule as a check after every step
+      std::vector<std::vector<double>> rh(in.size());
+      bool same = true;
+      for (auto *a : in) same = same && a->j == in[0]->j && a->j1 == in[0]->j1;
+      if (same && ortho.set == in) {
+        const int cnt = in[0]->j1 - in[0]->j;
+        std::vector<double> all;
+        const sbm_status st = ortho.gather_res(in[0]->j, cnt, all, s);
+        if (st != SBM_OK) return st;
+        for (size_t i = 0; i < in.size(); ++i) rh[i].assign(all.begin() + i * cnt, all.begin() + (i + 1) * cnt);
+      } else {
+        for (size_t i = 0; i < in.size(); ++i) {
+          GItem<T> *a = in[i];
+          const double *dres = a->c->ws->gm + (size_t)(m + 1) * m + 2 * m + (m + 1);
+          rh[i].resize(a->j1 - a->j);
+          SBM_HIP_CHECK(hipMemcpyAsync(rh[i].data(), dres + a->j, sizeof(double) * (a->j1 - a->j),
+                                       hipMemcpyDeviceToHost, s));
+        }
+        SBM_HIP_CHECK(hipStreamSynchronize(s));
+      }
+      for (size_t i = 0; i < in.size(); ++i) {
+        GItem<T> *a = in[i];
+        a->applies += a->j1 - a->j;
+        int k = a->j;
+        while (k < a->j1 && rh[i][k - a->j] > a->tol_abs) ++k;
+        if (k < a->j1) {
+          a->its += k + 1 - a->j;
+          a->j = k + 1;
+          a->stop = true;
+        } else {
+          a->its += a->j1 - a->j;
+          a->j = a->j1;
+        }
+      }
+    }
+    // back substitution and update x += V y, from the leading j columns
+    std::vector<GItem<T> *> fin;
+    std::vector<int> ncol;
+    for (auto *a : run)
+      if (a->j > 0) {
+        fin.push_back(a);
+        ncol.push_back(a->j);
+      }
+    if (!fin.empty()) {
+      sbm_status st = prun.prepare(fin, m, s);
+      if (st == SBM_OK) st = prun.finish(ncol, s);
+      if (st != SBM_OK) return st;
+    }
+  }
+}
+
+// FP64 applies of x for every operator listed (t = A x), then r = b - t and |r|^2 read back.
+static sbm_status batch_residuals(const std::vector<sbm_ctx *> &cs, const std::vector<const double *> &b,
+                                  const std::vector<double *> &x, PlanCache &plan, hipStream_t s,
+                                  std::vector<double> &rn2) {
+  std::vector<const void *> us(x.begin(), x.end());
+  std::vector<void *> vs;
+  for (sbm_ctx *c : cs) vs.push_back(c->ws->t);
+  sbm_status st = plan.run(cs, us, vs, SBM_F64, s);
+  if (st != SBM_OK) return st;
+  std::vector<const double *> src;
+  for (size_t i = 0; i < cs.size(); ++i) {
+    Workspace *ws = cs[i]->ws;
+    const int64_t n = cs[i]->n_dofs;
+    hipLaunchKernelGGL(residual_kernel<double>, dim3(nblocks(n)), dim3(kThreads), 0, s, b[i], ws->t, ws->r, n);
+    SBM_HIP_CHECK(multidot<double>(ws->r, n, 1, ws->r, n, ws->partial, ws->h, s));
+    src.push_back(ws->h);
+  }
+  SBM_HIP_CHECK(read_scalars(src, rn2, s));
+  return SBM_OK;
+}
+
+}  // namespace
+
+static sbm_status solve_batch_on(int n, sbm_handle *hs, const double *const *b, double *const *x, double rel_tol,
+                                 int max_it, int mode, int m, hipStream_t s, sbm_solve_info *infos,
+                                 std::chrono::steady_clock::time_point t0) {
+  std::vector<int> idx;  // operators with unknowns
+  for (int i = 0; i < n; ++i) {
+    if (hs[i]->n_dofs > 0) {
+      idx.push_back(i);
+    } else {
+      infos[i].status = SBM_OK;
+    }
+  }
+  const int q = (int)idx.size();
+  if (q == 0) return SBM_OK;
+  std::vector<sbm_ctx *> cs;
+  std::vector<const double *> bs;
+  std::vector<double *> xs;
+  for (int i : idx) {
+    cs.push_back(hs[i]);
+    bs.push_back(b[i]);
+    xs.push_back(x[i]);
+  }
+  // ||b|| and the absolute tolerances
+  std::vector<const double *> src;
+  for (int k = 0; k < q; ++k) {
+    SBM_HIP_CHECK(multidot<double>(bs[k], cs[k]->n_dofs, 1, bs[k], cs[k]->n_dofs, cs[k]->ws->partial, cs[k]->ws->h, s));
+    src.push_back(cs[k]->ws->h);
+  }
+  std::vector<double> bn2;
+  SBM_HIP_CHECK(read_scalars(src, bn2, s));
+  std::vector<double> bnorm(q), tol_abs(q);
+  for (int k = 0; k < q; ++k) {
+    bnorm[k] = std::sqrt(bn2[k]);
+    tol_abs[k] = rel_tol * (bnorm[k] > 0 ? bnorm[k] : 1.0);
+  }
+  std::vector<sbm_status> st(q, SBM_OK);
+  PlanCache p64;
+  if (mode == SBM_SOLVE_GMRES_F64) {
+    std::vector<GItem<double>> items(q);
+    for (int k = 0; k < q; ++k) {
+      Workspace *ws = cs[k]->ws;
+      GItem<double> &it = items[k];
+      it.c = cs[k];
+      it.rhs = bs[k];
+      it.x = xs[k];
+      it.V = ws->V;
+      it.vc = ws->vc;
+      it.w = ws->w;
+      it.tol_abs = tol_abs[k];
+      it.max_it = max_it;
+    }
+    const sbm_status e = gmres_batch<double>(items, SBM_F64, m, s);
+    if (e != SBM_OK) return e;
+    for (int k = 0; k < q; ++k) {
+      sbm_solve_info &inf = infos[idx[k]];
+      inf.inner_its = items[k].its;
+      inf.outer_its = (items[k].its + m - 1) / m;
+      inf.applies_f64 = items[k].applies;
+      st[k] = items[k].st;
+    }
+  } else {
+    // FP64 refinement around FP32 GMRES, in lockstep: r = b - A x (FP64), c ~= A32^-1 (r / |r|)
+    // by FP32 GMRES to max(1e-6, tol / (2 |r|)) in at most 4 restart cycles, x += |r| c
+    std::vector<int> total(q, 0);
+    std::vector<bool> live(q, true);
+    for (int outer = 0;; ++outer) {
+      std::vector<int> on;
+      for (int k = 0; k < q; ++k)
+        if (live[k]) on.push_back(k);
+      if (on.empty()) break;
+      std::vector<sbm_ctx *> c_on;
+      std::vector<const double *> b_on;
+      std::vector<double *> x_on;
+      for (int k : on) {
+        c_on.push_back(cs[k]);
+        b_on.push_back(bs[k]);
+        x_on.push_back(xs[k]);
+      }
+      std::vector<double> rn2;
+      const sbm_status e = batch_residuals(c_on, b_on, x_on, p64, s, rn2);
+      if (e != SBM_OK) return e;
+      std::vector<GItem<float>> items;
+      std::vector<int> of;
+      std::vector<double> res_on;
+      for (size_t i = 0; i < on.size(); ++i) {
+        const int k = on[i];
+        sbm_solve_info &inf = infos[idx[k]];
+        ++inf.applies_f64;
+        const double res = std::sqrt(rn2[i]);
+        inf.outer_its = outer;
+        if (!(res > tol_abs[k]) || total[k] >= max_it || !std::isfinite(res)) {
+          live[k] = false;
+          continue;
+        }
+        Workspace *ws = cs[k]->ws;
+        const int64_t nk = cs[k]->n_dofs;
+        SBM_HIP_CHECK(hipMemcpyAsync(ws->y + (m + 1), ws->h, sizeof(double), hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(to_f32_kernel, dim3(nblocks(nk)), dim3(kThreads), 0, s, ws->r, ws->y + (m + 1), ws->r32,
+                           nk);
+        hipLaunchKernelGGL(fill_f32_kernel, dim3(nblocks(nk)), dim3(kThreads), 0, s, ws->c32, nk);
+        GItem<float> it;
+        it.c = cs[k];
+        it.rhs = ws->r32;
+        it.x = ws->c32;
+        it.V = ws->V32;
+        it.vc = ws->vc32;
+        it.w = ws->w32;
+        it.tol_abs = std::max(1e-6, 0.5 * tol_abs[k] / res);
+        it.max_it = std::min(4 * m, max_it - total[k]);
+        items.push_back(it);
+        of.push_back(k);
+      }
+      if (items.empty()) continue;
+      const sbm_status ge = gmres_batch<float>(items, SBM_F32, m, s);
+      if (ge != SBM_OK) return ge;
+      for (size_t i = 0; i < items.size(); ++i) {
+        const int k = of[i];
+        sbm_solve_info &inf = infos[idx[k]];
+        total[k] += items[i].its;
+        inf.applies_f32 += items[i].applies;
+        Workspace *ws = cs[k]->ws;
+        hipLaunchKernelGGL(add_f32_kernel, dim3(nblocks(cs[k]->n_dofs)), dim3(kThreads), 0, s, ws->c32,
+                           ws->y + (m + 1), xs[k], cs[k]->n_dofs);
+        if (items[i].its == 0) live[k] = false;
+      }
+    }
+    for (int k = 0; k < q; ++k) infos[idx[k]].inner_its = total[k];
+  }
+  // final true residuals in FP64
+  std::vector<double> rn2;
+  const sbm_status e = batch_residuals(cs, bs, xs, p64, s, rn2);
+  if (e != SBM_OK) return e;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  sbm_status worst = SBM_OK;
+  for (int k = 0; k < q; ++k) {
+    sbm_solve_info &inf = infos[idx[k]];
+    ++inf.applies_f64;
+    inf.rel_residual = std::sqrt(rn2[k]) / (bnorm[k] > 0 ? bnorm[k] : 1.0);
+    inf.seconds = secs;
+    sbm_status sk = st[k];
+    if (sk == SBM_OK && !(inf.rel_residual <= rel_tol)) sk = SBM_ENOCONV;
+    inf.status = sk;
+    if (sk != SBM_OK && worst == SBM_OK) worst = sk;
+  }
+  if (worst == SBM_ENOCONV) set_error("sbm_solve_batch: tolerance not reached within max_it by some systems");
+  return worst;
+}
+
 extern "C" {
 
 sbm_status sbm_l2_error(sbm_handle h, const double *x, const double *ustar_qp, double *err) {
@@ -1285,6 +1988,55 @@ sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double 
                                (hipStream_t)stream));
   SBM_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
   return SBM_OK;
+}
+
+sbm_status sbm_solve_batch(int n, const sbm_handle *hs, const double *const *b, double *const *x, double rel_tol,
+                           int max_it, int mode, int restart, void *stream, sbm_solve_info *infos) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (n < 0 || (n > 0 && (!hs || !b || !x || !infos)) || !(rel_tol > 0) || max_it < 1) {
+    set_error("sbm_solve_batch: invalid argument");
+    return SBM_EINVAL;
+  }
+  for (int i = 0; i < n; ++i) std::memset(&infos[i], 0, sizeof(sbm_solve_info));
+  if (mode != SBM_SOLVE_GMRES_F64 && mode != SBM_SOLVE_GMRES_IR) {
+    set_error("sbm_solve_batch: only SBM_SOLVE_GMRES_F64 and SBM_SOLVE_GMRES_IR are batched");
+    for (int i = 0; i < n; ++i) infos[i].status = SBM_EUNSUPPORTED;
+    return SBM_EUNSUPPORTED;
+  }
+  std::vector<const sbm_ctx *> seen;
+  for (int i = 0; i < n; ++i) {
+    const sbm_ctx *c = hs[i];
+    const bool bad = !c || c->host_only || (c->n_dofs > 0 && (!b[i] || !x[i] || (const void *)b[i] == x[i])) ||
+                     std::find(seen.begin(), seen.end(), c) != seen.end();
+    if (bad) {
+      set_error("sbm_solve_batch: NULL, host-only or repeated handle, or NULL or aliased vectors");
+      for (int k = 0; k < n; ++k) infos[k].status = SBM_EINVAL;
+      return SBM_EINVAL;
+    }
+    seen.push_back(c);
+  }
+  const int m = restart > 0 ? std::min(restart, kMaxRestart) : 50;
+  for (int i = 0; i < n; ++i) {
+    if (hs[i]->n_dofs == 0) continue;
+    const hipError_t e = ensure_workspace(hs[i], m, mode == SBM_SOLVE_GMRES_IR);
+    if (e != hipSuccess) {
+      set_error(std::string("sbm_solve_batch: workspace allocation failed: ") + hipGetErrorString(e));
+      for (int k = 0; k < n; ++k) infos[k].status = SBM_ENOMEM;
+      return SBM_ENOMEM;
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<sbm_handle> hv(hs, hs + n);
+  sbm_status st = solve_batch_on(n, hv.data(), b, x, rel_tol, max_it, mode, m, s, infos, t0);
+  const hipError_t se = hipStreamSynchronize(s);
+  if (st == SBM_OK && se != hipSuccess) {
+    set_error(std::string("sbm_solve_batch: ") + hipGetErrorString(se));
+    st = SBM_EHIP;
+  }
+  if (st == SBM_EHIP || st == SBM_ENOMEM || st == SBM_EINVAL)
+    for (int k = 0; k < n; ++k)
+      if (infos[k].status == SBM_OK) infos[k].status = st;
+  return st;
 }
 
 sbm_status sbm_diagonal(sbm_handle h, void *diag, int prec, void *stream) {

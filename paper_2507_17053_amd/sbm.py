@@ -89,6 +89,9 @@ _lib.sbm_rhs_points.argtypes = [_P, _P, _P]
 _lib.sbm_rhs.argtypes = [_P, _P, _P, _P, _P]
 _lib.sbm_solve.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                            _P, ctypes.POINTER(SolveInfo)]
+_lib.sbm_solve_batch.argtypes = [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                 ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P,
+                                 ctypes.POINTER(SolveInfo)]
 _lib.sbm_diagonal.argtypes = [_P, _P, ctypes.c_int, _P]
 _lib.sbm_l2_error.argtypes = [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]
 _lib.sbm_set_extension_order.argtypes = [_P, ctypes.c_int]
@@ -103,7 +106,7 @@ _lib.sbm_layout_stats.argtypes = [_P, _I64P, _I64P, _I64P]
 EXPORTED = ["sbm_setup", "sbm_info", "sbm_destroy", "sbm_last_error", "sbm_apply", "sbm_apply_noalloc",
             "sbm_apply_parts",
             "sbm_apply_batch", "sbm_batch_create", "sbm_batch_run", "sbm_batch_destroy", "sbm_layout_stats",
-            "sbm_dof_points", "sbm_rhs_points", "sbm_rhs", "sbm_l2_error", "sbm_solve", "sbm_diagonal",
+            "sbm_dof_points", "sbm_rhs_points", "sbm_rhs", "sbm_l2_error", "sbm_solve", "sbm_solve_batch", "sbm_diagonal",
             "sbm_footprint_estimate", "sbm_export_cells", "sbm_export_sbm_faces", "sbm_export_face_xi",
             "sbm_export_cell_dofs"]
 
@@ -383,6 +386,29 @@ def apply_batch(ops, us, vs, stream=None):
     (sbm_apply_batch; asynchronous)."""
     n, hs, up, vp, prec = _batch_args(ops, us, vs)
     _check(_lib.sbm_apply_batch(n, hs, up, vp, prec, _stream_ptr(stream)), "sbm_apply_batch")
+
+
+def solve_batch(ops, bs, xs, rel_tol=1e-10, max_it=1000, mode="gmres_ir", restart=50, stream=None):
+    """Lockstep GMRES solves of several systems, their applies batched (sbm_solve_batch).
+    bs, xs: FP64 device tensors (xs: initial guesses, overwritten).  Returns one info dict per
+    system (status, outer_its, inner_its, applies_f64, applies_f32, rel_residual, seconds);
+    does not raise when a system stops short of the tolerance (its status says so)."""
+    import torch
+    n = len(ops)
+    if len(bs) != n or len(xs) != n:
+        raise ValueError("one right-hand side and one solution per operator")
+    for o, b, x in zip(ops, bs, xs):
+        if b.dtype != torch.float64 or x.dtype != torch.float64 or b.numel() != o.n_dofs or x.numel() != o.n_dofs:
+            raise ValueError("b and x must be FP64 vectors of the operators' sizes")
+    hs = (_P * max(n, 1))(*[o.handle for o in ops])
+    bp = (_P * max(n, 1))(*[b.data_ptr() for b in bs])
+    xp = (_P * max(n, 1))(*[x.data_ptr() for x in xs])
+    infos = (SolveInfo * max(n, 1))()
+    st = _lib.sbm_solve_batch(n, hs, bp, xp, float(rel_tol), int(max_it), SOLVE_MODES[mode], int(restart),
+                              _stream_ptr(stream), infos)
+    if st not in (SBM_OK, SBM_ENOCONV):
+        _check(st, "sbm_solve_batch")
+    return [infos[i].as_dict() for i in range(n)]
 
 
 class Batch:

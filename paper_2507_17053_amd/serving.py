@@ -259,6 +259,89 @@ class Server:
         }
 
 
+def run_batched(server, requests, time_scale=1.0, deadline_s=None, keep_solutions=False):
+    """Serve `requests` in lockstep batches: the scheduler admits every arrived request that
+    fits (slots, HBM budget), their operators and right-hand sides are set up, and the whole
+    set is solved together by sbm_solve_batch (each Krylov step's applies of all of them in one
+    batch of launches); then the next set is admitted.  Requests that arrive while a set is
+    solving wait for it to finish.  Same summary as Server.run."""
+    import torch
+
+    from . import inputs, sbm
+    sched = server.sched
+    reqs = {r["id"]: r for r in requests}
+    for r in requests:
+        fp, nd = server._estimate(r)
+        r["_footprint"], r["_n_dofs"] = fp, nd
+        sched.submit(r["id"], r["arrival"] * time_scale, fp, r)
+    t0 = time.perf_counter()
+    results = {}
+    while not sched.idle():
+        now = time.perf_counter() - t0
+        if deadline_s is not None and now > deadline_s:
+            sched.pending.clear()
+            break
+        batch = sched.admit(now)
+        if not batch:
+            nxt = sched.pending[0].arrival - now if sched.pending else 0.0
+            time.sleep(min(0.05, max(1e-3, nxt)))
+            continue
+        starts = time.perf_counter() - t0
+        ops, bs, xs, kept = [], [], [], []
+        try:
+            for rid, req in batch:
+                try:
+                    op = sbm.Operator(req["d"], req["n"], req["lo"], req["hi"], req["levelset"], req["p"],
+                                      disc=req["disc"], taylor_order=req.get("taylor_order", server.taylor_order),
+                                      solver_graphs=False)
+                except Exception as exc:  # a failed setup is reported; the others go on
+                    results[rid] = dict(id=rid, arrival=req["arrival"] * time_scale, start=starts,
+                                        end=time.perf_counter() - t0, error=repr(exc), info={}, x=None)
+                    results[rid]["latency"] = results[rid]["end"] - results[rid]["arrival"]
+                    sched.release(rid)
+                    continue
+                u_fn, f_fn = inputs.manufactured(req["d"])
+                cq, bp = op.rhs_points()
+                b = torch.empty(op.n_dofs, dtype=torch.float64, device="cuda")
+                op.rhs(f_fn(cq.reshape(-1, req["d"])), u_fn(bp.reshape(-1, req["d"])), b)
+                ops.append(op)
+                bs.append(b)
+                xs.append(torch.zeros_like(b))
+                kept.append((rid, req))
+            err = None
+            try:
+                infos = sbm.solve_batch(ops, bs, xs, rel_tol=server.rel_tol, max_it=server.max_it,
+                                        mode=server.mode, restart=server.restart) if ops else []
+            except Exception as exc:  # reported for every request of the set; the server goes on
+                infos, err = [{} for _ in ops], repr(exc)
+            end = time.perf_counter() - t0
+            for (rid, req), op, x, info in zip(kept, ops, xs, infos):
+                info = dict(info, n_dofs=op.n_dofs, disc=req["disc"], p=req["p"], device_bytes=op.device_bytes)
+                results[rid] = dict(id=rid, arrival=req["arrival"] * time_scale, start=starts, end=end, error=err,
+                                    latency=end - req["arrival"] * time_scale, info=info,
+                                    x=x.cpu().numpy() if keep_solutions and err is None else None)
+        finally:
+            for op in ops:
+                op.close()
+            for rid, _ in kept:
+                sched.release(rid)
+    wall = time.perf_counter() - t0
+    lat = [r["latency"] for r in results.values() if r["error"] is None]
+    ok = [r for r in results.values() if r["error"] is None and r["info"].get("status") == 0]
+    first_arrival = min((r["arrival"] for r in results.values()), default=0.0)
+    last_end = max((r["end"] for r in results.values()), default=0.0)
+    span = max(1e-9, last_end - first_arrival)
+    return {
+        "requests": len(requests), "served": len(results), "rejected": list(sched.rejected),
+        "converged": len(ok), "errors": sum(1 for r in results.values() if r["error"]),
+        "solves_per_s": len(results) / span, "converged_solves_per_s": len(ok) / span,
+        "latency_p50_s": percentile(lat, 50), "latency_p99_s": percentile(lat, 99),
+        "converged_latency_p50_s": percentile([r["latency"] for r in ok], 50),
+        "converged_latency_p99_s": percentile([r["latency"] for r in ok], 99),
+        "wall_s": wall, "results": results,
+    }
+
+
 class _null:
     def __enter__(self):
         return self

@@ -136,3 +136,58 @@ def test_batch_rejects_overlapping_arguments():
     finally:
         for o in ops:
             o.close()
+
+
+SOLVE_MIX = [
+    dict(d=2, n=16, ls=inputs.sphere((0.05, -0.03), 0.7), p=2, disc="cg"),
+    dict(d=2, n=13, ls=inputs.ellipsoid((0.02, 0.01), (0.8, 0.45)), p=1, disc="cg"),
+    dict(d=2, n=9, ls=inputs.sphere((0.05, -0.03), 0.7), p=3, disc="dg"),
+    dict(d=3, n=8, ls=inputs.sphere((0, 0, 0), 0.75), p=1, disc="cg"),
+    dict(d=3, n=8, ls=inputs.sphere((0, 0, 0), 0.75), p=4, disc="cg"),
+    dict(d=3, n=6, ls=inputs.sphere((0, 0, 0), 0.75), p=2, disc="dg"),
+    dict(d=3, n=8, ls=inputs.torus(0.55, 0.4), p=2, disc="cg", taylor=1),
+]
+INFO_KEYS = ("status", "outer_its", "inner_its", "applies_f64", "applies_f32", "rel_residual")
+
+
+@pytest.mark.parametrize("mode", ["gmres", "gmres_ir"])
+def test_solve_batch_is_bitwise_single_solves(mode):
+    """Lockstep batched GMRES (FP64, and FP32 inside FP64 refinement) over operators of
+    different kinds: every solution and every solve report equals the operator's own sbm_solve,
+    bit for bit, whether the system converges within the iteration bound or not."""
+    print(f"solve batch {mode}", flush=True)
+    ops = _ops(SOLVE_MIX)
+    try:
+        bs = [torch.from_numpy(inputs.uniform_vector(o.n_dofs, seed=500 + i)).to("cuda") for i, o in enumerate(ops)]
+        x0 = [torch.from_numpy(inputs.uniform_vector(o.n_dofs, seed=600 + i, lo=-0.1, hi=0.1)).to("cuda")
+              for i, o in enumerate(ops)]
+        xs_single = [x.clone() for x in x0]
+        ref = [o.solve(b, x, rel_tol=1e-10, max_it=150, mode=mode, restart=20) for o, b, x in zip(ops, bs, xs_single)]
+        xs = [x.clone() for x in x0]
+        infos = sbm.solve_batch(ops, bs, xs, rel_tol=1e-10, max_it=150, mode=mode, restart=20)
+        torch.cuda.synchronize()
+        assert any(r["status"] == sbm.SBM_OK for r in ref)  # the mix has converging systems
+        for c, r, inf, x, xr in zip(SOLVE_MIX, ref, infos, xs, xs_single):
+            for k in INFO_KEYS:
+                assert inf[k] == r[k], (c, k, inf[k], r[k])
+            assert torch.equal(x, xr), c
+    finally:
+        for o in ops:
+            o.close()
+
+
+def test_solve_batch_arguments():
+    ops = _ops(SOLVE_MIX[:2])
+    try:
+        bs = [torch.from_numpy(inputs.uniform_vector(o.n_dofs, seed=i)).to("cuda") for i, o in enumerate(ops)]
+        xs = [torch.zeros_like(b) for b in bs]
+        with pytest.raises(sbm.SbmError):
+            sbm.solve_batch([ops[0], ops[0]], [bs[0], bs[0].clone()], [xs[0], xs[0].clone()])
+        with pytest.raises(sbm.SbmError):
+            sbm.solve_batch(ops, bs, xs, mode="cg")
+        with pytest.raises(ValueError):
+            sbm.solve_batch(ops, bs[::-1], xs)
+        assert sbm.solve_batch([], [], []) == []
+    finally:
+        for o in ops:
+            o.close()

@@ -101,6 +101,32 @@ def test_each_result_same_alone_and_in_the_mix():
 
 
 @pytest.mark.gpu
+def test_batched_serving_same_alone_and_in_the_mix():
+    """Lockstep batched serving (all admitted requests solved together, each Krylov step's
+    applies in one batch of launches): every request converges and its solution equals the one
+    it gets alone, bit for bit; the admission caps each set at the slot count."""
+    torch = pytest.importorskip("torch")
+    from paper_2507_17053_amd.serving import Server, run_batched
+
+    reqs = [dict(r, id=i, arrival=0.0) for i, r in enumerate(SOLVABLE)]
+    srv = Server(budget_bytes=8 << 30, slots=4, mode="gmres_ir", rel_tol=1e-10, max_it=8000, restart=64)
+    summary = run_batched(srv, reqs, time_scale=0.0, keep_solutions=True)
+    errs = {rid: r["error"] for rid, r in summary["results"].items() if r["error"]}
+    assert summary["served"] == len(reqs) and summary["errors"] == 0, errs
+    assert summary["converged"] == len(reqs)
+    starts = sorted({r["start"] for r in summary["results"].values()})
+    assert len(starts) == 2  # 6 requests, 4 slots: two sets
+    alone = Server(budget_bytes=8 << 30, slots=1, mode="gmres_ir", rel_tol=1e-10, max_it=8000, restart=64)
+    for r in reqs:
+        x_alone, info = alone.solve_one(r)
+        got = summary["results"][r["id"]]
+        for k in ("status", "outer_its", "inner_its", "applies_f64", "applies_f32", "rel_residual"):
+            assert got["info"][k] == info[k], (r["id"], k)
+        assert np.array_equal(got["x"], x_alone), r["id"]
+    torch.cuda.synchronize()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("mode,jacobi", [("gmres", False), ("gmres_ir", True)])
 def test_admission_estimate_bounds_what_a_solve_holds(mode, jacobi):
     """The server's admission estimate is at least the device bytes the request's handle holds
