@@ -406,7 +406,8 @@ def serve_section(n_req, max_it, rate, slots, budget_gb, deadline_s):
                 "converged_latency_p99_s": s["converged_latency_p99_s"],
                 "median_rel_residual": rr[len(rr) // 2] if rr else None,
                 "converged_by_kind": {k: sum(1 for r in conv if f"{r['info'].get('disc', '')}" == k) for k in ("cg", "dg")},
-                "total_dofs": int(sum(r["info"].get("n_dofs", 0) for r in res)), "wall_s": s["wall_s"]}
+                "total_dofs": int(sum(r["info"].get("n_dofs", 0) for r in res)), "wall_s": s["wall_s"],
+                **{k: s[k] for k in ("sets", "setup_and_rhs_s", "lockstep_solve_s") if k in s}}
 
     closed = one(inputs.serving_requests(n_req, seed=2, rate=1.0), 0.0)
     mu = closed["solves_per_s"]

@@ -276,6 +276,8 @@ def run_batched(server, requests, time_scale=1.0, deadline_s=None, keep_solution
         sched.submit(r["id"], r["arrival"] * time_scale, fp, r)
     t0 = time.perf_counter()
     results = {}
+    t_setup = t_solve = 0.0
+    sets = 0
     while not sched.idle():
         now = time.perf_counter() - t0
         if deadline_s is not None and now > deadline_s:
@@ -308,6 +310,9 @@ def run_batched(server, requests, time_scale=1.0, deadline_s=None, keep_solution
                 bs.append(b)
                 xs.append(torch.zeros_like(b))
                 kept.append((rid, req))
+            t_solve0 = time.perf_counter()
+            t_setup += t_solve0 - t0 - starts
+            sets += 1
             err = None
             try:
                 infos = sbm.solve_batch(ops, bs, xs, rel_tol=server.rel_tol, max_it=server.max_it,
@@ -315,6 +320,7 @@ def run_batched(server, requests, time_scale=1.0, deadline_s=None, keep_solution
             except Exception as exc:  # reported for every request of the set; the server goes on
                 infos, err = [{} for _ in ops], repr(exc)
             end = time.perf_counter() - t0
+            t_solve += time.perf_counter() - t_solve0
             for (rid, req), op, x, info in zip(kept, ops, xs, infos):
                 info = dict(info, n_dofs=op.n_dofs, disc=req["disc"], p=req["p"], device_bytes=op.device_bytes)
                 results[rid] = dict(id=rid, arrival=req["arrival"] * time_scale, start=starts, end=end, error=err,
@@ -338,7 +344,8 @@ def run_batched(server, requests, time_scale=1.0, deadline_s=None, keep_solution
         "latency_p50_s": percentile(lat, 50), "latency_p99_s": percentile(lat, 99),
         "converged_latency_p50_s": percentile([r["latency"] for r in ok], 50),
         "converged_latency_p99_s": percentile([r["latency"] for r in ok], 99),
-        "wall_s": wall, "results": results,
+        "wall_s": wall, "sets": sets, "setup_and_rhs_s": t_setup, "lockstep_solve_s": t_solve,
+        "results": results,
     }
 
 
