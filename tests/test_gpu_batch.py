@@ -191,3 +191,37 @@ def test_solve_batch_arguments():
     finally:
         for o in ops:
             o.close()
+
+
+def test_batch_with_an_empty_operator_and_single_item():
+    """An operator without unknowns (no cell inside the domain) is allowed in a batch and
+    skipped; a batch of one operator is its own apply; a lockstep solve with an empty system
+    reports success for it and solves the others as alone."""
+    cases = [dict(d=3, n=8, ls=inputs.sphere((0, 0, 0), 0.05), p=3, disc="cg"), SOLVE_MIX[0], SOLVE_MIX[5]]
+    ops = _ops(cases)
+    try:
+        assert ops[0].n_dofs == 0
+        us = [torch.from_numpy(inputs.uniform_vector(max(o.n_dofs, 1), seed=900 + i)).to("cuda")[:o.n_dofs]
+              for i, o in enumerate(ops)]
+        vs = [torch.full_like(u, 3.0) for u in us]
+        refs = _singles(ops[1:], us[1:])
+        sbm.apply_batch(ops, us, vs)
+        v1 = torch.full_like(us[2], 3.0)
+        with sbm.Batch(ops[2:], us[2:], [v1], graph=True) as b1:
+            b1.run(torch.cuda.Stream())
+            torch.cuda.synchronize()
+        for v, r in zip(vs[1:], refs):
+            assert torch.equal(v, r)
+        assert torch.equal(v1, refs[1])
+        bs = [u.clone() for u in us]
+        xs = [torch.zeros_like(u) for u in us]
+        x_single = torch.zeros_like(us[1])
+        ref = ops[1].solve(bs[1], x_single, rel_tol=1e-10, max_it=60, mode="gmres", restart=20)
+        infos = sbm.solve_batch(ops, bs, xs, rel_tol=1e-10, max_it=60, mode="gmres", restart=20)
+        assert infos[0]["status"] == sbm.SBM_OK and infos[0]["inner_its"] == 0
+        for k in INFO_KEYS:
+            assert infos[1][k] == ref[k], k
+        assert torch.equal(xs[1], x_single)
+    finally:
+        for o in ops:
+            o.close()
