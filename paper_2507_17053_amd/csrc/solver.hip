@@ -1343,9 +1343,15 @@ struct OrthoPlan {
   int total[kOrthoKinds] = {};
   std::vector<GItem<T> *> set;
   std::vector<int> ncol_h;  // host copy of the column counts being uploaded (kept until the next sync)
-  ~OrthoPlan() { dev_free(d); }
+  hipStream_t stream = nullptr;  // where the tables are read (waited for before they are released)
+  ~OrthoPlan() {
+    if (!d) return;
+    (void)hipStreamSynchronize(stream);
+    dev_free(d);
+  }
 
   sbm_status prepare(const std::vector<GItem<T> *> &sub, int m, hipStream_t s) {
+    stream = s;
     std::vector<const void *> k(sub.begin(), sub.end());
     if (d && k == key) return SBM_OK;
     if (d) {
