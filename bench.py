@@ -388,11 +388,12 @@ def serve_section(n_req, max_it, rate, slots, budget_gb, deadline_s):
     from paper_2507_17053_amd import inputs
     from paper_2507_17053_amd.serving import Server, run_batched
 
-    def one(reqs, time_scale, cap=max_it, batched_slots=0):
-        srv = Server(budget_bytes=int(budget_gb * (1 << 30)), slots=batched_slots or slots, mode="gmres_ir",
-                     rel_tol=1e-10, max_it=cap, restart=32)
+    def one(reqs, time_scale, cap=max_it, batched_slots=0, prefetch=False):
+        srv = Server(budget_bytes=int(budget_gb * (1 << 30)), slots=(2 if prefetch else 1) * batched_slots or slots,
+                     mode="gmres_ir", rel_tol=1e-10, max_it=cap, restart=32)
         if batched_slots:
-            s = run_batched(srv, reqs, time_scale=time_scale, deadline_s=deadline_s)
+            s = run_batched(srv, reqs, time_scale=time_scale, deadline_s=deadline_s, set_size=batched_slots,
+                            prefetch=prefetch)
         else:
             s = srv.run(reqs, time_scale=time_scale, deadline_s=deadline_s)
         res = list(s["results"].values())
@@ -416,10 +417,13 @@ def serve_section(n_req, max_it, rate, slots, budget_gb, deadline_s):
     # the same requests with the first-order extension E_1, closed loop, 10x iteration cap
     first = one([dict(r, taylor_order=1) for r in inputs.serving_requests(n_req, seed=2, rate=1.0)], 0.0,
                 cap=10 * max_it)
-    # lockstep batches of up to 32 admitted requests (sbm_solve_batch), closed loop
+    # lockstep sets of up to 32 admitted requests (sbm_solve_batch), closed loop; then with the
+    # next set prepared on a host thread while the current one solves
     batched = one(inputs.serving_requests(n_req, seed=2, rate=1.0), 0.0, batched_slots=32)
+    piped = one(inputs.serving_requests(n_req, seed=2, rate=1.0), 0.0, batched_slots=32, prefetch=True)
     return {"closed_loop": closed, "open_loop": dict(opened, arrival_rate_per_s=lam),
-            "closed_loop_lockstep_batches": dict(batched, batch_slots=32), "slots": slots,
+            "closed_loop_lockstep_batches": dict(batched, batch_slots=32),
+            "closed_loop_lockstep_batches_prefetch": dict(piped, batch_slots=32), "slots": slots,
             "hbm_budget_GB": budget_gb, "krylov_cap": max_it, "admission_deadline_s": deadline_s,
             "closed_loop_first_order_extension": dict(first, krylov_cap=10 * max_it)}
 

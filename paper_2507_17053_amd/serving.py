@@ -52,10 +52,12 @@ class Scheduler:
         heapq.heappush(self.pending, _Pending(float(arrival), int(rid), int(footprint), payload))
         return True
 
-    def admit(self, now):
-        """Pop every request that has arrived by `now` and fits; returns [(rid, payload)]."""
+    def admit(self, now, limit=None):
+        """Pop every request that has arrived by `now` and fits (at most `limit` of them);
+        returns [(rid, payload)]."""
         out = []
-        while self.pending and self.pending[0].arrival <= now and len(self.active) < self.slots:
+        while (self.pending and self.pending[0].arrival <= now and len(self.active) < self.slots
+               and (limit is None or len(out) < limit)):
             head = self.pending[0]
             if self.used + head.footprint > self.budget:
                 break
@@ -259,17 +261,48 @@ class Server:
         }
 
 
-def run_batched(server, requests, time_scale=1.0, deadline_s=None, keep_solutions=False):
-    """Serve `requests` in lockstep batches: the scheduler admits every arrived request that
-    fits (slots, HBM budget), their operators and right-hand sides are set up, and the whole
-    set is solved together by sbm_solve_batch (each Krylov step's applies of all of them in one
-    batch of launches); then the next set is admitted.  Requests that arrive while a set is
-    solving wait for it to finish.  Same summary as Server.run."""
+def _prepare_set(server, batch):
+    """Operators, right-hand sides and zero initial guesses of an admitted set; returns the
+    prepared items [(rid, req, op, b, x)] and the setup failures [(rid, req, error)]."""
     import torch
 
     from . import inputs, sbm
+    items, failed = [], []
+    for rid, req in batch:
+        try:
+            op = sbm.Operator(req["d"], req["n"], req["lo"], req["hi"], req["levelset"], req["p"], disc=req["disc"],
+                              taylor_order=req.get("taylor_order", server.taylor_order), solver_graphs=False)
+        except Exception as exc:  # a failed setup is reported; the others go on
+            failed.append((rid, req, repr(exc)))
+            continue
+        try:
+            u_fn, f_fn = inputs.manufactured(req["d"])
+            cq, bp = op.rhs_points()
+            b = torch.empty(op.n_dofs, dtype=torch.float64, device="cuda")
+            op.rhs(f_fn(cq.reshape(-1, req["d"])), u_fn(bp.reshape(-1, req["d"])), b)  # synchronous
+        except Exception as exc:
+            op.close()
+            failed.append((rid, req, repr(exc)))
+            continue
+        items.append((rid, req, op, b, torch.zeros_like(b)))
+    return items, failed
+
+
+def run_batched(server, requests, time_scale=1.0, deadline_s=None, keep_solutions=False, set_size=None,
+                prefetch=False):
+    """Serve `requests` in lockstep sets: the scheduler admits up to set_size arrived requests
+    that fit (the server's slots and HBM budget), their operators and right-hand sides are set
+    up, and the whole set is solved together by sbm_solve_batch (each Krylov step's applies of
+    all of them in one batch of launches).  prefetch: while a set is solving, one host thread
+    admits and sets up the next one (both sets then hold slots and HBM: give the server twice
+    set_size slots), so the host's setup overlaps the device's solves.  Requests that arrive
+    while a set is solving wait for a later set.  Same summary as Server.run, plus the time
+    spent preparing sets and solving them."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from . import sbm
     sched = server.sched
-    reqs = {r["id"]: r for r in requests}
+    set_size = set_size or sched.slots
     for r in requests:
         fp, nd = server._estimate(r)
         r["_footprint"], r["_n_dofs"] = fp, nd
@@ -278,59 +311,75 @@ def run_batched(server, requests, time_scale=1.0, deadline_s=None, keep_solution
     results = {}
     t_setup = t_solve = 0.0
     sets = 0
-    while not sched.idle():
-        now = time.perf_counter() - t0
-        if deadline_s is not None and now > deadline_s:
-            sched.pending.clear()
-            break
-        batch = sched.admit(now)
-        if not batch:
+    pool = ThreadPoolExecutor(max_workers=1) if prefetch else None
+
+    def prepare(batch):
+        t = time.perf_counter()
+        items, failed = _prepare_set(server, batch)
+        return items, failed, t - t0, time.perf_counter() - t
+
+    def record_failures(failed, starts):
+        for rid, req, err in failed:
+            end = time.perf_counter() - t0
+            results[rid] = dict(id=rid, arrival=req["arrival"] * time_scale, start=starts, end=end, error=err,
+                                latency=end - req["arrival"] * time_scale, info={}, x=None)
+            sched.release(rid)
+
+    def admit_next(block):
+        """Admit the next set (waiting for arrivals if block); None when nothing is left."""
+        while not sched.idle():
+            now = time.perf_counter() - t0
+            if deadline_s is not None and now > deadline_s:
+                sched.pending.clear()
+                return None
+            batch = sched.admit(now, limit=set_size)
+            if batch or not block:
+                return batch or None
             nxt = sched.pending[0].arrival - now if sched.pending else 0.0
             time.sleep(min(0.05, max(1e-3, nxt)))
-            continue
-        starts = time.perf_counter() - t0
-        ops, bs, xs, kept = [], [], [], []
-        try:
-            for rid, req in batch:
-                try:
-                    op = sbm.Operator(req["d"], req["n"], req["lo"], req["hi"], req["levelset"], req["p"],
-                                      disc=req["disc"], taylor_order=req.get("taylor_order", server.taylor_order),
-                                      solver_graphs=False)
-                except Exception as exc:  # a failed setup is reported; the others go on
-                    results[rid] = dict(id=rid, arrival=req["arrival"] * time_scale, start=starts,
-                                        end=time.perf_counter() - t0, error=repr(exc), info={}, x=None)
-                    results[rid]["latency"] = results[rid]["end"] - results[rid]["arrival"]
-                    sched.release(rid)
-                    continue
-                u_fn, f_fn = inputs.manufactured(req["d"])
-                cq, bp = op.rhs_points()
-                b = torch.empty(op.n_dofs, dtype=torch.float64, device="cuda")
-                op.rhs(f_fn(cq.reshape(-1, req["d"])), u_fn(bp.reshape(-1, req["d"])), b)
-                ops.append(op)
-                bs.append(b)
-                xs.append(torch.zeros_like(b))
-                kept.append((rid, req))
-            t_solve0 = time.perf_counter()
-            t_setup += t_solve0 - t0 - starts
+        return None
+
+    try:
+        current = None
+        while True:
+            if current is None:
+                batch = admit_next(block=True)
+                if batch is None:
+                    break
+                current = prepare(batch)
+            items, failed, starts, prep_s = current
+            t_setup += prep_s
+            record_failures(failed, starts)
+            fut = None
+            if pool is not None:
+                nxt = admit_next(block=False)
+                if nxt:
+                    fut = pool.submit(prepare, nxt)
             sets += 1
+            t_solve0 = time.perf_counter()
             err = None
             try:
-                infos = sbm.solve_batch(ops, bs, xs, rel_tol=server.rel_tol, max_it=server.max_it,
-                                        mode=server.mode, restart=server.restart) if ops else []
+                infos = sbm.solve_batch([it[2] for it in items], [it[3] for it in items], [it[4] for it in items],
+                                        rel_tol=server.rel_tol, max_it=server.max_it, mode=server.mode,
+                                        restart=server.restart) if items else []
             except Exception as exc:  # reported for every request of the set; the server goes on
-                infos, err = [{} for _ in ops], repr(exc)
+                infos, err = [{} for _ in items], repr(exc)
             end = time.perf_counter() - t0
             t_solve += time.perf_counter() - t_solve0
-            for (rid, req), op, x, info in zip(kept, ops, xs, infos):
-                info = dict(info, n_dofs=op.n_dofs, disc=req["disc"], p=req["p"], device_bytes=op.device_bytes)
-                results[rid] = dict(id=rid, arrival=req["arrival"] * time_scale, start=starts, end=end, error=err,
-                                    latency=end - req["arrival"] * time_scale, info=info,
-                                    x=x.cpu().numpy() if keep_solutions and err is None else None)
-        finally:
-            for op in ops:
-                op.close()
-            for rid, _ in kept:
-                sched.release(rid)
+            try:
+                for (rid, req, op, b, x), info in zip(items, infos):
+                    info = dict(info, n_dofs=op.n_dofs, disc=req["disc"], p=req["p"], device_bytes=op.device_bytes)
+                    results[rid] = dict(id=rid, arrival=req["arrival"] * time_scale, start=starts, end=end,
+                                        error=err, latency=end - req["arrival"] * time_scale, info=info,
+                                        x=x.cpu().numpy() if keep_solutions and err is None else None)
+            finally:
+                for rid, req, op, b, x in items:
+                    op.close()
+                    sched.release(rid)
+            current = fut.result() if fut is not None else None
+    finally:
+        if pool is not None:
+            pool.shutdown(wait=True)
     wall = time.perf_counter() - t0
     lat = [r["latency"] for r in results.values() if r["error"] is None]
     ok = [r for r in results.values() if r["error"] is None and r["info"].get("status") == 0]

@@ -101,16 +101,18 @@ def test_each_result_same_alone_and_in_the_mix():
 
 
 @pytest.mark.gpu
-def test_batched_serving_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("prefetch", [False, True], ids=["sequential", "prefetch"])
+def test_batched_serving_same_alone_and_in_the_mix(prefetch):
     """Lockstep batched serving (all admitted requests solved together, each Krylov step's
-    applies in one batch of launches): every request converges and its solution equals the one
-    it gets alone, bit for bit; the admission caps each set at the slot count."""
+    applies in one batch of launches), with the next set prepared on a host thread during the
+    solve or not: every request converges and its solution equals the one it gets alone, bit
+    for bit; each set holds at most set_size requests."""
     torch = pytest.importorskip("torch")
     from paper_2507_17053_amd.serving import Server, run_batched
 
     reqs = [dict(r, id=i, arrival=0.0) for i, r in enumerate(SOLVABLE)]
-    srv = Server(budget_bytes=8 << 30, slots=4, mode="gmres_ir", rel_tol=1e-10, max_it=8000, restart=64)
-    summary = run_batched(srv, reqs, time_scale=0.0, keep_solutions=True)
+    srv = Server(budget_bytes=8 << 30, slots=8, mode="gmres_ir", rel_tol=1e-10, max_it=8000, restart=64)
+    summary = run_batched(srv, reqs, time_scale=0.0, keep_solutions=True, set_size=4, prefetch=prefetch)
     errs = {rid: r["error"] for rid, r in summary["results"].items() if r["error"]}
     assert summary["served"] == len(reqs) and summary["errors"] == 0, errs
     assert summary["converged"] == len(reqs)
