@@ -1115,15 +1115,28 @@ sbm_status sbm_rhs_points(sbm_handle h, double *cell_qp, double *bdry_pts) {
   const int d = h->dim, n1 = h->n1;
   if (cell_qp) {
     const int nq = h->nb;
-    for (int64_t r = 0; r < h->n_cells; ++r) {
-      const int32_t *cc = &h->cells[r * d];
-      for (int q = 0; q < nq; ++q) {
-        int qq = q;
-        for (int m = 0; m < d; ++m) {
-          cell_qp[(r * nq + q) * d + m] = h->lo[m] + h->h * (cc[m] + h->rules.g[qq % n1]);
-          qq /= n1;
+    auto fill = [&](int64_t r0, int64_t r1) {
+      for (int64_t r = r0; r < r1; ++r) {
+        const int32_t *cc = &h->cells[r * d];
+        for (int q = 0; q < nq; ++q) {
+          int qq = q;
+          for (int m = 0; m < d; ++m) {
+            cell_qp[(r * nq + q) * d + m] = h->lo[m] + h->h * (cc[m] + h->rules.g[qq % n1]);
+            qq /= n1;
+          }
         }
       }
+    };
+    // every point on its own (host threads over cell ranges for large meshes)
+    const int64_t nt = std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 16, h->n_cells / 2048}));
+    if (nt <= 1) {
+      fill(0, h->n_cells);
+    } else {
+      std::vector<std::thread> pool;
+      for (int64_t t = 0; t < nt; ++t)
+        pool.emplace_back([&, t] { fill(h->n_cells * t / nt, h->n_cells * (t + 1) / nt); });
+      for (auto &th : pool) th.join();
     }
   }
   if (bdry_pts) std::memcpy(bdry_pts, h->face_xtrue.data(), h->face_xtrue.size() * sizeof(double));

@@ -12,10 +12,12 @@
 // deterministic given a deterministic apply.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <thread>
 #include <type_traits>
 #include <vector>
@@ -1899,16 +1901,17 @@ sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double 
   const Rules1D &R = h->rules;
   const int64_t nc = h->n_cells, nf = h->n_sbm;
   // Every integral is a tensor-product quadrature, so the transposed interpolation to the
-  // basis is done axis by axis (N^T along each axis in turn).  Cells and faces are split over
-  // host threads; each entity's local vector has its own slot, and the slots are added into b
-  // in entity order afterwards (the result does not depend on the split).
+  // basis is done axis by axis (N^T along each axis in turn):
   //   cell r:  loc_i = sum_q psi_i(g_q) W_q h^d f(x_q)
   //   face:    loc_i = c(i_a) T(i_t), T = sum_q psi_t(g_q) omega_q g(x_q) (tangential axes),
   //            c(i_a) = sigma [i_a = s p] - sgn / h l'_{i_a}(s)   (sigma g v - g dv/dn~)
-  std::vector<double> cl((size_t)nc * nb), fl((size_t)nf * nb);
-  // out = contraction of in (tensor with n1 points per axis, `dims` axes, first fastest)
-  // with N^T along `axis`: out[.., i, ..] = sum_q N[q][i] in[.., q, ..]
+  // Each DoF sums its contributions in entity order: all cells in rank order, then all faces
+  // in face order.  The work is split over host threads without changing that order: DG
+  // cells own disjoint blocks (each face adds to its cell's block, the faces of a cell in face
+  // order); CG cells are split into chunks that accumulate into private DoF ranges, which are
+  // then added in chunk order (a chunk's zero entries add exactly nothing).
   auto contract = [&](const double *in, double *out, int dims, int axis) {
+    // out = contraction of in (n1 points per axis, `dims` axes, first fastest) with N^T along axis
     int st = 1;
     for (int m = 0; m < axis; ++m) st *= n1;
     int tot = 1;
@@ -1920,51 +1923,48 @@ sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double 
       out[idx] = acc;
     }
   };
-  auto cells = [&](int64_t r0, int64_t r1) {
-    std::vector<double> A(nb), B(nb);
-    for (int64_t r = r0; r < r1; ++r) {
-      for (int q = 0; q < nb; ++q) {
-        const int qk[3] = {q % n1, (q / n1) % n1, q / (n1 * n1)};
-        double w = 1.0;
-        for (int m = 0; m < d; ++m) w *= R.w[qk[m]] * h->h;
-        A[q] = f_qp[r * nb + q] * w;
-      }
-      double *src = A.data(), *dst = B.data();
-      for (int m = 0; m < d; ++m) {
-        contract(src, dst, d, m);
-        std::swap(src, dst);
-      }
-      std::copy(src, src + nb, cl.begin() + r * nb);
+  // cell r's local vector into out (A, B: scratch of nb)
+  auto cell_local = [&](int64_t r, double *A, double *B, double *out) {
+    for (int q = 0; q < nb; ++q) {
+      const int qk[3] = {q % n1, (q / n1) % n1, q / (n1 * n1)};
+      double w = 1.0;
+      for (int m = 0; m < d; ++m) w *= R.w[qk[m]] * h->h;
+      A[q] = f_qp[r * nb + q] * w;
     }
+    double *src = A, *dst = B;
+    for (int m = 0; m < d; ++m) {
+      contract(src, dst, d, m);
+      std::swap(src, dst);
+    }
+    std::copy(src, src + nb, out);
   };
-  auto faces = [&](int64_t f0, int64_t f1) {
-    std::vector<double> A(np), B(np), cn(n1);
-    for (int64_t f = f0; f < f1; ++f) {
-      const int32_t a = h->faces[3 * f + 1], s = h->faces[3 * f + 2];
-      const double sgn = s ? 1.0 : -1.0;
-      const double *Ds = s ? R.D1.data() : R.D0.data();
-      for (int q = 0; q < np; ++q) {
-        const int qt[2] = {q % n1, q / n1};
-        double om = 1.0;
-        for (int t = 0; t < d - 1; ++t) om *= R.w[qt[t]] * h->h;
-        A[q] = om * g_bp[f * np + q];
-      }
-      double *src = A.data(), *dst = B.data();
-      for (int m = 0; m < d - 1; ++m) {
-        contract(src, dst, d - 1, m);
-        std::swap(src, dst);
-      }
-      for (int ia = 0; ia < n1; ++ia) cn[ia] = (ia == s * P ? h->sigma_gamma : 0.0) - sgn / h->h * Ds[ia];
-      for (int i = 0; i < nb; ++i) {
-        const int ik[3] = {i % n1, (i / n1) % n1, i / (n1 * n1)};
-        int jt = 0, sc = 1;
-        for (int m = 0; m < d; ++m)
-          if (m != a) {
-            jt += ik[m] * sc;
-            sc *= n1;
-          }
-        fl[(size_t)f * nb + i] = cn[ik[a]] * src[jt];
-      }
+  // face f's local vector into out (A, B: scratch of np)
+  auto face_local = [&](int64_t f, double *A, double *B, double *out) {
+    const int32_t a = h->faces[3 * f + 1], s = h->faces[3 * f + 2];
+    const double sgn = s ? 1.0 : -1.0;
+    const double *Ds = s ? R.D1.data() : R.D0.data();
+    for (int q = 0; q < np; ++q) {
+      const int qt[2] = {q % n1, q / n1};
+      double om = 1.0;
+      for (int t = 0; t < d - 1; ++t) om *= R.w[qt[t]] * h->h;
+      A[q] = om * g_bp[f * np + q];
+    }
+    double *src = A, *dst = B;
+    for (int m = 0; m < d - 1; ++m) {
+      contract(src, dst, d - 1, m);
+      std::swap(src, dst);
+    }
+    double cn[kMaxN1];
+    for (int ia = 0; ia < n1; ++ia) cn[ia] = (ia == s * P ? h->sigma_gamma : 0.0) - sgn / h->h * Ds[ia];
+    for (int i = 0; i < nb; ++i) {
+      const int ik[3] = {i % n1, (i / n1) % n1, i / (n1 * n1)};
+      int jt = 0, sc = 1;
+      for (int m = 0; m < d; ++m)
+        if (m != a) {
+          jt += ik[m] * sc;
+          sc *= n1;
+        }
+      out[i] = cn[ik[a]] * src[jt];
     }
   };
   auto run = [](int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &fn) {
@@ -1978,19 +1978,75 @@ sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double 
     for (int64_t t = 0; t < nt; ++t) pool.emplace_back([&, t] { fn(n * t / nt, n * (t + 1) / nt); });
     for (auto &th : pool) th.join();
   };
-  run(nc, 1024, cells);
-  run(nf, 1024, faces);
   auto dof_of = [&](int64_t r, int i) -> int64_t {
     return (h->disc == SBM_CG) ? (int64_t)h->runs[r * np + i / n1] + i % n1 : r * nb + i;
   };
-  std::vector<double> bh(h->n_dofs, 0.0);
-  for (int64_t r = 0; r < nc; ++r)
-    for (int i = 0; i < nb; ++i) bh[dof_of(r, i)] += cl[(size_t)r * nb + i];
-  for (int64_t f = 0; f < nf; ++f) {
-    const int32_t r = h->faces[3 * f];
-    for (int i = 0; i < nb; ++i) bh[dof_of(r, i)] += fl[(size_t)f * nb + i];
+  std::unique_ptr<double[]> bh(new double[(size_t)std::max<int64_t>(1, h->n_dofs)]);
+  if (h->disc == SBM_DG) {
+    // faces of each cell, in face order (the faces are listed by cell rank, but this does not
+    // rely on it)
+    std::vector<int64_t> fstart(nc + 1, 0), flist(nf);
+    for (int64_t f = 0; f < nf; ++f) ++fstart[h->faces[3 * f] + 1];
+    for (int64_t r = 0; r < nc; ++r) fstart[r + 1] += fstart[r];
+    {
+      std::vector<int64_t> pos(fstart.begin(), fstart.end() - 1);
+      for (int64_t f = 0; f < nf; ++f) flist[pos[h->faces[3 * f]]++] = f;
+    }
+    run(nc, 256, [&](int64_t r0, int64_t r1) {
+      std::vector<double> A(std::max(nb, np)), B(std::max(nb, np)), L(nb);
+      for (int64_t r = r0; r < r1; ++r) {
+        double *blk = bh.get() + r * nb;
+        cell_local(r, A.data(), B.data(), L.data());
+        for (int i = 0; i < nb; ++i) blk[i] = 0.0 + L[i];
+        for (int64_t k = fstart[r]; k < fstart[r + 1]; ++k) {
+          face_local(flist[k], A.data(), B.data(), L.data());
+          for (int i = 0; i < nb; ++i) blk[i] += L[i];
+        }
+      }
+    });
+  } else {
+    // CG: chunks of cells in rank order, each into a private copy of the DoF range it touches
+    const int64_t nt = std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 16, nc / 1024}));
+    std::vector<int64_t> lo(nt), hi(nt);
+    std::vector<std::vector<double>> priv(nt);
+    run(nt, 1, [&](int64_t t0, int64_t t1) {
+      std::vector<double> A(nb), B(nb), L(nb);
+      for (int64_t t = t0; t < t1; ++t) {
+        const int64_t r0 = nc * t / nt, r1 = nc * (t + 1) / nt;
+        int64_t mn = INT64_MAX, mx = -1;
+        for (int64_t r = r0; r < r1; ++r)
+          for (int j = 0; j < np; ++j) {
+            mn = std::min<int64_t>(mn, h->runs[r * np + j]);
+            mx = std::max<int64_t>(mx, (int64_t)h->runs[r * np + j] + n1 - 1);
+          }
+        if (mx < 0) mn = mx = 0;
+        lo[t] = mn;
+        hi[t] = mx;
+        std::vector<double> &pv = priv[t];
+        pv.assign((size_t)(mx - mn + 1), 0.0);
+        for (int64_t r = r0; r < r1; ++r) {
+          cell_local(r, A.data(), B.data(), L.data());
+          for (int i = 0; i < nb; ++i) pv[dof_of(r, i) - mn] += L[i];
+        }
+      }
+    });
+    run(h->n_dofs, 1 << 16, [&](int64_t d0, int64_t d1) {
+      for (int64_t k = d0; k < d1; ++k) {
+        double v = 0.0;
+        for (int64_t t = 0; t < nt; ++t)
+          if (lo[t] <= k && k <= hi[t]) v += priv[t][k - lo[t]];
+        bh[k] = v;
+      }
+    });
+    std::vector<double> A(std::max(nb, np)), B(std::max(nb, np)), L(nb);
+    for (int64_t f = 0; f < nf; ++f) {
+      const int32_t r = h->faces[3 * f];
+      face_local(f, A.data(), B.data(), L.data());
+      for (int i = 0; i < nb; ++i) bh[dof_of(r, i)] += L[i];
+    }
   }
-  SBM_HIP_CHECK(hipMemcpyAsync(b, bh.data(), bh.size() * sizeof(double), hipMemcpyHostToDevice,
+  SBM_HIP_CHECK(hipMemcpyAsync(b, bh.get(), (size_t)h->n_dofs * sizeof(double), hipMemcpyHostToDevice,
                                (hipStream_t)stream));
   SBM_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
   return SBM_OK;
