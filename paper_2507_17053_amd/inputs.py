@@ -100,6 +100,7 @@ def workload(name: str, **over):
     disk2d_q2:        2D CG Q2, 16^2 cells on [-1,1]^2, disk r=0.7 centred (0.05,-0.03)
     sphere3d_q4:      3D CG Q4, 64^3 cells on [-1,1]^3, sphere r=0.75 at the origin
     torus3d_dg:       3D SIPG DG, 32^3 cells, torus R=0.6 r=0.25 (axis z), p=3 or 5
+    torus3d_dg80:     the same DG Q3 torus on 80^3 cells (fills the device)
     spheres3d_q6:     3D CG Q6, 48^3 cells, union of 8 seeded balls
     """
     if name == "disk2d_q2":
@@ -108,6 +109,8 @@ def workload(name: str, **over):
         w = dict(d=3, n=64, lo=-1.0, hi=1.0, p=4, disc="cg", levelset=sphere((0, 0, 0), 0.75))
     elif name == "torus3d_dg":
         w = dict(d=3, n=32, lo=-1.0, hi=1.0, p=3, disc="dg", levelset=torus(0.6, 0.25))
+    elif name == "torus3d_dg80":
+        w = dict(d=3, n=80, lo=-1.0, hi=1.0, p=3, disc="dg", levelset=torus(0.6, 0.25))
     elif name == "spheres3d_q6":
         w = dict(d=3, n=48, lo=-1.0, hi=1.0, p=6, disc="cg", levelset=sphere_union(1))
     else:
