@@ -1383,9 +1383,9 @@ __global__ __launch_bounds__(256) void dg_cell_seq_kernel(int n_cells, const int
 template <typename T, int D, int N1>
 constexpr int dg_cells_per_block(bool one_wave) {
   constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, TPC = 2 * D * NP;
-  // LDS per cell: own tile, cell-term tiles, 2d neighbour tiles, cell result (NB each);
-  // per face 6 NP of scratch and results
-  constexpr int per_cell = ((4 + 2 * D) * NB + 2 * D * 6 * NP) * (int)sizeof(T);
+  // LDS per cell: own tile, 2d neighbour tiles (two of them reused for the cell term), cell
+  // result (NB each); per face 6 NP of scratch and results
+  constexpr int per_cell = ((2 + 2 * D) * NB + 2 * D * 6 * NP) * (int)sizeof(T);
   int e = (one_wave ? 64 : 256) / TPC;
   if (e < 1) e = 1;
   while (e > 1 && e * per_cell > 60000) --e;
@@ -1399,8 +1399,7 @@ __device__ __forceinline__ void dg_cell_body(const int blk, int n_cells, const i
                                                       int parts) {
   constexpr int NP = Shape<D, N1>::NP, NB = Shape<D, N1>::NB, P = N1 - 1, NF = 2 * D, TPC = NF * NP;
   __shared__ T su_all[EPB * NB];           // own tile
-  __shared__ T sab_all[2 * EPB * NB];        // cell-term tiles (A, B) per cell
-  __shared__ T sn_all[EPB * NF * NB];      // neighbour tiles, one per face
+  __shared__ T sn_all[EPB * NF * NB];      // neighbour tiles, one per face (then the cell-term tiles)
   __shared__ T sw_all[EPB * NB];           // cell term
   __shared__ T f_all[EPB * NF * 6 * NP];   // per face: f1..f4 scratch, Rv, Rg
   const int le = threadIdx.x / TPC, r = threadIdx.x - le * TPC;  // cell in block, thread in cell
@@ -1472,12 +1471,13 @@ __device__ __forceinline__ void dg_cell_body(const int blk, int n_cells, const i
     }
   }
   // ---- cell term: the block's first EPB * NP threads, NP per cell (whole wavefronts beyond
-  // them only take part in the barriers) ----
+  // them only take part in the barriers).  Its two sweep tiles are the cell's first two
+  // neighbour tiles: every neighbour value was read before the face phase's first barrier ----
   {
     const int lc = threadIdx.x / NP, tc = threadIdx.x - lc * NP;
     const bool work = lc < EPB;
     const int lw = work ? lc : 0;
-    T *A = sab_all + 2 * lw * NB, *B = A + NB;
+    T *A = sn_all + lw * NF * NB, *B = A + NB;
     T x[N1], out[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) x[k] = work ? su_all[lw * NB + tc + NP * k] : T(0);
