@@ -36,6 +36,25 @@ def test_scheduler_head_of_line_keeps_fcfs():
     assert [r for r, _ in s.admit(1.0)] == [1, 2]
 
 
+def test_scheduler_limit_caps_a_set_and_keeps_order():
+    """admit(limit=k) takes at most k of the arrived requests, in arrival order, the rest stay
+    queued for the next set (the lockstep sets of the serving loop)."""
+    s = Scheduler(budget_bytes=1000, slots=8)
+    for i in range(7):
+        s.submit(i, 0.1 * i, 10)
+    assert [r for r, _ in s.admit(10.0, limit=3)] == [0, 1, 2]
+    assert [r for r, _ in s.admit(10.0, limit=3)] == [3, 4, 5]   # a second set while the first holds slots
+    assert [r for r, _ in s.admit(10.0, limit=3)] == [6]
+    assert s.admit(10.0, limit=3) == []
+    for i in range(7):
+        s.release(i)
+    assert s.idle() and s.used == 0
+    s2 = Scheduler(budget_bytes=1000, slots=2)
+    for i in range(4):
+        s2.submit(i, 0.0, 10)
+    assert [r for r, _ in s2.admit(1.0, limit=3)] == [0, 1]        # slots bind before the limit
+
+
 def test_footprint_counts_workspace():
     from paper_2507_17053_amd.serving import workspace_bytes
     # the FP64 basis alone is (m + 1) row-tiled columns; the mixed mode adds the FP32 copies
