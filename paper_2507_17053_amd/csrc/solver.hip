@@ -1528,7 +1528,7 @@ static sbm_status gmres_batch(std::vector<GItem<T>> &items, int prec, int m, hip
     it.its = 0;
     it.done = false;
   }
-  for (int cycle = 0;; ++cycle) {
+  for (;;) {  // restart cycles
     std::vector<GItem<T> *> act;
     for (auto &it : items)
       if (!it.done) act.push_back(&it);
