@@ -225,3 +225,26 @@ def test_batch_with_an_empty_operator_and_single_item():
     finally:
         for o in ops:
             o.close()
+
+
+def test_solve_batch_long_restart_falls_back_bitwise():
+    """Restart 80: past 64 columns the lockstep solver orthogonalises system by system (the wide
+    Gram-Schmidt kernels); solutions and reports still equal the single solves bit for bit."""
+    print("solve batch restart 80", flush=True)
+    cases = [SOLVE_MIX[0], SOLVE_MIX[3], SOLVE_MIX[5]]
+    ops = _ops(cases)
+    try:
+        bs = [torch.from_numpy(inputs.uniform_vector(o.n_dofs, seed=800 + i)).to("cuda") for i, o in enumerate(ops)]
+        xs_single = [torch.zeros_like(b) for b in bs]
+        ref = [o.solve(b, x, rel_tol=1e-12, max_it=150, mode="gmres", restart=80) for o, b, x in zip(ops, bs, xs_single)]
+        xs = [torch.zeros_like(b) for b in bs]
+        infos = sbm.solve_batch(ops, bs, xs, rel_tol=1e-12, max_it=150, mode="gmres", restart=80)
+        torch.cuda.synchronize()
+        assert any(r["inner_its"] > 64 for r in ref)  # the wide path was taken
+        for c, r, inf, x, xr in zip(cases, ref, infos, xs, xs_single):
+            for k in INFO_KEYS:
+                assert inf[k] == r[k], (c, k, inf[k], r[k])
+            assert torch.equal(x, xr), c
+    finally:
+        for o in ops:
+            o.close()
