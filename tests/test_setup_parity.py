@@ -166,6 +166,38 @@ def test_library_exports_every_declared_symbol():
     assert set(sbm.EXPORTED) <= declared
 
 
+def test_batch_entry_points_host_logic():
+    """Argument checks of the batch entry points, which fail before any device work: host-only
+    or repeated handles, NULL arrays, a negative count, an unbatched solver mode."""
+    P = ctypes.c_void_p
+    op = sbm.Operator(3, 4, -1.0, 1.0, inputs.sphere((0, 0, 0), 0.8), 2, host_only=True)
+    try:
+        hs = (P * 1)(op.handle)
+        u, v = (P * 1)(P(8)), (P * 1)(P(16))
+        out = P()
+        assert sbm._lib.sbm_batch_create(1, hs, u, v, sbm.SBM_F64, 1, 4, ctypes.byref(out)) == sbm.SBM_EINVAL
+        assert b"host-only" in sbm._lib.sbm_last_error()
+        assert sbm._lib.sbm_batch_create(-1, hs, u, v, sbm.SBM_F64, 1, 4, ctypes.byref(out)) == sbm.SBM_EINVAL
+        assert sbm._lib.sbm_batch_create(1, None, u, v, sbm.SBM_F64, 1, 4, ctypes.byref(out)) == sbm.SBM_EINVAL
+        assert sbm._lib.sbm_batch_create(1, hs, u, v, 7, 1, 4, ctypes.byref(out)) == sbm.SBM_EINVAL
+        assert sbm._lib.sbm_apply_batch(1, hs, u, v, sbm.SBM_F64, None) == sbm.SBM_EINVAL
+        assert sbm._lib.sbm_apply_batch(0, None, None, None, sbm.SBM_F64, None) == sbm.SBM_OK
+        assert sbm._lib.sbm_batch_run(None, None) == sbm.SBM_EINVAL
+        assert sbm._lib.sbm_batch_destroy(None) == sbm.SBM_OK
+        infos = (sbm.SolveInfo * 2)()
+        hs2 = (P * 2)(op.handle, op.handle)
+        b2, x2 = (P * 2)(P(8), P(24)), (P * 2)(P(16), P(32))
+        st = sbm._lib.sbm_solve_batch(1, hs, u, v, 1e-10, 10, sbm.SOLVE_MODES["gmres"], 20, None, infos)
+        assert st == sbm.SBM_EINVAL and infos[0].status == sbm.SBM_EINVAL  # host-only handle
+        st = sbm._lib.sbm_solve_batch(2, hs2, b2, x2, 1e-10, 10, sbm.SOLVE_MODES["gmres"], 20, None, infos)
+        assert st == sbm.SBM_EINVAL  # repeated handle
+        st = sbm._lib.sbm_solve_batch(1, hs, u, v, 1e-10, 10, sbm.SOLVE_MODES["cg"], 20, None, infos)
+        assert st == sbm.SBM_EUNSUPPORTED and infos[0].status == sbm.SBM_EUNSUPPORTED
+        assert sbm._lib.sbm_solve_batch(1, hs, u, v, 0.0, 10, 0, 20, None, infos) == sbm.SBM_EINVAL
+    finally:
+        op.close()
+
+
 def test_extension_order_host_logic():
     """sbm_set_extension_order needs no device: NULL handle -> EINVAL; any order is accepted
     and a negative one restores the full extension; the diagnostic split then refuses."""
