@@ -92,6 +92,24 @@ def manufactured(d: int):
     return manufactured_2d() if d == 2 else manufactured_3d()
 
 
+def manufactured_cell_f(d: int, cells: np.ndarray, lo: float, h: float, p: int) -> np.ndarray:
+    """f of the manufactured solution at the (p+1)^d Gauss points of every cell (cells: n x d
+    integer corners; points lexicographic, first coordinate fastest; shape n x (p+1)^d), by the
+    product structure of u*: per cell and axis the p+1 one-dimensional factors, then their
+    outer product (the same values as f at the points, to rounding; d(p+1) sines per cell
+    instead of d(p+1)^d)."""
+    g = (np.polynomial.legendre.leggauss(p + 1)[0] + 1.0) / 2.0
+    c = np.asarray(cells, dtype=np.float64)
+    x = [lo + h * (c[:, m:m + 1] + g[None, :]) for m in range(d)]  # n x (p+1) per axis
+    if d == 2:
+        a, b = np.sin(np.pi * x[0]), np.cos(np.pi * x[1])
+        f = 2.0 * math.pi ** 2 * (b[:, :, None] * a[:, None, :])
+    else:
+        a, b, e = (np.sin(np.pi * x[m]) for m in range(3))
+        f = 3.0 * math.pi ** 2 * (e[:, :, None, None] * (b[:, None, :, None] * a[:, None, None, :]))
+    return np.ascontiguousarray(f.reshape(len(c), (p + 1) ** d))
+
+
 # ---- named workloads ----
 
 def workload(name: str, **over):

@@ -339,10 +339,12 @@ class Operator:
         _check(_lib.sbm_dof_points(self._h, _hptr(out)), "sbm_dof_points")
         return out
 
-    def rhs_points(self):
-        cq = np.empty((self.n_cells, self.nb, self.d))
+    def rhs_points(self, cells=True):
+        """(cell Gauss points n_cells x (p+1)^d x d, true-boundary points n_faces x (p+1)^(d-1) x d);
+        cells=False skips the cell points (returned as None)."""
+        cq = np.empty((self.n_cells, self.nb, self.d)) if cells else None
         bp = np.empty((self.n_sbm_faces, self.nq_face, self.d))
-        _check(_lib.sbm_rhs_points(self._h, _hptr(cq), _hptr(bp)), "sbm_rhs_points")
+        _check(_lib.sbm_rhs_points(self._h, _hptr(cq) if cells else None, _hptr(bp)), "sbm_rhs_points")
         return cq, bp
 
     def export_cells(self):

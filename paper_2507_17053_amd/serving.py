@@ -133,6 +133,18 @@ def count_inside_cells(req) -> int:
     return int(act.sum())
 
 
+def problem_data(op, req):
+    """The request's problem data for sbm_rhs: f of the manufactured solution at the cells'
+    Gauss points (from the cells' corners by its product structure) and g = u* at the
+    true-boundary points of the surrogate faces."""
+    from . import inputs
+    d = req["d"]
+    u_fn, _ = inputs.manufactured(d)
+    _, bp = op.rhs_points(cells=False)
+    f_qp = inputs.manufactured_cell_f(d, op.export_cells(), req["lo"], (req["hi"] - req["lo"]) / req["n"], req["p"])
+    return f_qp, u_fn(bp.reshape(-1, d))
+
+
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else float("nan")
 
@@ -171,15 +183,14 @@ class Server:
         """Setup, right-hand side and solve of one request on `stream`; returns (x, info)."""
         import torch
 
-        from . import inputs, sbm
+        from . import sbm
         op = sbm.Operator(req["d"], req["n"], req["lo"], req["hi"], req["levelset"], req["p"], disc=req["disc"],
                           taylor_order=req.get("taylor_order", self.taylor_order), solver_graphs=self.solver_graphs)
         try:
-            u_fn, f_fn = inputs.manufactured(req["d"])
-            cq, bp = op.rhs_points()
+            f_qp, g_bp = problem_data(op, req)
             with torch.cuda.stream(stream) if stream is not None else _null():
                 b = torch.empty(op.n_dofs, dtype=torch.float64, device="cuda")
-                op.rhs(f_fn(cq.reshape(-1, req["d"])), u_fn(bp.reshape(-1, req["d"])), b, stream=stream)
+                op.rhs(f_qp, g_bp, b, stream=stream)
                 x = torch.zeros_like(b)
                 info = op.solve(b, x, rel_tol=self.rel_tol, max_it=self.max_it, mode=self.mode,
                                 restart=self.restart, jacobi=self.jacobi, stream=stream)
@@ -266,7 +277,7 @@ def _prepare_set(server, batch):
     prepared items [(rid, req, op, b, x)] and the setup failures [(rid, req, error)]."""
     import torch
 
-    from . import inputs, sbm
+    from . import sbm
     items, failed = [], []
     for rid, req in batch:
         try:
@@ -276,10 +287,9 @@ def _prepare_set(server, batch):
             failed.append((rid, req, repr(exc)))
             continue
         try:
-            u_fn, f_fn = inputs.manufactured(req["d"])
-            cq, bp = op.rhs_points()
+            f_qp, g_bp = problem_data(op, req)
             b = torch.empty(op.n_dofs, dtype=torch.float64, device="cuda")
-            op.rhs(f_fn(cq.reshape(-1, req["d"])), u_fn(bp.reshape(-1, req["d"])), b)  # synchronous
+            op.rhs(f_qp, g_bp, b)  # synchronous
         except Exception as exc:
             op.close()
             failed.append((rid, req, repr(exc)))

@@ -55,6 +55,26 @@ def test_scheduler_limit_caps_a_set_and_keeps_order():
     assert [r for r, _ in s2.admit(1.0, limit=3)] == [0, 1]        # slots bind before the limit
 
 
+def test_problem_data_by_product_structure_equals_pointwise():
+    """The serving loop's f at the cell Gauss points, formed per cell from one-dimensional
+    factors, equals f evaluated point by point at the library's Gauss points, bit for bit."""
+    from paper_2507_17053_amd import sbm
+    from paper_2507_17053_amd.serving import problem_data
+    for d, n, ls, p in [(3, 8, inputs.ellipsoid((0, 0, 0), (0.7, 0.6, 0.5)), 4),
+                        (2, 12, inputs.sphere((0.05, -0.03), 0.7), 3),
+                        (3, 16, inputs.sphere_union(1003), 6)]:
+        op = sbm.Operator(d, n, -1.0, 1.0, ls, p, host_only=True)
+        try:
+            cq, bp = op.rhs_points()
+            u_fn, f_fn = inputs.manufactured(d)
+            f_qp, g_bp = problem_data(op, dict(d=d, n=n, lo=-1.0, hi=1.0, p=p))
+            assert f_qp.shape == (op.n_cells, (p + 1) ** d)
+            assert np.array_equal(f_qp, f_fn(cq.reshape(-1, d)).reshape(op.n_cells, -1))
+            assert np.array_equal(g_bp, u_fn(bp.reshape(-1, d)))
+        finally:
+            op.close()
+
+
 def test_footprint_counts_workspace():
     from paper_2507_17053_amd.serving import workspace_bytes
     # the FP64 basis alone is (m + 1) row-tiled columns; the mixed mode adds the FP32 copies
