@@ -1914,13 +1914,18 @@ sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double 
     // out = contraction of in (n1 points per axis, `dims` axes, first fastest) with N^T along axis
     int st = 1;
     for (int m = 0; m < axis; ++m) st *= n1;
-    int tot = 1;
-    for (int m = 0; m < dims; ++m) tot *= n1;
-    for (int idx = 0; idx < tot; ++idx) {
-      const int i = (idx / st) % n1, base = idx - i * st;
-      double acc = 0.0;
-      for (int q = 0; q < n1; ++q) acc += R.N[q * n1 + i] * in[base + q * st];
-      out[idx] = acc;
+    int outer = 1;
+    for (int m = axis + 1; m < dims; ++m) outer *= n1;
+    const double *N = R.N.data();
+    for (int o = 0; o < outer; ++o) {
+      const double *src = in + (size_t)o * n1 * st;
+      double *dst = out + (size_t)o * n1 * st;
+      for (int i = 0; i < n1; ++i)
+        for (int l = 0; l < st; ++l) {
+          double acc = 0.0;
+          for (int q = 0; q < n1; ++q) acc += N[q * n1 + i] * src[q * st + l];
+          dst[i * st + l] = acc;
+        }
     }
   };
   // cell r's local vector into out (A, B: scratch of nb)
@@ -2007,7 +2012,7 @@ sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double 
   } else {
     // CG: chunks of cells in rank order, each into a private copy of the DoF range it touches
     const int64_t nt = std::max<int64_t>(
-        1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 16, nc / 1024}));
+        1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 16, nc / 64}));
     std::vector<int64_t> lo(nt), hi(nt);
     std::vector<std::vector<double>> priv(nt);
     run(nt, 1, [&](int64_t t0, int64_t t1) {
@@ -2039,10 +2044,15 @@ sbm_status sbm_rhs(sbm_handle h, const double *f_qp, const double *g_bp, double 
         bh[k] = v;
       }
     });
-    std::vector<double> A(std::max(nb, np)), B(std::max(nb, np)), L(nb);
+    // the faces' local vectors in parallel, then added in face order
+    std::vector<double> fl((size_t)nf * nb);
+    run(nf, 64, [&](int64_t f0, int64_t f1) {
+      std::vector<double> A(std::max(nb, np)), B(std::max(nb, np));
+      for (int64_t f = f0; f < f1; ++f) face_local(f, A.data(), B.data(), fl.data() + (size_t)f * nb);
+    });
     for (int64_t f = 0; f < nf; ++f) {
       const int32_t r = h->faces[3 * f];
-      face_local(f, A.data(), B.data(), L.data());
+      const double *L = fl.data() + (size_t)f * nb;
       for (int i = 0; i < nb; ++i) bh[dof_of(r, i)] += L[i];
     }
   }
