@@ -234,11 +234,19 @@ hipError_t enqueue(sbm_batch b, hipStream_t s) {
     return hipSuccess;
   }
   hipError_t e = hipEventRecord(b->fork, s);
-  for (size_t j = 0; e == hipSuccess && j < b->streams.size(); ++j) {
-    e = hipStreamWaitEvent(b->streams[j], b->fork, 0);
+  if (e != hipSuccess) return e;
+  // every stream that took the fork is joined back, also after a failed launch, so that the
+  // run's completion event on s covers all of the batch's work
+  for (size_t j = 0; j < b->streams.size(); ++j) {
+    hipError_t ej = hipStreamWaitEvent(b->streams[j], b->fork, 0);
+    if (ej != hipSuccess) {
+      if (e == hipSuccess) e = ej;
+      continue;
+    }
     for (size_t q = 0; e == hipSuccess && q < b->lanes[j].size(); ++q) e = enqueue_group(b, b->lanes[j][q], b->streams[j]);
-    if (e == hipSuccess) e = hipEventRecord(b->join[j], b->streams[j]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[j], 0);
+    ej = hipEventRecord(b->join[j], b->streams[j]);
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(s, b->join[j], 0);
+    if (ej != hipSuccess && e == hipSuccess) e = ej;
   }
   return e;
 }
@@ -265,12 +273,11 @@ sbm_status run(sbm_batch b, hipStream_t s) {
       b->graph_off = true;  // launches are issued directly from now on
     }
   }
-  if (b->exec) {
-    SBM_HIP_CHECK(hipGraphLaunch(b->exec, s));
-  } else {
-    SBM_HIP_CHECK(enqueue(b, s));
-  }
-  SBM_HIP_CHECK(hipEventRecord(b->done, s));
+  const hipError_t e = b->exec ? hipGraphLaunch(b->exec, s) : enqueue(b, s);
+  // recorded also after a failed launch: destroy then waits for whatever was enqueued
+  const hipError_t er = hipEventRecord(b->done, s);
+  SBM_HIP_CHECK(e);
+  SBM_HIP_CHECK(er);
   return SBM_OK;
 }
 
